@@ -1,0 +1,56 @@
+"""Accuracy gates and throughput conventions.
+
+Throughput follows the paper's convention (Section VI-A): an N-point complex
+transform counts 5 N log2 N floating-point operations; GFLOPS is that count
+times the batch divided by the time.  Algorithmic HBM traffic of one
+out-of-place transform is 16 N bytes (read 8N, write 8N, complex64).
+"""
+import math
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+
+
+def fft_flops(n, batch=1):
+    return 5.0 * n * math.log2(n) * batch
+
+
+def fft_bytes(n, batch=1):
+    return 16.0 * n * batch
+
+
+def gflops(n, batch, seconds):
+    return fft_flops(n, batch) / seconds / 1e9
+
+
+def per_row_errors(y, ref, x):
+    """Return (rel_rms[b], max_abs[b], x_norm[b]) over rows of complex arrays.
+
+    rel_rms_b = ||y_b - X_b||_2 / ||X_b||_2; max_abs_b = max_k |y_b - X_b|;
+    the max-abs gate is taken relative to the input row norm ||x_b||_2."""
+    y = np.asarray(y).reshape(-1, np.asarray(y).shape[-1]).astype(np.complex128)
+    ref = np.asarray(ref).reshape(y.shape).astype(np.complex128)
+    x = np.asarray(x).reshape(-1, np.asarray(x).shape[-1]).astype(np.complex128)
+    d = y - ref
+    num = np.sqrt(np.sum(np.abs(d) ** 2, axis=1))
+    den = np.sqrt(np.sum(np.abs(ref) ** 2, axis=1))
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rel = np.where(den > 0, num / den, np.where(num == 0, 0.0, np.inf))
+    mabs = np.max(np.abs(d), axis=1) if d.shape[1] else np.zeros(d.shape[0])
+    xn = np.sqrt(np.sum(np.abs(x) ** 2, axis=1))
+    return rel, mabs, xn
+
+
+REL_RMS_GATE = 5e-6
+MAX_ABS_GATE = 1e-5  # times the input row norm
+
+
+def gate(y, ref, x, rel_gate=REL_RMS_GATE, abs_gate=MAX_ABS_GATE):
+    """Return (ok, worst_rel_rms, median_rel_rms, worst_abs_ratio)."""
+    rel, mabs, xn = per_row_errors(y, ref, x)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ratio = np.where(xn > 0, mabs / xn, np.where(mabs == 0, 0.0, np.inf))
+    ok = bool(np.all(rel <= rel_gate) and np.all(ratio <= abs_gate))
+    return ok, float(rel.max(initial=0.0)), float(np.median(rel) if rel.size else 0.0), \
+        float(ratio.max(initial=0.0))

@@ -1,0 +1,113 @@
+"""Host-side checks: the throughput convention against the paper's printed
+numbers, and the seeded workload generators."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2603_27569_amd import metrics, workloads
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "paper_tables.json")
+
+
+def _golden():
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def test_flop_convention_matches_table_vi():
+    """Table VI's GFLOPS and us/FFT columns agree under 5 N log2 N."""
+    for row in _golden()["table_vi_n4096_batch256"]["rows"]:
+        g = metrics.gflops(4096, 1, row["us_per_fft"] * 1e-6)
+        assert abs(g - row["gflops"]) / row["gflops"] < 0.005, row
+
+
+def test_bmax_equation():
+    b = _golden()["bmax"]
+    assert b["local_mem_bytes"] // b["bytes_per_elem"] == b["bmax"] == 4096
+
+
+def test_bytes_convention():
+    assert metrics.fft_bytes(4096, 256) == 16 * 1024 * 1024
+    assert metrics.fft_flops(4096, 256) == 62914560
+
+
+def test_gate_logic():
+    x = workloads.plain_normal(64, 4, seed=3).astype(np.complex128)
+    ok, worst, med, ab = metrics.gate(x, x, x)
+    assert ok and worst == 0.0 and ab == 0.0
+    y = x.copy()
+    y[1, 3] += 1e-3
+    ok, worst, _, _ = metrics.gate(y, x, x)
+    assert not ok and worst > 5e-6
+    z = np.zeros((2, 8), complex)
+    assert metrics.gate(z, z, z)[0]
+    z2 = z.copy()
+    z2[0, 0] = 1e-30
+    assert not metrics.gate(z2, z, z)[0]
+
+
+def test_generators_deterministic_and_typed():
+    a = workloads.plain_normal()
+    b = workloads.plain_normal()
+    assert a.dtype == np.complex64 and a.shape == (256, 4096)
+    assert np.array_equal(a, b)
+    assert not np.array_equal(a, workloads.plain_normal(seed=1))
+    u = workloads.plain_uniform()
+    assert u.shape == (64, 256)
+    assert np.all(np.abs(u.real) <= 1) and np.all(np.abs(u.imag) <= 1)
+    assert abs(np.mean(a.real)) < 0.01 and abs(np.std(a.real) - 1) < 0.01
+
+
+def test_delta_and_tone():
+    d = workloads.delta_batch(256, 300)
+    assert np.all(np.sum(d != 0, axis=1) == 1)
+    assert d[299, 299 % 256] == 1
+    t = workloads.tone_batch(256, 8)
+    assert np.allclose(np.abs(t), 1.0, atol=1e-6)
+    k = workloads.tone_bins(256, 8)
+    m = np.arange(256)
+    ref = np.exp(2j * np.pi * k[3] * m / 256)
+    assert np.max(np.abs(t[3] - ref)) < 1e-6
+
+
+@pytest.mark.parametrize("n", [8192, 16384])
+def test_chirp_noise_statistics(n):
+    x, meta = workloads.chirp_noise(n, batch=64)
+    assert x.shape == (64, n) and x.dtype == np.complex64
+    L = meta["chirp_len"]
+    assert L == n // 4
+    offs = meta["offsets"]
+    assert np.all(offs >= 0) and np.all(offs + L <= n)
+    assert np.all((meta["beta"] >= 0.2) & (meta["beta"] <= 0.8))
+    # Off-support power is the noise variance (0.1 at 10 dB over the chirp power 1).
+    off = []
+    on = []
+    for b in range(64):
+        mask = np.zeros(n, bool)
+        mask[offs[b]:offs[b] + L] = True
+        off.append(np.mean(np.abs(x[b, ~mask]) ** 2))
+        on.append(np.mean(np.abs(x[b, mask]) ** 2))
+    assert abs(np.mean(off) - 0.1) < 0.005
+    assert abs(np.mean(on) - 1.1) < 0.02
+    x2, _ = workloads.chirp_noise(n, batch=64)
+    assert np.array_equal(x, x2)
+
+
+def test_spectral_inputs():
+    x, w = workloads.spectral_energy_inputs()
+    assert x.shape == (512, 4096) and w.shape == (4096,) and w.dtype == np.float32
+    assert np.all((w >= 0) & (w < 1))
+
+
+def test_ragged_recipe():
+    sizes, offs, data = workloads.ragged()
+    assert sizes.shape == (2000,) and offs.shape == (2000,)
+    assert set(np.unique(sizes)) <= set(workloads.SIZES)
+    assert len(np.unique(sizes)) == 7
+    assert offs[0] == 0 and np.all(np.diff(offs) == sizes[:-1])
+    assert data.shape == (int(sizes.sum()),) and data.dtype == np.complex64
+    # log-uniform exponents: each class near 2000/7
+    counts = np.array([np.sum(sizes == s) for s in workloads.SIZES])
+    assert np.all(np.abs(counts - 2000 / 7) < 60)
