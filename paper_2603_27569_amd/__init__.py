@@ -1,1 +1,391 @@
-"""stockfft for MI355X: batched complex-to-complex FP32 FFTs on gfx950."""
+"""stockfft for MI355X: batched complex-to-complex FP32 FFTs on gfx950.
+
+The transform is the unscaled DFT of arXiv 2603.27569, Section II-A,
+computed by Stockham autosort passes (Section II-B) in hand-written HIP
+kernels (libstockfft.so, C ABI in include/stockfft.h).  This module is the
+thin Python layer above that ABI:
+
+* the C entry points under their C names (fft_plan, fft_exec, fft_destroy,
+  fft_exec_spectral_energy, ...), taking plain integers for device pointers
+  and streams;
+* torch helpers that pass tensor pointers and the current stream:
+  ``fft``, ``ifft_unnormalized``, ``spectral_energy``, ``matched_filter``,
+  ``ragged_fft``, and the autograd Functions ``FFTFunction`` and
+  ``SpectralEnergyFunction``.
+
+torch is used for device memory and streams only; every arithmetic step runs
+in the library's kernels.
+"""
+import ctypes
+import json
+import threading
+
+from ._lib import (CODES, FFT_ALGO_AUTO, FFT_ALGO_FOUR_STEP, FFT_ALGO_SINGLE_PASS,
+                   FFT_BACKWARD, FFT_FORWARD, STATUS, StockfftError, check, lib)
+
+__all__ = [
+    "FFT_FORWARD", "FFT_BACKWARD", "FFT_ALGO_AUTO", "FFT_ALGO_SINGLE_PASS",
+    "FFT_ALGO_FOUR_STEP", "StockfftError", "STATUS", "CODES",
+    "fft_plan", "fft_plan_config", "fft_exec", "fft_destroy",
+    "fft_exec_spectral_energy", "fft_exec_matched_filter",
+    "fft_plan_ragged", "fft_exec_ragged", "fft_exec_ragged_plain", "fft_destroy_ragged",
+    "fft_tune_load", "fft_tune_set", "fft_tune_clear", "fft_tune_query",
+    "fft_set_launch_limit",
+    "fft_variant_count", "fft_variant_describe", "fft_variant_twiddles",
+    "fft_plan_describe", "fft_status_string", "fft_last_hip_error", "fft_version",
+    "variants", "Plan", "RaggedPlan", "fft", "ifft_unnormalized", "spectral_energy",
+    "matched_filter", "ragged_fft", "FFTFunction", "SpectralEnergyFunction",
+]
+
+
+# ------------------------------------------------------------------ C names
+
+def _vp(x):
+    return ctypes.c_void_p(int(x) if x else 0)
+
+
+def fft_plan(n, batch, direction):
+    h = ctypes.c_void_p()
+    check("fft_plan", lib().fft_plan(ctypes.byref(h), int(n), int(batch), int(direction)))
+    return h.value
+
+
+def fft_plan_config(n, batch, direction, algorithm=FFT_ALGO_AUTO, variant=None):
+    h = ctypes.c_void_p()
+    v = variant.encode() if variant else None
+    check("fft_plan_config", lib().fft_plan_config(
+        ctypes.byref(h), int(n), int(batch), int(direction), int(algorithm), v))
+    return h.value
+
+
+def fft_exec(plan, in_ptr, out_ptr, stream=0):
+    return check("fft_exec", lib().fft_exec(_vp(plan), _vp(in_ptr), _vp(out_ptr), _vp(stream)))
+
+
+def fft_destroy(plan):
+    return check("fft_destroy", lib().fft_destroy(_vp(plan)))
+
+
+def fft_exec_spectral_energy(plan, x, w, grad_scale, grad_x, row_loss, loss_total, stream=0):
+    return check("fft_exec_spectral_energy", lib().fft_exec_spectral_energy(
+        _vp(plan), _vp(x), _vp(w), _vp(grad_scale), _vp(grad_x), _vp(row_loss),
+        _vp(loss_total), _vp(stream)))
+
+
+def fft_exec_matched_filter(plan, x, h, out, stream=0):
+    return check("fft_exec_matched_filter", lib().fft_exec_matched_filter(
+        _vp(plan), _vp(x), _vp(h), _vp(out), _vp(stream)))
+
+
+def fft_plan_ragged(sizes, direction):
+    arr = (ctypes.c_int64 * len(sizes))(*[int(s) for s in sizes])
+    h = ctypes.c_void_p()
+    check("fft_plan_ragged", lib().fft_plan_ragged(ctypes.byref(h), arr, len(sizes), int(direction)))
+    return h.value
+
+
+def fft_exec_ragged(plan, in_ptr, out_ptr, stream=0):
+    return check("fft_exec_ragged", lib().fft_exec_ragged(
+        _vp(plan), _vp(in_ptr), _vp(out_ptr), _vp(stream)))
+
+
+def fft_exec_ragged_plain(plan, in_by_size, out_by_size, stream=0):
+    ins = (ctypes.c_void_p * 7)(*[int(p) if p else None for p in in_by_size])
+    outs = (ctypes.c_void_p * 7)(*[int(p) if p else None for p in out_by_size])
+    return check("fft_exec_ragged_plain", lib().fft_exec_ragged_plain(
+        _vp(plan), ins, outs, _vp(stream)))
+
+
+def fft_destroy_ragged(plan):
+    return check("fft_destroy_ragged", lib().fft_destroy_ragged(_vp(plan)))
+
+
+def fft_tune_load(path):
+    return check("fft_tune_load", lib().fft_tune_load(str(path).encode()))
+
+
+def fft_tune_set(n, batch_min, batch_max, variant):
+    return check("fft_tune_set", lib().fft_tune_set(int(n), int(batch_min), int(batch_max),
+                                                    variant.encode()))
+
+
+def fft_tune_clear():
+    return check("fft_tune_clear", lib().fft_tune_clear())
+
+
+def fft_tune_query(n, batch):
+    buf = ctypes.create_string_buffer(256)
+    check("fft_tune_query", lib().fft_tune_query(int(n), int(batch), buf, len(buf)))
+    return buf.value.decode()
+
+
+def fft_set_launch_limit(max_groups):
+    return check("fft_set_launch_limit", lib().fft_set_launch_limit(int(max_groups)))
+
+
+def fft_variant_count():
+    return int(lib().fft_variant_count())
+
+
+def fft_variant_describe(index):
+    buf = ctypes.create_string_buffer(1024)
+    check("fft_variant_describe", lib().fft_variant_describe(int(index), buf, len(buf)))
+    return json.loads(buf.value.decode())
+
+
+def fft_variant_twiddles(index):
+    """Returns the variant's FP32 twiddle table as a complex64 numpy array."""
+    import numpy as np
+    cnt = ctypes.c_int64()
+    check("fft_variant_twiddles", lib().fft_variant_twiddles(int(index), None, 0, ctypes.byref(cnt)))
+    out = np.empty(2 * cnt.value, dtype=np.float32)
+    check("fft_variant_twiddles", lib().fft_variant_twiddles(
+        int(index), out.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), cnt.value, ctypes.byref(cnt)))
+    return out.view(np.complex64)
+
+
+def fft_plan_describe(plan):
+    buf = ctypes.create_string_buffer(4096)
+    check("fft_plan_describe", lib().fft_plan_describe(_vp(plan), buf, len(buf)))
+    return json.loads(buf.value.decode())
+
+
+def fft_status_string(status):
+    return lib().fft_status_string(int(status)).decode()
+
+
+def fft_last_hip_error():
+    return int(lib().fft_last_hip_error())
+
+
+def fft_version():
+    return int(lib().fft_version())
+
+
+def variants():
+    """Descriptions of every compiled kernel variant (host only)."""
+    return [fft_variant_describe(i) for i in range(fft_variant_count())]
+
+
+# ------------------------------------------------------------- plan objects
+
+class Plan:
+    """Owns one fft_plan handle; destroyed with the object or by close()."""
+
+    def __init__(self, n, batch, direction=FFT_FORWARD, algorithm=FFT_ALGO_AUTO, variant=None):
+        self.n, self.batch, self.direction = int(n), int(batch), int(direction)
+        self.handle = fft_plan_config(n, batch, direction, algorithm, variant)
+
+    def describe(self):
+        return fft_plan_describe(self.handle)
+
+    def exec(self, in_ptr, out_ptr, stream=0):
+        fft_exec(self.handle, in_ptr, out_ptr, stream)
+
+    def close(self):
+        if self.handle:
+            fft_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class RaggedPlan:
+    def __init__(self, sizes, direction=FFT_FORWARD):
+        self.sizes = [int(s) for s in sizes]
+        self.direction = int(direction)
+        self.handle = fft_plan_ragged(self.sizes, direction)
+
+    def exec(self, in_ptr, out_ptr, stream=0):
+        fft_exec_ragged(self.handle, in_ptr, out_ptr, stream)
+
+    def exec_plain(self, in_by_size, out_by_size, stream=0):
+        fft_exec_ragged_plain(self.handle, in_by_size, out_by_size, stream)
+
+    def close(self):
+        if self.handle:
+            fft_destroy_ragged(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_cache_lock = threading.Lock()
+_plan_cache = {}
+
+
+def cached_plan(n, batch, direction, device_index, algorithm=FFT_ALGO_AUTO, variant=None):
+    import torch
+    key = (int(n), int(batch), int(direction), int(device_index), int(algorithm), variant)
+    with _cache_lock:
+        p = _plan_cache.get(key)
+        if p is None:
+            with torch.cuda.device(device_index):
+                p = Plan(n, batch, direction, algorithm, variant)
+            _plan_cache[key] = p
+        return p
+
+
+def clear_plan_cache():
+    with _cache_lock:
+        for p in _plan_cache.values():
+            p.close()
+        _plan_cache.clear()
+
+
+# ------------------------------------------------------------ torch helpers
+
+def _check_tensor(x, name="x"):
+    import torch
+    if not isinstance(x, torch.Tensor) or x.device.type != "cuda":
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if x.dtype != torch.complex64:
+        raise ValueError(f"{name} must be complex64, got {x.dtype}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _stream(device):
+    import torch
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _transform(x, direction, out=None, algorithm=FFT_ALGO_AUTO, variant=None):
+    import torch
+    _check_tensor(x)
+    n = x.shape[-1]
+    batch = x.numel() // n if n else 0
+    if out is None:
+        out = torch.empty_like(x)
+    else:
+        _check_tensor(out, "out")
+        if out.shape != x.shape:
+            raise ValueError("out must have the shape of x")
+    if batch == 0:
+        return out
+    p = cached_plan(n, batch, direction, x.device.index, algorithm, variant)
+    fft_exec(p.handle, x.data_ptr(), out.data_ptr(), _stream(x.device))
+    return out
+
+
+def fft(x, inverse=False, out=None, algorithm=FFT_ALGO_AUTO, variant=None):
+    """Unscaled DFT along the last axis of a contiguous complex64 tensor.
+
+    inverse=True gives the backward transform exp(+2 pi i n k / N), also
+    unscaled (backward(forward(x)) = N x)."""
+    return _transform(x, FFT_BACKWARD if inverse else FFT_FORWARD, out, algorithm, variant)
+
+
+def ifft_unnormalized(x, out=None):
+    return fft(x, inverse=True, out=out)
+
+
+def spectral_energy(x, w, grad_scale=None, want_grad=True):
+    """Fused kernel: returns (loss_total[1], row_loss[batch], grad or None).
+
+    loss = sum_b sum_k w_k^2 |(F x_b)[k]|^2; grad = scale * F^H(2 w^2 F x_b)."""
+    import torch
+    _check_tensor(x)
+    if w.device != x.device or w.dtype != torch.float32 or not w.is_contiguous():
+        raise ValueError("w must be a contiguous float32 tensor on x's device")
+    n = x.shape[-1]
+    if w.numel() != n:
+        raise ValueError("w must have N elements")
+    batch = x.numel() // n
+    p = cached_plan(n, batch, FFT_FORWARD, x.device.index, FFT_ALGO_SINGLE_PASS)
+    row_loss = torch.empty(batch, dtype=torch.float32, device=x.device)
+    total = torch.empty(1, dtype=torch.float32, device=x.device)
+    grad = torch.empty_like(x) if want_grad else None
+    gs = 0
+    if grad_scale is not None:
+        if grad_scale.dtype != torch.float32 or grad_scale.device != x.device:
+            raise ValueError("grad_scale must be a float32 tensor on x's device")
+        grad_scale = grad_scale.contiguous()
+        gs = grad_scale.data_ptr()
+    fft_exec_spectral_energy(p.handle, x.data_ptr(), w.data_ptr(), gs,
+                             grad.data_ptr() if grad is not None else 0,
+                             row_loss.data_ptr(), total.data_ptr(), _stream(x.device))
+    return total, row_loss, grad
+
+
+def matched_filter(x, h, out=None):
+    """Fused range compression: out = F^{-1}(conj(h) * F x) per row."""
+    import torch
+    _check_tensor(x)
+    _check_tensor(h, "h")
+    n = x.shape[-1]
+    if h.numel() != n:
+        raise ValueError("h must have N elements")
+    batch = x.numel() // n
+    if out is None:
+        out = torch.empty_like(x)
+    p = cached_plan(n, batch, FFT_FORWARD, x.device.index, FFT_ALGO_SINGLE_PASS)
+    fft_exec_matched_filter(p.handle, x.data_ptr(), h.data_ptr(), out.data_ptr(), _stream(x.device))
+    return out
+
+
+def ragged_fft(packed, plan, out=None):
+    """Transforms every row of a packed ragged buffer with a RaggedPlan."""
+    import torch
+    _check_tensor(packed, "packed")
+    if out is None:
+        out = torch.empty_like(packed)
+    plan.exec(packed.data_ptr(), out.data_ptr(), _stream(packed.device))
+    return out
+
+
+def _autograd():
+    import torch
+
+    class FFTFunction(torch.autograd.Function):
+        """y = F x (unscaled).  The gradient of a real loss through y is
+        F^H g, the backward transform of g, computed by the same kernels."""
+
+        @staticmethod
+        def forward(ctx, x, inverse=False):
+            ctx.inverse = bool(inverse)
+            return fft(x.contiguous(), inverse=inverse)
+
+        @staticmethod
+        def backward(ctx, g):
+            return fft(g.contiguous(), inverse=not ctx.inverse), None
+
+    class SpectralEnergyFunction(torch.autograd.Function):
+        """L = sum_b sum_k w_k^2 |(F x_b)[k]|^2 as a scalar.
+
+        The forward pass runs the fused kernel in loss-only mode (reads x
+        once); the backward pass runs it again with grad_output folded in as
+        the device-side scale, producing F^H(2 w^2 F x) in one kernel."""
+
+        @staticmethod
+        def forward(ctx, x, w):
+            x = x.contiguous()
+            total, _, _ = spectral_energy(x, w, want_grad=False)
+            ctx.save_for_backward(x, w)
+            return total.reshape(())
+
+        @staticmethod
+        def backward(ctx, go):
+            x, w = ctx.saved_tensors
+            scale = go.reshape(1).to(torch.float32).contiguous()
+            _, _, grad = spectral_energy(x, w, grad_scale=scale)
+            return grad, None
+
+    return FFTFunction, SpectralEnergyFunction
+
+
+def __getattr__(name):
+    if name in ("FFTFunction", "SpectralEnergyFunction"):
+        f, s = _autograd()
+        globals()["FFTFunction"] = f
+        globals()["SpectralEnergyFunction"] = s
+        return globals()[name]
+    raise AttributeError(name)

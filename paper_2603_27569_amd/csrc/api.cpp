@@ -1,0 +1,663 @@
+// C ABI of the library: planning, twiddle tables, execution, tuning and
+// introspection.  Declarations and argument contracts: include/stockfft.h.
+#include "../../include/stockfft.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cerrno>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <unordered_set>
+#include <vector>
+
+#include "internal.hpp"
+#include "variants.hpp"
+
+namespace stockfft {
+const SingleVariant* variants_small(int* count);
+const SingleVariant* variants_4096(int* count);
+const SingleVariant* variants_large(int* count);
+hipError_t launch_sum_rows(const float* rows, float* total, int64_t count, hipStream_t s);
+}  // namespace stockfft
+
+using namespace stockfft;
+
+namespace stockfft {
+
+thread_local int g_last_hip_error = 0;
+
+namespace {
+std::atomic<int64_t> g_max_groups{kDefaultMaxGroupsPerLaunch};
+}
+int64_t max_groups_per_launch() { return g_max_groups.load(std::memory_order_relaxed); }
+void set_max_groups_per_launch(int64_t g) { g_max_groups.store(g, std::memory_order_relaxed); }
+
+int hip_fail(hipError_t e) {
+  g_last_hip_error = (int)e;
+  if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) return FFT_ALLOC_FAILED;
+  return FFT_HIP_ERROR;
+}
+
+const std::vector<const SingleVariant*>& single_variants() {
+  static const std::vector<const SingleVariant*> all = [] {
+    std::vector<const SingleVariant*> v;
+    for (auto fn : {variants_small, variants_4096, variants_large}) {
+      int c = 0;
+      const SingleVariant* t = fn(&c);
+      for (int i = 0; i < c; ++i) v.push_back(&t[i]);
+    }
+    return v;
+  }();
+  return all;
+}
+
+const SingleVariant* find_single(const char* name) {
+  if (!name) return nullptr;
+  for (const SingleVariant* v : single_variants())
+    if (std::strcmp(v->name, name) == 0) return v;
+  return nullptr;
+}
+
+int num_four_step() {
+  int c = 0;
+  four_step_variants(&c);
+  return c;
+}
+
+const FourStepVariant& four_step_at(int i) {
+  int c = 0;
+  return four_step_variants(&c)[i];
+}
+
+const FourStepVariant* find_four_step(const char* name) {
+  if (!name) return nullptr;
+  for (int i = 0; i < num_four_step(); ++i)
+    if (std::strcmp(four_step_at(i).name, name) == 0) return &four_step_at(i);
+  return nullptr;
+}
+
+bool valid_size(int64_t n) { return n >= 256 && n <= 16384 && (n & (n - 1)) == 0; }
+
+int ilog2(int64_t n) {
+  int l = 0;
+  while ((int64_t(1) << l) < n) ++l;
+  return l;
+}
+
+// exp(-2 pi i m / L) for 0 <= m < L, evaluated in FP64 and rounded once to FP32.
+static void root_f32(int64_t m, int64_t L, float* re, float* im) {
+  const double a = -2.0 * M_PI * (double)m / (double)L;
+  *re = (float)std::cos(a);
+  *im = (float)std::sin(a);
+}
+
+// Per-pass tables of a Stockham plan: for pass p >= 1 with Ns = R_0 ... R_{p-1},
+// entry [r - 1][k] = W_{Ns R_p}^{k r}, r in [1, R_p), k in [0, Ns).
+void build_stockham_twiddles(const SingleVariant& v, std::vector<float>& out) {
+  out.clear();
+  int64_t ns = v.radix[0];
+  for (int p = 1; p < v.npass; ++p) {
+    const int R = v.radix[p];
+    const int64_t L = ns * R;
+    for (int r = 1; r < R; ++r)
+      for (int64_t k = 0; k < ns; ++k) {
+        float re, im;
+        root_f32(k * r, L, &re, &im);
+        out.push_back(re);
+        out.push_back(im);
+      }
+    ns *= R;
+  }
+}
+
+// Four-step table: entry [n1 - 1][k2] = W_N^{n1 k2}, n1 in [1, N1), k2 in [0, N2).
+void build_four_step_twiddles(int n1c, int n2c, std::vector<float>& out) {
+  out.clear();
+  const int64_t N = (int64_t)n1c * n2c;
+  for (int n1 = 1; n1 < n1c; ++n1)
+    for (int64_t k2 = 0; k2 < n2c; ++k2) {
+      float re, im;
+      root_f32(n1 * k2, N, &re, &im);
+      out.push_back(re);
+      out.push_back(im);
+    }
+}
+
+int upload(const std::vector<float>& host, void** dev) {
+  *dev = nullptr;
+  if (host.empty()) return FFT_SUCCESS;
+  if (std::getenv("STOCKFFT_FAIL_ALLOC")) return FFT_ALLOC_FAILED;
+  hipError_t e = hipMalloc(dev, host.size() * sizeof(float));
+  if (e != hipSuccess) {
+    *dev = nullptr;
+    return hip_fail(e);
+  }
+  e = hipMemcpy(*dev, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(*dev);
+    *dev = nullptr;
+    return hip_fail(e);
+  }
+  return FFT_SUCCESS;
+}
+
+int check_device(int* dev) {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return FFT_NO_DEVICE;
+  hipError_t e = hipGetDevice(dev);
+  if (e != hipSuccess) return hip_fail(e);
+  return FFT_SUCCESS;
+}
+
+bool ranges_partially_overlap(const void* a, const void* b, size_t bytes) {
+  const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+  if (x == y) return false;
+  return x < y + bytes && y < x + bytes;
+}
+
+bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
+
+DeviceGuard::DeviceGuard(int dev) {
+  if (hipGetDevice(&prev_) == hipSuccess && prev_ != dev) {
+    if (hipSetDevice(dev) == hipSuccess) switched_ = true;
+  }
+}
+DeviceGuard::~DeviceGuard() {
+  if (switched_) (void)hipSetDevice(prev_);
+}
+
+// ------------------------------------------------------------------ tuning
+
+namespace {
+
+struct TuneEntry {
+  int64_t n, bmin, bmax;
+  const SingleVariant* v;
+};
+
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+bool g_env_tune_done = false;
+
+// Built-in choices per size (used when no tuning entry matches).
+const char* builtin_variant(int64_t n) {
+  switch (n) {
+    case 256: return "n256_e16_b16_p4_r16.16";
+    case 512: return "n512_e16_b8_p4_r16.16.2";
+    case 1024: return "n1024_e16_b4_p4_r16.16.4";
+    case 2048: return "n2048_e16_b2_p4_r16.16.8";
+    case 4096: return "n4096_e16_b1_p4_r16.16.16";
+    case 8192: return "n8192_e16_b1_p4_r16.16.16.2";
+    case 16384: return "n16384_e16_b1_p4_r16.16.16.4";
+    default: return nullptr;
+  }
+}
+
+void load_env_tune_locked();
+
+}  // namespace
+
+const SingleVariant* tuned_variant(int64_t n, int64_t batch) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_env_tune_locked();
+  const SingleVariant* pick = nullptr;
+  for (const TuneEntry& e : g_tune)
+    if (e.n == n && batch >= e.bmin && batch <= e.bmax) pick = e.v;
+  return pick ? pick : find_single(builtin_variant(n));
+}
+
+namespace {
+
+// Minimal reader for the tuner's JSON: every innermost {...} object carrying
+// "n" and "variant" is an entry; "arch" at top level is compared with the
+// device's architecture name when a device is present.
+bool json_find_int(const std::string& obj, const char* key, int64_t* out) {
+  std::string k = std::string("\"") + key + "\"";
+  size_t p = obj.find(k);
+  if (p == std::string::npos) return false;
+  p = obj.find(':', p + k.size());
+  if (p == std::string::npos) return false;
+  const char* s = obj.c_str() + p + 1;
+  char* end = nullptr;
+  errno = 0;
+  long long v = std::strtoll(s, &end, 10);
+  if (end == s || errno) return false;
+  *out = (int64_t)v;
+  return true;
+}
+
+bool json_find_str(const std::string& obj, const char* key, std::string* out) {
+  std::string k = std::string("\"") + key + "\"";
+  size_t p = obj.find(k);
+  if (p == std::string::npos) return false;
+  p = obj.find(':', p + k.size());
+  if (p == std::string::npos) return false;
+  size_t q = obj.find('"', p);
+  if (q == std::string::npos) return false;
+  size_t r = obj.find('"', q + 1);
+  if (r == std::string::npos) return false;
+  *out = obj.substr(q + 1, r - q - 1);
+  return true;
+}
+
+int load_tune_file_locked(const char* path) {
+  FILE* f = std::fopen(path, "rb");
+  if (!f) {
+    std::fprintf(stderr, "stockfft: tune file %s not readable; using built-in table\n", path);
+    return FFT_INVALID_ARGUMENT;
+  }
+  std::string text;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+  std::fclose(f);
+  std::string arch;
+  if (json_find_str(text, "arch", &arch)) {
+    int count = 0, dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceCount(&count) == hipSuccess && count > 0 && hipGetDevice(&dev) == hipSuccess &&
+        hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+        std::strncmp(prop.gcnArchName, arch.c_str(), arch.size()) != 0) {
+      std::fprintf(stderr, "stockfft: tune file %s is for %s, device is %s; ignored\n", path,
+                   arch.c_str(), prop.gcnArchName);
+      return FFT_INVALID_ARGUMENT;
+    }
+  }
+  std::vector<TuneEntry> add;
+  int skipped = 0;
+  size_t pos = 0;
+  while ((pos = text.find('{', pos)) != std::string::npos) {
+    size_t close = text.find('}', pos);
+    size_t inner = text.find('{', pos + 1);
+    if (close == std::string::npos) break;
+    if (inner != std::string::npos && inner < close) {  // not innermost
+      pos = inner;
+      continue;
+    }
+    std::string obj = text.substr(pos, close - pos + 1);
+    pos = close + 1;
+    int64_t n = 0, bmin = 1, bmax = INT64_MAX;
+    std::string name;
+    if (!json_find_int(obj, "n", &n) || !json_find_str(obj, "variant", &name)) continue;
+    json_find_int(obj, "batch_min", &bmin);
+    json_find_int(obj, "batch_max", &bmax);
+    const SingleVariant* v = find_single(name.c_str());
+    if (!v || v->n != n) {
+      ++skipped;
+      continue;
+    }
+    add.push_back({n, bmin, bmax, v});
+  }
+  if (skipped)
+    std::fprintf(stderr, "stockfft: %d tune entries in %s name unknown variants; skipped\n",
+                 skipped, path);
+  g_tune.insert(g_tune.end(), add.begin(), add.end());
+  return FFT_SUCCESS;
+}
+
+void load_env_tune_locked() {
+  if (g_env_tune_done) return;
+  g_env_tune_done = true;
+  const char* p = std::getenv("STOCKFFT_TUNE_CACHE");
+  if (p && *p) (void)load_tune_file_locked(p);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------- plans
+
+namespace {
+std::mutex g_plans_mu;
+std::unordered_set<const void*> g_plans;
+}  // namespace
+
+void register_handle(const void* p) {
+  std::lock_guard<std::mutex> lk(g_plans_mu);
+  g_plans.insert(p);
+}
+bool unregister_handle(const void* p) {
+  std::lock_guard<std::mutex> lk(g_plans_mu);
+  return g_plans.erase(p) == 1;
+}
+bool live_handle(const void* p) {
+  std::lock_guard<std::mutex> lk(g_plans_mu);
+  return g_plans.count(p) == 1;
+}
+
+}  // namespace stockfft
+
+struct stockfft_plan_s {
+  int64_t n = 0, batch = 0;
+  int direction = FFT_FORWARD;
+  int device = 0;
+  int algorithm = FFT_ALGO_SINGLE_PASS;
+  const SingleVariant* sv = nullptr;    // single-pass shape, or the four-step sub-shape
+  const FourStepVariant* fs = nullptr;  // four-step split when algorithm == FOUR_STEP
+  void* d_tw = nullptr;
+  void* d_tw4 = nullptr;
+  void* d_ws = nullptr;
+  size_t ws_bytes = 0;
+};
+
+static void free_plan(stockfft_plan_s* p) {
+  if (!p) return;
+  if (p->d_tw) (void)hipFree(p->d_tw);
+  if (p->d_tw4) (void)hipFree(p->d_tw4);
+  if (p->d_ws) (void)hipFree(p->d_ws);
+  delete p;
+}
+
+static int validate_common(int64_t n, int64_t batch, int direction) {
+  if (!valid_size(n)) return FFT_INVALID_SIZE;
+  if (batch < 1 || batch > (int64_t)(SIZE_MAX / 8 / (uint64_t)n) ||
+      batch > INT64_MAX / 8 / n)
+    return FFT_INVALID_BATCH;
+  if (direction != FFT_FORWARD && direction != FFT_BACKWARD) return FFT_INVALID_DIRECTION;
+  return FFT_SUCCESS;
+}
+
+extern "C" int fft_plan_config(fft_plan_t* plan, int64_t n, int64_t batch, int direction,
+                               int algorithm, const char* variant) {
+  if (!plan) return FFT_INVALID_POINTER;
+  *plan = nullptr;
+  int rc = validate_common(n, batch, direction);
+  if (rc) return rc;
+  if (algorithm != FFT_ALGO_AUTO && algorithm != FFT_ALGO_SINGLE_PASS &&
+      algorithm != FFT_ALGO_FOUR_STEP)
+    return FFT_INVALID_ARGUMENT;
+
+  const SingleVariant* sv = nullptr;
+  const FourStepVariant* fs = nullptr;
+  if (algorithm == FFT_ALGO_FOUR_STEP) {
+    if (variant) {
+      fs = find_four_step(variant);
+      if (!fs || fs->n != n) return FFT_INVALID_ARGUMENT;
+    } else {
+      for (int i = 0; i < num_four_step() && !fs; ++i)
+        if (four_step_at(i).n == n) fs = &four_step_at(i);
+      if (!fs) return FFT_UNSUPPORTED;
+    }
+    sv = find_single(fs->sub_name);
+    if (!sv) return FFT_INVALID_ARGUMENT;
+  } else if (variant) {
+    sv = find_single(variant);
+    if (!sv || sv->n != n) {
+      const FourStepVariant* f = find_four_step(variant);
+      if (algorithm == FFT_ALGO_AUTO && f && f->n == n) {
+        fs = f;
+        sv = find_single(f->sub_name);
+      } else {
+        return FFT_INVALID_ARGUMENT;
+      }
+    }
+  } else {
+    sv = tuned_variant(n, batch);
+    if (!sv) return FFT_INVALID_SIZE;
+  }
+
+  int dev = 0;
+  rc = check_device(&dev);
+  if (rc) return rc;
+
+  stockfft_plan_s* p = new (std::nothrow) stockfft_plan_s;
+  if (!p) return FFT_ALLOC_FAILED;
+  p->n = n;
+  p->batch = batch;
+  p->direction = direction;
+  p->device = dev;
+  p->sv = sv;
+  p->fs = fs;
+  p->algorithm = fs ? FFT_ALGO_FOUR_STEP : FFT_ALGO_SINGLE_PASS;
+
+  std::vector<float> host;
+  build_stockham_twiddles(*sv, host);
+  rc = upload(host, &p->d_tw);
+  if (!rc && fs) {
+    build_four_step_twiddles(fs->n1, fs->n2, host);
+    rc = upload(host, &p->d_tw4);
+    if (!rc) {
+      p->ws_bytes = (size_t)n * (size_t)batch * 8;
+      hipError_t e = hipMalloc(&p->d_ws, p->ws_bytes);
+      if (e != hipSuccess) {
+        p->d_ws = nullptr;
+        rc = hip_fail(e);
+      }
+    }
+  }
+  if (rc) {
+    free_plan(p);
+    return rc;
+  }
+  register_handle(p);
+  *plan = p;
+  return FFT_SUCCESS;
+}
+
+extern "C" int fft_plan(fft_plan_t* plan, int64_t n, int64_t batch, int direction) {
+  return fft_plan_config(plan, n, batch, direction, FFT_ALGO_AUTO, nullptr);
+}
+
+extern "C" int fft_exec(fft_plan_t plan, const void* in, void* out, void* stream) {
+  if (!plan || !live_handle(plan)) return FFT_INVALID_PLAN;
+  if (!in || !out) return FFT_INVALID_POINTER;
+  if (!aligned8(in) || !aligned8(out)) return FFT_MISALIGNED;
+  const size_t bytes = (size_t)plan->n * (size_t)plan->batch * 8;
+  if (ranges_partially_overlap(in, out, bytes)) return FFT_OVERLAP;
+  DeviceGuard g(plan->device);
+  hipStream_t s = (hipStream_t)stream;
+  const bool inv = plan->direction == FFT_BACKWARD;
+  hipError_t e;
+  if (plan->algorithm == FFT_ALGO_FOUR_STEP) {
+    e = plan->fs->columns(in, plan->d_ws, plan->d_tw, plan->batch, inv, s);
+    if (e == hipSuccess) e = plan->fs->combine(plan->d_ws, out, plan->d_tw4, plan->batch, inv, s);
+  } else {
+    e = plan->sv->launch(in, out, plan->d_tw, plan->batch, inv, s);
+  }
+  return e == hipSuccess ? FFT_SUCCESS : hip_fail(e);
+}
+
+extern "C" int fft_destroy(fft_plan_t plan) {
+  if (!plan) return FFT_SUCCESS;
+  if (!unregister_handle(plan)) return FFT_INVALID_PLAN;
+  free_plan(plan);
+  return FFT_SUCCESS;
+}
+
+extern "C" int fft_exec_spectral_energy(fft_plan_t plan, const void* x, const float* w,
+                                        const float* grad_scale, void* grad_x, float* row_loss,
+                                        float* loss_total, void* stream) {
+  if (!plan || !live_handle(plan)) return FFT_INVALID_PLAN;
+  if (plan->direction != FFT_FORWARD || plan->algorithm != FFT_ALGO_SINGLE_PASS ||
+      !plan->sv->fused)
+    return FFT_UNSUPPORTED;
+  if (!x || !w || !row_loss) return FFT_INVALID_POINTER;
+  if (!aligned8(x) || (grad_x && !aligned8(grad_x)) || ((uintptr_t)w & 3u) ||
+      ((uintptr_t)row_loss & 3u) || (grad_scale && ((uintptr_t)grad_scale & 3u)) ||
+      (loss_total && ((uintptr_t)loss_total & 3u)))
+    return FFT_MISALIGNED;
+  const size_t bytes = (size_t)plan->n * (size_t)plan->batch * 8;
+  if (grad_x && ranges_partially_overlap(x, grad_x, bytes)) return FFT_OVERLAP;
+  DeviceGuard g(plan->device);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = plan->sv->fused(x, w, grad_scale, grad_x, row_loss, plan->d_tw, plan->batch, s);
+  if (e == hipSuccess && loss_total) e = launch_sum_rows(row_loss, loss_total, plan->batch, s);
+  return e == hipSuccess ? FFT_SUCCESS : hip_fail(e);
+}
+
+extern "C" int fft_exec_matched_filter(fft_plan_t plan, const void* x, const void* h, void* out,
+                                       void* stream) {
+  if (!plan || !live_handle(plan)) return FFT_INVALID_PLAN;
+  if (plan->direction != FFT_FORWARD || plan->algorithm != FFT_ALGO_SINGLE_PASS ||
+      !plan->sv->filter)
+    return FFT_UNSUPPORTED;
+  if (!x || !h || !out) return FFT_INVALID_POINTER;
+  if (!aligned8(x) || !aligned8(h) || !aligned8(out)) return FFT_MISALIGNED;
+  const size_t bytes = (size_t)plan->n * (size_t)plan->batch * 8;
+  if (ranges_partially_overlap(x, out, bytes)) return FFT_OVERLAP;
+  DeviceGuard g(plan->device);
+  hipError_t e = plan->sv->filter(x, h, out, plan->d_tw, plan->batch, (hipStream_t)stream);
+  return e == hipSuccess ? FFT_SUCCESS : hip_fail(e);
+}
+
+// ------------------------------------------------------------ tuning ABI
+
+static int put_text(const std::string& s, char* buf, int64_t cap) {
+  if (!buf) return FFT_INVALID_POINTER;
+  if (cap < (int64_t)s.size() + 1) return FFT_INVALID_ARGUMENT;
+  std::memcpy(buf, s.c_str(), s.size() + 1);
+  return FFT_SUCCESS;
+}
+
+extern "C" int fft_tune_load(const char* json_path) {
+  if (!json_path) return FFT_INVALID_POINTER;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_env_tune_locked();
+  return load_tune_file_locked(json_path);
+}
+
+extern "C" int fft_tune_set(int64_t n, int64_t batch_min, int64_t batch_max, const char* variant) {
+  if (!variant) return FFT_INVALID_POINTER;
+  if (!valid_size(n)) return FFT_INVALID_SIZE;
+  if (batch_min < 1 || batch_max < batch_min) return FFT_INVALID_BATCH;
+  const SingleVariant* v = find_single(variant);
+  if (!v || v->n != n) return FFT_INVALID_ARGUMENT;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  load_env_tune_locked();
+  g_tune.push_back({n, batch_min, batch_max, v});
+  return FFT_SUCCESS;
+}
+
+extern "C" int fft_tune_query(int64_t n, int64_t batch, char* buf, int64_t cap) {
+  if (!buf) return FFT_INVALID_POINTER;
+  if (!valid_size(n)) return FFT_INVALID_SIZE;
+  if (batch < 1) return FFT_INVALID_BATCH;
+  const SingleVariant* v = tuned_variant(n, batch);
+  if (!v) return FFT_INVALID_SIZE;
+  return put_text(v->name, buf, cap);
+}
+
+extern "C" int fft_set_launch_limit(int64_t max_groups) {
+  set_max_groups_per_launch(max_groups > 0 ? max_groups : kDefaultMaxGroupsPerLaunch);
+  return FFT_SUCCESS;
+}
+
+extern "C" int fft_tune_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_env_tune_done = true;
+  g_tune.clear();
+  return FFT_SUCCESS;
+}
+
+// --------------------------------------------------------- introspection
+
+static int barriers_of(const SingleVariant& v) {
+  // One barrier after each LDS write and one after each LDS read that is
+  // followed by another write: the first pass reads and the last pass writes
+  // global memory directly.
+  return v.npass >= 2 ? 2 * v.npass - 3 : 0;
+}
+
+static std::string radices_json(const SingleVariant& v) {
+  std::string s = "[";
+  for (int i = 0; i < v.npass; ++i) {
+    if (i) s += ",";
+    s += std::to_string(v.radix[i]);
+  }
+  return s + "]";
+}
+
+static std::string describe_single(const SingleVariant& v) {
+  char buf[512];
+  std::snprintf(buf, sizeof buf,
+                "{\"kind\":\"single\",\"name\":\"%s\",\"n\":%d,\"values_per_lane\":%d,"
+                "\"lanes_per_transform\":%d,\"transforms_per_workgroup\":%d,\"pad_log2\":%d,"
+                "\"passes\":%d,\"radices\":%s,\"threads\":%d,\"lds_bytes\":%d,"
+                "\"twiddle_entries\":%d,\"barriers\":%d}",
+                v.name, v.n, v.e, v.t, v.tpb, v.padlog, v.npass, radices_json(v).c_str(),
+                v.threads, v.lds_bytes, v.tw_elems, barriers_of(v));
+  return buf;
+}
+
+static std::string describe_four_step(const FourStepVariant& f) {
+  char buf[384];
+  std::snprintf(buf, sizeof buf,
+                "{\"kind\":\"four_step\",\"name\":\"%s\",\"n\":%d,\"n1\":%d,\"n2\":%d,"
+                "\"sub_variant\":\"%s\",\"twiddle_entries\":%d}",
+                f.name, f.n, f.n1, f.n2, f.sub_name, f.tw_sub_elems + (f.n1 - 1) * f.n2);
+  return buf;
+}
+
+extern "C" int fft_variant_count(void) {
+  return (int)single_variants().size() + num_four_step();
+}
+
+extern "C" int fft_variant_describe(int index, char* buf, int64_t cap) {
+  const int ns = (int)single_variants().size();
+  if (index < 0 || index >= ns + num_four_step()) return FFT_INVALID_ARGUMENT;
+  if (index < ns) return put_text(describe_single(*single_variants()[index]), buf, cap);
+  return put_text(describe_four_step(four_step_at(index - ns)), buf, cap);
+}
+
+extern "C" int fft_variant_twiddles(int index, float* out, int64_t cap_complex, int64_t* count) {
+  if (!count) return FFT_INVALID_POINTER;
+  const int ns = (int)single_variants().size();
+  if (index < 0 || index >= ns + num_four_step()) return FFT_INVALID_ARGUMENT;
+  std::vector<float> host, tw4;
+  if (index < ns) {
+    build_stockham_twiddles(*single_variants()[index], host);
+  } else {
+    const FourStepVariant& f = four_step_at(index - ns);
+    const SingleVariant* sub = find_single(f.sub_name);
+    if (!sub) return FFT_INVALID_ARGUMENT;
+    build_stockham_twiddles(*sub, host);
+    build_four_step_twiddles(f.n1, f.n2, tw4);
+    host.insert(host.end(), tw4.begin(), tw4.end());
+  }
+  *count = (int64_t)host.size() / 2;
+  if (!out) return FFT_SUCCESS;
+  if (cap_complex < *count) return FFT_INVALID_ARGUMENT;
+  std::memcpy(out, host.data(), host.size() * sizeof(float));
+  return FFT_SUCCESS;
+}
+
+extern "C" int fft_plan_describe(fft_plan_t plan, char* buf, int64_t cap) {
+  if (!plan || !live_handle(plan)) return FFT_INVALID_PLAN;
+  std::string s = "{\"n\":" + std::to_string(plan->n) + ",\"batch\":" +
+                  std::to_string(plan->batch) + ",\"direction\":" +
+                  std::to_string(plan->direction) + ",\"device\":" + std::to_string(plan->device) +
+                  ",\"algorithm\":\"" +
+                  (plan->algorithm == FFT_ALGO_FOUR_STEP ? "four_step" : "single_pass") + "\"" +
+                  ",\"workspace_bytes\":" + std::to_string(plan->ws_bytes) +
+                  ",\"variant\":" + describe_single(*plan->sv) +
+                  (plan->fs ? ",\"four_step\":" + describe_four_step(*plan->fs) : "") + "}";
+  return put_text(s, buf, cap);
+}
+
+extern "C" const char* fft_status_string(int status) {
+  switch (status) {
+    case FFT_SUCCESS: return "success";
+    case FFT_INVALID_SIZE: return "invalid size: N must be a power of two in [256, 16384]";
+    case FFT_INVALID_BATCH: return "invalid batch";
+    case FFT_INVALID_DIRECTION: return "invalid direction: use FFT_FORWARD (-1) or FFT_BACKWARD (+1)";
+    case FFT_INVALID_POINTER: return "null pointer";
+    case FFT_MISALIGNED: return "misaligned pointer";
+    case FFT_OVERLAP: return "input and output partially overlap";
+    case FFT_INVALID_PLAN: return "invalid or destroyed plan";
+    case FFT_NO_DEVICE: return "no HIP device";
+    case FFT_ALLOC_FAILED: return "device allocation failed";
+    case FFT_HIP_ERROR: return "HIP error";
+    case FFT_INVALID_ARGUMENT: return "invalid argument";
+    case FFT_UNSUPPORTED: return "unsupported operation for this plan";
+    default: return "unknown status";
+  }
+}
+
+extern "C" int fft_last_hip_error(void) { return g_last_hip_error; }
+
+extern "C" int fft_version(void) { return 10000; }

@@ -1,0 +1,285 @@
+// Kernels of the plain, fused and four-step paths, templated on a Stockham
+// Shape (stockham.hpp).  Each kernel is launched by a small host wrapper that
+// splits very large batches into several grids.
+#pragma once
+
+#include "stockham.hpp"
+#include "variants.hpp"
+
+namespace stockfft {
+
+
+template <class S>
+__device__ __forceinline__ void global_load_row(c32 (&a)[S::E], const c32* src, int t, bool live) {
+  if (live) {
+#pragma unroll
+    for (int m = 0; m < S::E; ++m) a[m] = src[t + m * S::T];
+  } else {
+#pragma unroll
+    for (int m = 0; m < S::E; ++m) a[m] = c32{0.f, 0.f};
+  }
+}
+
+template <class S>
+__device__ __forceinline__ void global_store_row(const c32 (&a)[S::E], c32* dst, int t, bool live) {
+  if (live) {
+#pragma unroll
+    for (int m = 0; m < S::E; ++m) dst[t + m * S::T] = a[m];
+  }
+}
+
+// ------------------------------------------------------------ single pass
+// One dispatch per batch (the paper's synthesis rule 1, Section IV-D): each
+// workgroup owns TPB whole transforms; every pass stays on chip.
+template <class S, bool INV>
+__global__ __launch_bounds__(S::THREADS) void k_stockham(const c32* in, c32* out,
+                                                         const c32* __restrict__ tw, int64_t rows) {
+  __shared__ c32 lds_all[S::TPB * S::LDS_ELEMS];
+  const int tid = threadIdx.x;
+  const int slot = tid / S::T;
+  const int t = tid - slot * S::T;
+  const int64_t row = (int64_t)blockIdx.x * S::TPB + slot;
+  const bool live = row < rows;
+  c32* lds = lds_all + slot * S::LDS_ELEMS;
+  c32 a[S::E];
+  global_load_row<S>(a, in + row * S::N, t, live);
+  run_passes<S, 0, INV>(a, lds, tw, t);
+  global_store_row<S>(a, out + row * S::N, t, live);
+}
+
+template <class S>
+hipError_t launch_single(const void* in, void* out, const void* tw, int64_t batch, bool inverse,
+                         hipStream_t s) {
+  const int64_t groups = (batch + S::TPB - 1) / S::TPB;
+  const int64_t cap = max_groups_per_launch();
+  for (int64_t g0 = 0; g0 < groups; g0 += cap) {
+    const int64_t g = groups - g0 < cap ? groups - g0 : cap;
+    const int64_t r0 = g0 * S::TPB;
+    const c32* ip = static_cast<const c32*>(in) + r0 * S::N;
+    c32* op = static_cast<c32*>(out) + r0 * S::N;
+    const c32* twp = static_cast<const c32*>(tw);
+    if (inverse)
+      k_stockham<S, true><<<dim3((unsigned)g), dim3(S::THREADS), 0, s>>>(ip, op, twp, batch - r0);
+    else
+      k_stockham<S, false><<<dim3((unsigned)g), dim3(S::THREADS), 0, s>>>(ip, op, twp, batch - r0);
+  }
+  return hipGetLastError();
+}
+
+// Sum v over the T lanes that own one transform.  Returns the total in lane
+// t == 0 of each transform (other lanes: partial values).  `red` holds one
+// float per wave; the caller places a barrier between this call's LDS write
+// and finish_row_sum().
+template <class S>
+__device__ __forceinline__ float wave_group_sum(float v) {
+  constexpr int W = S::T < 64 ? S::T : 64;
+#pragma unroll
+  for (int off = W / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// -------------------------------------------------- fused forward/adjoint
+// x -> y = F x -> (row loss sum w^2 |y|^2, g = 2 w^2 y * scale) -> F^H g.
+// Reads x once and writes the gradient once: 16 N bytes per row against the
+// 48 N of three separate launches.
+template <class S>
+__global__ __launch_bounds__(S::THREADS) void k_spectral_energy(
+    const c32* x, const float* __restrict__ w, const float* __restrict__ scale, c32* grad,
+    float* __restrict__ row_loss, const c32* __restrict__ tw, int64_t rows) {
+  __shared__ c32 lds_all[S::TPB * S::LDS_ELEMS];
+  __shared__ float red[(S::THREADS + 63) / 64];
+  const int tid = threadIdx.x;
+  const int slot = tid / S::T;
+  const int t = tid - slot * S::T;
+  const int64_t row = (int64_t)blockIdx.x * S::TPB + slot;
+  const bool live = row < rows;
+  c32* lds = lds_all + slot * S::LDS_ELEMS;
+  c32 a[S::E];
+  global_load_row<S>(a, x + row * S::N, t, live);
+  run_passes<S, 0, false>(a, lds, tw, t);
+
+  const float sc = scale ? 2.0f * scale[0] : 2.0f;
+  float acc = 0.f;
+#pragma unroll
+  for (int m = 0; m < S::E; ++m) {
+    const float wq = w[t + m * S::T];
+    const float w2 = wq * wq;
+    const c32 y = a[m];
+    acc += w2 * (y.x * y.x + y.y * y.y);
+    const float g = sc * w2;
+    a[m] = c32{g * y.x, g * y.y};
+  }
+  acc = wave_group_sum<S>(acc);
+  if constexpr (S::T > 64) {
+    if ((tid & 63) == 0) red[tid >> 6] = acc;
+  }
+  __syncthreads();  // forward passes done with LDS; wave partials visible
+  if (t == 0 && live) {
+    float total = acc;
+    if constexpr (S::T > 64) {
+      total = 0.f;
+      const int w0 = (slot * S::T) >> 6;
+#pragma unroll
+      for (int i = 0; i < S::T / 64; ++i) total += red[w0 + i];
+    }
+    row_loss[row] = total;
+  }
+  if (grad == nullptr) return;  // uniform across the workgroup
+  run_passes<S, 0, true>(a, lds, tw, t);
+  global_store_row<S>(a, grad + row * S::N, t, live);
+}
+
+template <class S>
+hipError_t launch_spectral_energy(const void* x, const float* w, const float* scale, void* grad,
+                                  float* row_loss, const void* tw, int64_t batch, hipStream_t s) {
+  const int64_t groups = (batch + S::TPB - 1) / S::TPB;
+  const int64_t cap = max_groups_per_launch();
+  for (int64_t g0 = 0; g0 < groups; g0 += cap) {
+    const int64_t g = groups - g0 < cap ? groups - g0 : cap;
+    const int64_t r0 = g0 * S::TPB;
+    k_spectral_energy<S><<<dim3((unsigned)g), dim3(S::THREADS), 0, s>>>(
+        static_cast<const c32*>(x) + r0 * S::N, w, scale,
+        grad ? static_cast<c32*>(grad) + r0 * S::N : nullptr, row_loss + r0,
+        static_cast<const c32*>(tw), batch - r0);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------- matched filter
+// Range compression (the paper's future work on SAR pipeline fusion):
+// out = (1/N) F^H(conj(h) .* F x) in one kernel.
+template <class S>
+__global__ __launch_bounds__(S::THREADS) void k_matched_filter(const c32* x, const c32* __restrict__ h,
+                                                               c32* out, const c32* __restrict__ tw,
+                                                               int64_t rows) {
+  __shared__ c32 lds_all[S::TPB * S::LDS_ELEMS];
+  const int tid = threadIdx.x;
+  const int slot = tid / S::T;
+  const int t = tid - slot * S::T;
+  const int64_t row = (int64_t)blockIdx.x * S::TPB + slot;
+  const bool live = row < rows;
+  c32* lds = lds_all + slot * S::LDS_ELEMS;
+  c32 a[S::E];
+  global_load_row<S>(a, x + row * S::N, t, live);
+  run_passes<S, 0, false>(a, lds, tw, t);
+  constexpr float inv_n = 1.0f / float(S::N);  // a power of two: exact
+#pragma unroll
+  for (int m = 0; m < S::E; ++m) {
+    const c32 hq = h[t + m * S::T];
+    const c32 y = cmulc(a[m], hq);
+    a[m] = c32{y.x * inv_n, y.y * inv_n};
+  }
+  __syncthreads();
+  run_passes<S, 0, true>(a, lds, tw, t);
+  global_store_row<S>(a, out + row * S::N, t, live);
+}
+
+template <class S>
+hipError_t launch_matched_filter(const void* x, const void* h, void* out, const void* tw,
+                                 int64_t batch, hipStream_t s) {
+  const int64_t groups = (batch + S::TPB - 1) / S::TPB;
+  const int64_t cap = max_groups_per_launch();
+  for (int64_t g0 = 0; g0 < groups; g0 += cap) {
+    const int64_t g = groups - g0 < cap ? groups - g0 : cap;
+    const int64_t r0 = g0 * S::TPB;
+    k_matched_filter<S><<<dim3((unsigned)g), dim3(S::THREADS), 0, s>>>(
+        static_cast<const c32*>(x) + r0 * S::N, static_cast<const c32*>(h),
+        static_cast<c32*>(out) + r0 * S::N, static_cast<const c32*>(tw), batch - r0);
+  }
+  return hipGetLastError();
+}
+
+// -------------------------------------------------------------- four-step
+// The paper's eq. (3) order: length-N2 sub-transforms of the N1 decimated
+// sequences x[n1 + N1 m] (stage 1), then twiddle W_N^{n1 k2} and length-N1
+// DFTs across the sub-transforms, stored at k2 + N2 k1 (stage 2).  The
+// intermediate goes through device memory.
+//
+// Stage 1 mapping is XCD-aware: the workgroups are dealt round-robin to the 8
+// XCDs, so block i serves row 8 (i div 8N1) + (i mod 8) and sub-sequence
+// (i mod 8N1) div 8; all N1 readers of one row then share one L2, which
+// absorbs the stride-N1 reads.
+constexpr int kXcds = 8;
+
+template <class S, int N1, bool INV>
+__global__ __launch_bounds__(S::THREADS) void k_four_step_columns(const c32* x, c32* y,
+                                                                  const c32* __restrict__ tw,
+                                                                  int64_t rows) {
+  static_assert(S::TPB == 1, "four-step sub-transforms use one transform per workgroup");
+  __shared__ c32 lds[S::LDS_ELEMS];
+  const int64_t i = blockIdx.x;
+  const int64_t grp = i / (kXcds * N1);
+  const int r = (int)(i - grp * kXcds * N1);
+  const int n1 = r / kXcds;
+  const int64_t row = grp * kXcds + (r - n1 * kXcds);
+  if (row >= rows) return;  // whole workgroup, before any barrier
+  constexpr int N = S::N * N1;
+  const int t = threadIdx.x;
+  const c32* src = x + row * N + n1;
+  c32 a[S::E];
+#pragma unroll
+  for (int m = 0; m < S::E; ++m) a[m] = src[(int64_t)(t + m * S::T) * N1];
+  run_passes<S, 0, INV>(a, lds, tw, t);
+  global_store_row<S>(a, y + (row * N1 + n1) * S::N, t, true);
+}
+
+template <int N1, int N2, bool INV>
+__global__ __launch_bounds__(256) void k_four_step_combine(const c32* y, c32* out,
+                                                           const c32* __restrict__ tw4, int64_t rows) {
+  constexpr int N = N1 * N2;
+  const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t row = gid / N2;
+  const int k2 = (int)(gid - row * N2);
+  if (row >= rows) return;
+  const c32* src = y + row * N + k2;
+  c32 v[N1];
+  v[0] = src[0];
+#pragma unroll
+  for (int n1 = 1; n1 < N1; ++n1) v[n1] = ctw<INV>(src[(int64_t)n1 * N2], tw4[(n1 - 1) * N2 + k2]);
+  Dft<N1, INV>::run(v);
+  c32* dst = out + row * N + k2;
+#pragma unroll
+  for (int k1 = 0; k1 < N1; ++k1) dst[(int64_t)k1 * N2] = v[k1];
+}
+
+template <class S, int N1>
+hipError_t launch_four_step_columns(const void* x, void* y, const void* tw, int64_t batch,
+                                    bool inverse, hipStream_t s) {
+  // Rows are processed in chunks of kXcds * (max groups) so the block index fits.
+  const int64_t units = max_groups_per_launch() / (kXcds * N1);
+  const int64_t rows_per_launch = (units > 0 ? units : 1) * kXcds;
+  for (int64_t r0 = 0; r0 < batch; r0 += rows_per_launch) {
+    const int64_t rows = batch - r0 < rows_per_launch ? batch - r0 : rows_per_launch;
+    const int64_t blocks = ((rows + kXcds - 1) / kXcds) * kXcds * N1;
+    const c32* xp = static_cast<const c32*>(x) + r0 * S::N * N1;
+    c32* yp = static_cast<c32*>(y) + r0 * S::N * N1;
+    const c32* twp = static_cast<const c32*>(tw);
+    if (inverse)
+      k_four_step_columns<S, N1, true><<<dim3((unsigned)blocks), dim3(S::THREADS), 0, s>>>(xp, yp, twp, rows);
+    else
+      k_four_step_columns<S, N1, false><<<dim3((unsigned)blocks), dim3(S::THREADS), 0, s>>>(xp, yp, twp, rows);
+  }
+  return hipGetLastError();
+}
+
+template <int N1, int N2>
+hipError_t launch_four_step_combine(const void* y, void* out, const void* tw4, int64_t batch,
+                                    bool inverse, hipStream_t s) {
+  static_assert(N2 % 256 == 0, "combine blocks cover 256 consecutive k2");
+  const int64_t per = max_groups_per_launch() * 256 / N2;
+  const int64_t rows_per_launch = per > 0 ? per : 1;
+  for (int64_t r0 = 0; r0 < batch; r0 += rows_per_launch) {
+    const int64_t rows = batch - r0 < rows_per_launch ? batch - r0 : rows_per_launch;
+    const int64_t blocks = rows * N2 / 256;
+    const c32* yp = static_cast<const c32*>(y) + r0 * N1 * N2;
+    c32* op = static_cast<c32*>(out) + r0 * N1 * N2;
+    const c32* twp = static_cast<const c32*>(tw4);
+    if (inverse)
+      k_four_step_combine<N1, N2, true><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(yp, op, twp, rows);
+    else
+      k_four_step_combine<N1, N2, false><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(yp, op, twp, rows);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace stockfft

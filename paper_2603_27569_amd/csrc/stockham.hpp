@@ -1,0 +1,250 @@
+// Device building blocks of the Stockham autosort FFT for gfx950.
+//
+// Notation follows the paper (Section II): W_N = exp(-2 pi i / N); one
+// Stockham pass of radix R applies N/R butterflies; butterfly j reads its R
+// legs at j + r N/R, multiplies leg r by W_{Ns R}^{(j mod Ns) r} (Ns = product
+// of the radices of the earlier passes), takes a length-R DFT and writes leg
+// k to (j div Ns) Ns R + (j mod Ns) + k Ns.  After the last pass the output
+// is in natural order (Section II-B), with no bit reversal.
+//
+// Work split (the two-tier model of Section III-B, re-derived for gfx950):
+// a transform is owned by T lanes; each lane keeps E = N/T complex values in
+// VGPRs (tier 1) and does E/R butterflies per pass.  The LDS (tier 2) is only
+// an exchange buffer between passes: one buffer per transform, reused by
+// every pass (Section IV-A), with an optional pad of one element every
+// 2^PADLOG elements against bank conflicts.  The first pass reads global
+// memory straight into registers and the last pass writes global memory
+// straight from registers (the device-memory bypass of Section V-A).
+//
+// Register index convention: for every pass, lane t holds in a[m] the element
+// at position t + m T of the buffer being read, so leg r of the lane's b-th
+// butterfly (j = t + b T) is a[b + r E/R].  With this convention the global
+// load of the first pass and the global store of the last pass are both
+// a[m] <-> x[t + m T]: consecutive lanes touch consecutive 8-byte elements.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stockfft {
+
+// ------------------------------------------------------------------ complex
+
+struct c32 {
+  float x, y;
+};
+
+__device__ __forceinline__ c32 cadd(c32 a, c32 b) { return {a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ c32 csub(c32 a, c32 b) { return {a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ c32 cmul(c32 a, c32 w) {
+  return {a.x * w.x - a.y * w.y, a.x * w.y + a.y * w.x};
+}
+// a * conj(w)
+__device__ __forceinline__ c32 cmulc(c32 a, c32 w) {
+  return {a.x * w.x + a.y * w.y, a.y * w.x - a.x * w.y};
+}
+template <bool INV>
+__device__ __forceinline__ c32 ctw(c32 a, c32 w) {
+  if constexpr (INV) return cmulc(a, w);
+  else return cmul(a, w);
+}
+// multiply by -i (forward) or +i (backward): the root W_4^1 of the direction
+template <bool INV>
+__device__ __forceinline__ c32 mul_w4(c32 a) {
+  if constexpr (INV) return {-a.y, a.x};
+  else return {a.y, -a.x};
+}
+
+// cos/sin of k pi / 8, rounded once from their exact values.
+constexpr float kC1 = 0.923879532511286756128f;  // cos(pi/8)
+constexpr float kS1 = 0.382683432365089771728f;  // sin(pi/8)
+constexpr float kR2 = 0.707106781186547524401f;  // cos(pi/4)
+
+// v * W_R^k for the direction (W = e^{-2 pi i / R} forward, its conjugate
+// backward), with k and R compile-time; exact roots need no multiply.
+template <int R, int K, bool INV>
+__device__ __forceinline__ c32 mul_root(c32 v) {
+  constexpr int k16 = (K * 16 / R) & 15;  // the same root expressed in W_16
+  static_assert((K * 16) % R == 0, "roots beyond W_16 are not tabulated");
+  if constexpr (k16 == 0) {
+    return v;
+  } else if constexpr (k16 == 4) {
+    return mul_w4<INV>(v);
+  } else if constexpr (k16 == 8) {
+    return {-v.x, -v.y};
+  } else if constexpr (k16 == 12) {
+    return mul_w4<!INV>(v);
+  } else if constexpr (k16 == 2 || k16 == 6 || k16 == 10 || k16 == 14) {
+    // (+-r2, +-r2) roots: two multiplies.
+    constexpr float cr = (k16 == 2 || k16 == 14) ? kR2 : -kR2;
+    constexpr float si = (k16 == 2 || k16 == 6) ? -kR2 : kR2;  // forward sign
+    constexpr float s = INV ? -si : si;
+    return {cr * v.x - s * v.y, cr * v.y + s * v.x};
+  } else {
+    // odd multiples of pi/8
+    constexpr float c = (k16 == 1 || k16 == 15) ? kC1 : (k16 == 3 || k16 == 13) ? kS1
+                        : (k16 == 5 || k16 == 11) ? -kS1 : -kC1;
+    constexpr float sf = (k16 == 1 || k16 == 7) ? -kS1 : (k16 == 3 || k16 == 5) ? -kC1
+                         : (k16 == 9 || k16 == 15) ? kS1 : kC1;
+    constexpr float s = INV ? -sf : sf;
+    return {c * v.x - s * v.y, c * v.y + s * v.x};
+  }
+}
+
+// ---------------------------------------------------------------- DFT_R
+// In-register length-R DFT, R in {2, 4, 8, 16}, natural-order in and out,
+// by radix-2 decimation in time: DFT_R = combine(DFT_{R/2}(even),
+// W_R^k * DFT_{R/2}(odd)).  For R = 8 this is the split DIT butterfly of
+// Section V-B, eq. (4).
+
+template <int R, bool INV>
+struct Dft;
+
+template <bool INV>
+struct Dft<2, INV> {
+  __device__ __forceinline__ static void run(c32 (&v)[2]) {
+    c32 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  }
+};
+
+template <int R, bool INV>
+struct Dft {
+  template <int K>
+  __device__ __forceinline__ static void combine(c32 (&v)[R], const c32 (&e)[R / 2],
+                                                 const c32 (&o)[R / 2]) {
+    if constexpr (K < R / 2) {
+      c32 t = mul_root<R, K, INV>(o[K]);
+      v[K] = cadd(e[K], t);
+      v[K + R / 2] = csub(e[K], t);
+      combine<K + 1>(v, e, o);
+    }
+  }
+  __device__ __forceinline__ static void run(c32 (&v)[R]) {
+    c32 e[R / 2], o[R / 2];
+#pragma unroll
+    for (int i = 0; i < R / 2; ++i) {
+      e[i] = v[2 * i];
+      o[i] = v[2 * i + 1];
+    }
+    Dft<R / 2, INV>::run(e);
+    Dft<R / 2, INV>::run(o);
+    combine<0>(v, e, o);
+  }
+};
+
+// ------------------------------------------------------------- plan shape
+
+template <int... Rs>
+struct RadixList {
+  static constexpr int P = sizeof...(Rs);
+  static constexpr int r[P] = {Rs...};
+};
+
+// N points, E values per lane, TPB transforms per workgroup, LDS pad of one
+// element every 2^PADLOG (0 = no pad), radices of the passes in order.
+template <int N_, int E_, int TPB_, int PADLOG_, int... Rs>
+struct Shape {
+  using L = RadixList<Rs...>;
+  static constexpr int N = N_;
+  static constexpr int E = E_;
+  static constexpr int T = N_ / E_;
+  static constexpr int TPB = TPB_;
+  static constexpr int PADLOG = PADLOG_;
+  static constexpr int P = L::P;
+  static constexpr int THREADS = T * TPB;
+  static constexpr int LDS_ELEMS = N + (PADLOG ? (N >> PADLOG) : 0);
+  static constexpr int radix(int p) { return L::r[p]; }
+  static constexpr int ns(int p) {
+    int s = 1;
+    for (int i = 0; i < p; ++i) s *= L::r[i];
+    return s;
+  }
+  // Offset of pass p's table: entries [r-1][k], r in [1,R_p), k in [0,Ns_p).
+  static constexpr int tw_off(int p) {
+    int o = 0;
+    for (int i = 1; i < p; ++i) o += (L::r[i] - 1) * ns(i);
+    return o;
+  }
+  static constexpr int TW_ELEMS = tw_off(P);
+  static constexpr bool valid() {
+    if (ns(P) != N || T * E != N || THREADS > 1024 || THREADS < 1) return false;
+    for (int i = 0; i < P; ++i)
+      if (E % L::r[i] != 0) return false;
+    return true;
+  }
+  static_assert(valid(), "inconsistent Stockham shape");
+  __device__ __forceinline__ static int pidx(int i) {
+    if constexpr (PADLOG > 0) return i + (i >> PADLOG);
+    else return i;
+  }
+};
+
+// ------------------------------------------------------------ one pass
+
+// Twiddle + butterflies of pass p on the lane's registers.
+template <class S, int p, bool INV>
+__device__ __forceinline__ void pass_compute(c32 (&a)[S::E], const c32* __restrict__ tw, int t) {
+  constexpr int R = S::radix(p);
+  constexpr int NS = S::ns(p);
+  constexpr int BPT = S::E / R;
+  if constexpr (NS > 1) {
+    const c32* twp = tw + S::tw_off(p);
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+      const int k = (t + b * S::T) & (NS - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r) a[b + r * BPT] = ctw<INV>(a[b + r * BPT], twp[(r - 1) * NS + k]);
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    c32 v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[r] = a[b + r * BPT];
+    Dft<R, INV>::run(v);
+#pragma unroll
+    for (int r = 0; r < R; ++r) a[b + r * BPT] = v[r];
+  }
+}
+
+// Write pass p's outputs into the exchange buffer at the Stockham positions.
+template <class S, int p>
+__device__ __forceinline__ void pass_store_lds(const c32 (&a)[S::E], c32* lds, int t) {
+  constexpr int R = S::radix(p);
+  constexpr int NS = S::ns(p);
+  constexpr int BPT = S::E / R;
+#pragma unroll
+  for (int b = 0; b < BPT; ++b) {
+    const int j = t + b * S::T;
+    const int base = (j / NS) * NS * R + (j & (NS - 1));
+#pragma unroll
+    for (int k = 0; k < R; ++k) lds[S::pidx(base + k * NS)] = a[b + k * BPT];
+  }
+}
+
+template <class S>
+__device__ __forceinline__ void lds_load_all(c32 (&a)[S::E], const c32* lds, int t) {
+#pragma unroll
+  for (int m = 0; m < S::E; ++m) a[m] = lds[S::pidx(t + m * S::T)];
+}
+
+// Runs passes p..P-1.  On entry a[] holds the pass-p inputs in the register
+// convention.  On exit a[] holds the transform in natural order, a[m] at
+// position t + m T.  Between passes the data goes through lds, which must be
+// free to overwrite on entry (the caller's barrier).
+template <class S, int p, bool INV>
+__device__ __forceinline__ void run_passes(c32 (&a)[S::E], c32* lds, const c32* __restrict__ tw,
+                                           int t) {
+  pass_compute<S, p, INV>(a, tw, t);
+  if constexpr (p + 1 < S::P) {
+    pass_store_lds<S, p>(a, lds, t);
+    __syncthreads();
+    lds_load_all<S>(a, lds, t);
+    if constexpr (p + 2 < S::P) __syncthreads();  // all reads done before the next overwrite
+    run_passes<S, p + 1, INV>(a, lds, tw, t);
+  }
+}
+
+}  // namespace stockfft

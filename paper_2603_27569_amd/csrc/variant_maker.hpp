@@ -1,0 +1,38 @@
+// Builds SingleVariant table entries from Stockham shapes.
+#pragma once
+
+#include "kernels.hpp"
+
+namespace stockfft {
+
+template <class S>
+SingleVariant make_variant(const char* name) {
+  SingleVariant v{};
+  v.name = name;
+  v.n = S::N;
+  v.e = S::E;
+  v.t = S::T;
+  v.tpb = S::TPB;
+  v.padlog = S::PADLOG;
+  v.npass = S::P;
+  for (int i = 0; i < S::P; ++i) v.radix[i] = S::radix(i);
+  v.threads = S::THREADS;
+  v.lds_bytes = S::TPB * S::LDS_ELEMS * (int)sizeof(c32);
+  v.tw_elems = S::TW_ELEMS;
+  v.launch = &launch_single<S>;
+  v.fused = &launch_spectral_energy<S>;
+  v.filter = &launch_matched_filter<S>;
+  return v;
+}
+
+}  // namespace stockfft
+
+// Each size group exports its entries through one accessor.
+#define STOCKFFT_VARIANT_GROUP(FN, ...)                                   \
+  namespace stockfft {                                                    \
+  const SingleVariant* FN(int* count) {                                   \
+    static const SingleVariant table[] = {__VA_ARGS__};                   \
+    *count = (int)(sizeof(table) / sizeof(table[0]));                     \
+    return table;                                                         \
+  }                                                                       \
+  }

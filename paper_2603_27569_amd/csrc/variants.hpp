@@ -1,0 +1,66 @@
+// Host-visible description of every compiled kernel variant.
+//
+// A single-pass variant is one Stockham shape (N, values per lane E, lanes per
+// transform T = N/E, transforms per workgroup, LDS pad, radix sequence)
+// compiled for both directions.  The planner and the autotuner pick among
+// them per size; the four-step, fused and ragged paths reuse the same shapes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stockfft {
+
+constexpr int kMaxPasses = 8;
+
+// Grids larger than this many workgroups are split into several launches.
+constexpr int64_t kDefaultMaxGroupsPerLaunch = int64_t(1) << 20;
+int64_t max_groups_per_launch();
+void set_max_groups_per_launch(int64_t groups);
+
+using LaunchFn = hipError_t (*)(const void* in, void* out, const void* tw, int64_t batch,
+                                bool inverse, hipStream_t s);
+
+// Fused forward -> weight -> adjoint: grad = scale * F^H(2 w^2 .* F x) and
+// row_loss[b] = sum_k w_k^2 |(F x_b)[k]|^2.  grad may be null (loss only).
+using FusedFn = hipError_t (*)(const void* x, const float* w, const float* scale, void* grad,
+                               float* row_loss, const void* tw, int64_t batch, hipStream_t s);
+
+// Fused matched filter: out = (1/N) F^H(conj(h) .* F x).
+using FilterFn = hipError_t (*)(const void* x, const void* h, void* out, const void* tw,
+                                int64_t batch, hipStream_t s);
+
+struct SingleVariant {
+  const char* name;
+  int n, e, t, tpb, padlog, npass;
+  int radix[kMaxPasses];
+  int threads;
+  int lds_bytes;
+  int tw_elems;
+  LaunchFn launch;
+  FusedFn fused;     // null when not compiled for this variant
+  FilterFn filter;   // null when not compiled for this variant
+};
+
+extern const SingleVariant kSingleVariants[];
+extern const int kNumSingleVariants;
+
+// Four-step second stage: Z[b][k2 + N2 k1] = sum_{n1} W_N1^{n1 k1} W_N^{n1 k2} Y[b][n1][k2]
+using FourStepCombineFn = hipError_t (*)(const void* y, void* out, const void* tw4, int64_t batch,
+                                         bool inverse, hipStream_t s);
+// Four-step first stage: Y[b][n1][.] = FFT_N2(x[b][n1 + N1 m], m = 0..N2-1)
+using FourStepColumnsFn = hipError_t (*)(const void* x, void* y, const void* tw, int64_t batch,
+                                         bool inverse, hipStream_t s);
+
+struct FourStepVariant {
+  const char* name;
+  int n, n1, n2;
+  const char* sub_name;  // single-pass shape of the length-N2 sub-transforms
+  int tw_sub_elems;
+  FourStepColumnsFn columns;
+  FourStepCombineFn combine;
+};
+
+const FourStepVariant* four_step_variants(int* count);
+
+}  // namespace stockfft

@@ -1,0 +1,16 @@
+// Single-pass shapes for N = 4096: the paper's radix-4 (1024 lanes) and
+// radix-8 (512 lanes) designs, the radix-16 re-derivation for gfx950's
+// larger register file, and the LDS-layout ablation (no pad / 1 in 16 / 1 in 32).
+#include "variant_maker.hpp"
+
+using stockfft::Shape;
+using stockfft::make_variant;
+
+STOCKFFT_VARIANT_GROUP(variants_4096,
+  make_variant<Shape<4096, 4, 1, 4, 4, 4, 4, 4, 4, 4>>("n4096_e4_b1_p4_r4.4.4.4.4.4"),
+  make_variant<Shape<4096, 8, 1, 4, 8, 8, 8, 8>>("n4096_e8_b1_p4_r8.8.8.8"),
+  make_variant<Shape<4096, 16, 1, 4, 16, 16, 16>>("n4096_e16_b1_p4_r16.16.16"),
+  make_variant<Shape<4096, 16, 1, 0, 16, 16, 16>>("n4096_e16_b1_p0_r16.16.16"),
+  make_variant<Shape<4096, 16, 1, 5, 16, 16, 16>>("n4096_e16_b1_p5_r16.16.16"),
+  make_variant<Shape<4096, 32, 1, 4, 16, 16, 16>>("n4096_e32_b1_p4_r16.16.16"),
+  make_variant<Shape<4096, 32, 2, 4, 16, 16, 16>>("n4096_e32_b2_p4_r16.16.16"))

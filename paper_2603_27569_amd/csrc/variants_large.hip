@@ -1,0 +1,14 @@
+// Single-pass shapes for N = 8192 and 16384.  gfx950's 160 KiB LDS holds a
+// whole 16384-point complex64 transform (128 KiB + pad), so these sizes need
+// no device-memory exchange at all; the four-step path is kept beside them.
+#include "variant_maker.hpp"
+
+using stockfft::Shape;
+using stockfft::make_variant;
+
+STOCKFFT_VARIANT_GROUP(variants_large,
+  make_variant<Shape<8192, 8, 1, 4, 8, 8, 8, 8, 2>>("n8192_e8_b1_p4_r8.8.8.8.2"),
+  make_variant<Shape<8192, 16, 1, 4, 16, 16, 16, 2>>("n8192_e16_b1_p4_r16.16.16.2"),
+  make_variant<Shape<8192, 32, 1, 4, 16, 16, 16, 2>>("n8192_e32_b1_p4_r16.16.16.2"),
+  make_variant<Shape<16384, 16, 1, 4, 16, 16, 16, 4>>("n16384_e16_b1_p4_r16.16.16.4"),
+  make_variant<Shape<16384, 32, 1, 4, 16, 16, 16, 4>>("n16384_e32_b1_p4_r16.16.16.4"))

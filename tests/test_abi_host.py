@@ -1,0 +1,241 @@
+"""Host-side checks of the C ABI: exported symbols, argument validation
+(returned before any HIP call), twiddle tables and plan structure.  These
+run without a GPU."""
+import ctypes
+import json
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_2603_27569_amd as sf
+from paper_2603_27569_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "stockfft.h")
+GOLDEN = os.path.join(ROOT, "tests", "golden", "paper_tables.json")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fft_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    # the binding declares exactly the header's entry points
+    assert sorted(_lib.SIGNATURES) == names
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r" T (fft_[a-z_]+)$", out, flags=re.M))
+    assert set(names) <= exported
+
+
+def test_status_strings_and_version():
+    for code in range(13):
+        assert sf.fft_status_string(code)
+    assert sf.fft_version() >= 10000
+
+
+def _plan_rc(n, batch, direction, algo=0, variant=None, null_out=False):
+    h = ctypes.c_void_p(12345)
+    ptr = None if null_out else ctypes.byref(h)
+    rc = _lib.lib().fft_plan_config(ptr, n, batch, direction, algo,
+                                    variant.encode() if variant else None)
+    return rc, h.value
+
+
+@pytest.mark.parametrize("n", [0, 1, 128, 255, 257, 3000, 32768, -4096])
+def test_invalid_size_rejected_before_device(n):
+    rc, h = _plan_rc(n, 1, -1)
+    assert rc == _lib.CODES["FFT_INVALID_SIZE"] and h is None
+
+
+@pytest.mark.parametrize("batch", [0, -1, 2 ** 62])
+def test_invalid_batch(batch):
+    rc, h = _plan_rc(4096, batch, -1)
+    assert rc == _lib.CODES["FFT_INVALID_BATCH"] and h is None
+
+
+@pytest.mark.parametrize("d", [0, 2, -2])
+def test_invalid_direction(d):
+    assert _plan_rc(4096, 1, d)[0] == _lib.CODES["FFT_INVALID_DIRECTION"]
+
+
+def test_invalid_algorithm_and_variant_names():
+    assert _plan_rc(4096, 1, -1, algo=7)[0] == _lib.CODES["FFT_INVALID_ARGUMENT"]
+    assert _plan_rc(4096, 1, -1, variant="nope")[0] == _lib.CODES["FFT_INVALID_ARGUMENT"]
+    assert _plan_rc(4096, 1, -1, variant="n256_e16_b16_p4_r16.16")[0] == _lib.CODES["FFT_INVALID_ARGUMENT"]
+    assert _plan_rc(4096, 1, -1, algo=2)[0] == _lib.CODES["FFT_UNSUPPORTED"]
+    assert _plan_rc(4096, 1, -1, null_out=True)[0] == _lib.CODES["FFT_INVALID_POINTER"]
+
+
+def test_exec_and_destroy_reject_bad_handles():
+    L = _lib.lib()
+    assert L.fft_exec(None, None, None, None) == _lib.CODES["FFT_INVALID_PLAN"]
+    assert L.fft_exec(ctypes.c_void_p(0xdead0), None, None, None) == _lib.CODES["FFT_INVALID_PLAN"]
+    assert L.fft_destroy(None) == 0
+    assert L.fft_destroy(ctypes.c_void_p(0xdead0)) == _lib.CODES["FFT_INVALID_PLAN"]
+    assert L.fft_exec_spectral_energy(None, None, None, None, None, None, None, None) == \
+        _lib.CODES["FFT_INVALID_PLAN"]
+    assert L.fft_exec_matched_filter(None, None, None, None, None) == _lib.CODES["FFT_INVALID_PLAN"]
+    assert L.fft_exec_ragged(None, None, None, None) == _lib.CODES["FFT_INVALID_PLAN"]
+    assert L.fft_destroy_ragged(None) == 0
+
+
+def test_ragged_plan_validation():
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    arr = (ctypes.c_int64 * 3)(256, 1000, 4096)
+    assert L.fft_plan_ragged(ctypes.byref(h), arr, 3, -1) == _lib.CODES["FFT_INVALID_SIZE"]
+    arr = (ctypes.c_int64 * 2)(256, 4096)
+    assert L.fft_plan_ragged(ctypes.byref(h), arr, 0, -1) == _lib.CODES["FFT_INVALID_BATCH"]
+    assert L.fft_plan_ragged(ctypes.byref(h), arr, 2, 5) == _lib.CODES["FFT_INVALID_DIRECTION"]
+    assert L.fft_plan_ragged(ctypes.byref(h), None, 2, -1) == _lib.CODES["FFT_INVALID_POINTER"]
+    assert L.fft_plan_ragged(None, arr, 2, -1) == _lib.CODES["FFT_INVALID_POINTER"]
+
+
+def test_no_device_reported_cleanly():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a device is present")
+    except Exception:
+        pass
+    rc, h = _plan_rc(4096, 8, -1)
+    assert rc == _lib.CODES["FFT_NO_DEVICE"] and h is None
+
+
+# ---------------------------------------------------------------- variants
+
+def _variants():
+    return sf.variants()
+
+
+def test_variant_inventory():
+    vs = _variants()
+    singles = [v for v in vs if v["kind"] == "single"]
+    fours = [v for v in vs if v["kind"] == "four_step"]
+    assert {v["n"] for v in singles} == {256, 512, 1024, 2048, 4096, 8192, 16384}
+    assert {v["n"] for v in fours} == {8192, 16384}
+    names = [v["name"] for v in vs]
+    assert len(set(names)) == len(names)
+    for v in singles:
+        assert int(np.prod(v["radices"])) == v["n"]
+        assert v["lanes_per_transform"] * v["values_per_lane"] == v["n"]
+        assert all(v["values_per_lane"] % r == 0 for r in v["radices"])
+        assert v["threads"] == v["lanes_per_transform"] * v["transforms_per_workgroup"] <= 1024
+        pad = (v["n"] >> v["pad_log2"]) if v["pad_log2"] else 0
+        assert v["lds_bytes"] == v["transforms_per_workgroup"] * (v["n"] + pad) * 8
+        assert v["lds_bytes"] <= 160 * 1024  # gfx950 LDS per workgroup
+        assert v["barriers"] == (2 * v["passes"] - 3 if v["passes"] > 1 else 0)
+
+
+def test_paper_table_v_radix4_shapes():
+    """The radix-4 variants are the paper's Table V kernels: N/4 lanes, the
+    printed pass counts, and the printed exchange-buffer size."""
+    g = json.load(open(GOLDEN))["table_v_multisize_radix4"]["rows"]
+    by_n = {v["n"]: v for v in _variants() if v["kind"] == "single" and v["values_per_lane"] == 4}
+    for row in g:
+        v = by_n[row["n"]]
+        assert v["lanes_per_transform"] == row["threads"]
+        assert v["radices"].count(4) == row["radix4_passes"]
+        assert v["radices"].count(2) == row["radix2_tail"]
+        assert v["n"] * 8 == row["tg_kib"] * 1024
+
+
+def test_paper_table_iv_stage_counts():
+    """Stages at N=4096 per radix (Table IV); our barrier count is one fewer
+    than the paper's 2(stages-1) because the first exchange write needs no
+    preceding barrier."""
+    g = json.load(open(GOLDEN))["table_iv_radix_analysis_n4096"]["rows"]
+    by_r = {}
+    for v in _variants():
+        if v["kind"] == "single" and v["n"] == 4096 and len(set(v["radices"])) == 1:
+            by_r.setdefault(v["radices"][0], v)
+    for row in g:
+        if row["radix"] not in by_r:
+            continue
+        v = by_r[row["radix"]]
+        assert v["passes"] == row["stages"]
+        assert v["barriers"] == row["barriers"] - 1
+    assert {4, 8, 16} <= set(by_r)
+
+
+def test_paper_four_step_splits_present():
+    g = json.load(open(GOLDEN))["four_step_splits"]["rows"]
+    fours = {(v["n"], v["n1"], v["n2"]) for v in _variants() if v["kind"] == "four_step"}
+    for row in g:
+        assert (row["n"], row["n1"], row["n2"]) in fours
+
+
+def _exact_roots(m, L):
+    return np.exp(-2j * np.pi * m / L)
+
+
+def _ulp_err(tab, exact):
+    exact = np.asarray(exact)
+    er = np.abs(tab.real.astype(np.float64) - exact.real)
+    ei = np.abs(tab.imag.astype(np.float64) - exact.imag)
+    ur = np.spacing(np.abs(exact.real).astype(np.float32)).astype(np.float64)
+    ui = np.spacing(np.abs(exact.imag).astype(np.float32)).astype(np.float64)
+    return max(np.max(er / ur), np.max(ei / ui))
+
+
+def test_twiddle_tables_rounded_once_from_fp64():
+    """Every table entry is W_L^m rounded once to FP32: within half an ulp of
+    the exact root (plus FP64 evaluation slack)."""
+    vs = _variants()
+    for i, v in enumerate(vs):
+        tab = sf.fft_variant_twiddles(i)
+        if v["kind"] == "single":
+            radices = v["radices"]
+            sub = None
+        else:
+            sub = next(s for s in vs if s["name"] == v["sub_variant"])
+            radices = sub["radices"]
+        expect = []
+        ns = radices[0]
+        for r_p in radices[1:]:
+            L = ns * r_p
+            for r in range(1, r_p):
+                for k in range(ns):
+                    expect.append(_exact_roots(k * r, L))
+            ns *= r_p
+        if v["kind"] == "four_step":
+            N = v["n"]
+            for n1 in range(1, v["n1"]):
+                for k2 in range(v["n2"]):
+                    expect.append(_exact_roots(n1 * k2, N))
+        expect = np.array(expect)
+        assert tab.shape == expect.shape, v["name"]
+        assert _ulp_err(tab, expect) <= 0.5 + 1e-6, v["name"]
+
+
+def test_tune_table_set_query_load(tmp_path):
+    sf.fft_tune_clear()
+    try:
+        assert sf.fft_tune_query(4096, 256) == "n4096_e16_b1_p4_r16.16.16"
+        sf.fft_tune_set(4096, 1, 100, "n4096_e8_b1_p4_r8.8.8.8")
+        assert sf.fft_tune_query(4096, 50) == "n4096_e8_b1_p4_r8.8.8.8"
+        assert sf.fft_tune_query(4096, 256) == "n4096_e16_b1_p4_r16.16.16"
+        with pytest.raises(sf.StockfftError):
+            sf.fft_tune_set(4096, 1, 10, "n256_e16_b16_p4_r16.16")
+        p = tmp_path / "tune.json"
+        p.write_text(json.dumps({"arch": "gfx950", "entries": [
+            {"n": 2048, "batch_min": 1, "batch_max": 10 ** 9, "variant": "n2048_e8_b1_p4_r8.8.8.4"},
+            {"n": 2048, "batch_min": 1, "batch_max": 10, "variant": "bogus"}]}))
+        sf.fft_tune_load(str(p))
+        assert sf.fft_tune_query(2048, 5) == "n2048_e8_b1_p4_r8.8.8.4"
+        with pytest.raises(sf.StockfftError):
+            sf.fft_tune_load(str(tmp_path / "missing.json"))
+        assert sf.fft_tune_query(2048, 5) == "n2048_e8_b1_p4_r8.8.8.4"
+    finally:
+        sf.fft_tune_clear()

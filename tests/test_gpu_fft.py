@@ -1,0 +1,247 @@
+"""GPU parity of the HIP path against the FP64 oracle.
+
+Every case runs the library through its C ABI (via the Python binding) on
+seeded inputs and compares element by element with the oracle on the same
+complex64 values.  Gates (per row, worst row decides): relative RMS error
+<= 5e-6 and max abs error <= 1e-5 * ||x_b||_2.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2603_27569_amd as sf
+from paper_2603_27569_amd import metrics, workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+def _gpu(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def _host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _check(y, x, inverse=False, ref=None):
+    if ref is None:
+        ref = oracle.fft(x, inverse=inverse)
+    ok, worst, med, ab = metrics.gate(y, ref, x)
+    assert ok, f"rel-RMS worst {worst:.3e} median {med:.3e} max-abs/||x|| {ab:.3e}"
+    return worst
+
+
+SINGLE = [v for v in sf.variants() if v["kind"] == "single"]
+FOUR = [v for v in sf.variants() if v["kind"] == "four_step"]
+
+
+@pytest.mark.parametrize("v", SINGLE, ids=[v["name"] for v in SINGLE])
+@pytest.mark.parametrize("inverse", [False, True], ids=["fwd", "bwd"])
+def test_single_pass_variant_parity(v, inverse):
+    n = v["n"]
+    batch = 3 * v["transforms_per_workgroup"] + 1  # a ragged last workgroup
+    x = workloads.plain_uniform(n, batch, seed=n + batch)
+    y = sf.fft(_gpu(x), inverse=inverse, algorithm=sf.FFT_ALGO_SINGLE_PASS, variant=v["name"])
+    worst = _check(_host(y), x, inverse)
+    assert worst < 2e-6  # a healthy FP32 Stockham sits near 1e-7
+
+
+@pytest.mark.parametrize("v", FOUR, ids=[v["name"] for v in FOUR])
+@pytest.mark.parametrize("inverse", [False, True], ids=["fwd", "bwd"])
+def test_four_step_variant_parity(v, inverse):
+    n = v["n"]
+    batch = 13  # not a multiple of the 8-row XCD group
+    x = workloads.plain_normal(n, batch, seed=n + 7)
+    y = sf.fft(_gpu(x), inverse=inverse, algorithm=sf.FFT_ALGO_FOUR_STEP, variant=v["name"])
+    _check(_host(y), x, inverse)
+
+
+def test_plain_uniform_n256_delta_tone():
+    n, b = 256, 64
+    x = workloads.plain_uniform(n, b)
+    _check(_host(sf.fft(_gpu(x))), x)
+    d = workloads.delta_batch(n, b)
+    y = _host(sf.fft(_gpu(d)))
+    k = np.arange(n)
+    for r in range(b):
+        n0 = r % n
+        exact = np.exp(-2j * np.pi * ((n0 * k) % n) / n)
+        assert np.max(np.abs(y[r] - exact)) < 2e-6
+    t = workloads.tone_batch(n, b)
+    y = _host(sf.fft(_gpu(t)))
+    bins = workloads.tone_bins(n, b)
+    for r in range(b):
+        z = y[r].copy()
+        assert abs(z[bins[r]] - n) < 1e-3
+        z[bins[r]] = 0
+        assert np.max(np.abs(z)) < 1e-3
+    _check(y, t)
+
+
+@pytest.mark.parametrize("inverse", [False, True], ids=["fwd", "bwd"])
+def test_headline_n4096_b256(inverse):
+    x = workloads.plain_normal(4096, 256)
+    y = _host(sf.fft(_gpu(x), inverse=inverse))
+    worst = _check(y, x, inverse)
+    print(f"n4096 b256 inverse={inverse} worst rel-RMS {worst:.3e}", flush=True)
+
+
+@pytest.mark.parametrize("n", [8192, 16384])
+@pytest.mark.parametrize("algo", [sf.FFT_ALGO_SINGLE_PASS, sf.FFT_ALGO_FOUR_STEP], ids=["single", "fourstep"])
+def test_chirp_noise_b1024(n, algo):
+    x, _ = workloads.chirp_noise(n, 1024)
+    y = _host(sf.fft(_gpu(x), algorithm=algo))
+    worst = _check(y, x)
+    print(f"chirp n{n} algo={algo} worst rel-RMS {worst:.3e}", flush=True)
+
+
+@pytest.mark.parametrize("n", workloads.SIZES)
+def test_roundtrip_in_place_and_determinism(n):
+    x = workloads.plain_normal(n, 5, seed=3)
+    xt = _gpu(x)
+    y1 = sf.fft(xt)
+    y2 = sf.fft(xt)
+    assert torch.equal(y1, y2)  # bitwise run to run
+    back = _host(sf.fft(y1, inverse=True)) / n
+    assert np.max(np.abs(back - x)) < 1e-5 * np.max(np.abs(x)) * np.log2(n)
+    z = xt.clone()
+    sf.fft(z, out=z)  # in place
+    assert torch.equal(z, y1)
+
+
+@pytest.mark.parametrize("algo", [sf.FFT_ALGO_SINGLE_PASS, sf.FFT_ALGO_FOUR_STEP])
+def test_zero_rows_are_exact_zeros(algo):
+    x = np.zeros((9, 8192), np.complex64)
+    x[3] = workloads.plain_normal(8192, 1)[0]
+    y = _host(sf.fft(_gpu(x), algorithm=algo))
+    assert np.all(y[[0, 1, 2, 4, 5, 6, 7, 8]] == 0)
+    _check(y, x)
+
+
+def test_exec_pointer_errors():
+    n, b = 1024, 4
+    p = sf.Plan(n, b)
+    buf = torch.zeros(2 * n * b + 8, dtype=torch.complex64, device=DEV)
+    base = buf.data_ptr()
+    codes = sf.CODES
+    L = sf._lib.lib()
+    import ctypes
+    vp = ctypes.c_void_p
+    assert L.fft_exec(vp(p.handle), vp(base + 4), vp(base + 16 * n * b), None) == codes["FFT_MISALIGNED"]
+    assert L.fft_exec(vp(p.handle), vp(base), vp(base + 8), None) == codes["FFT_OVERLAP"]
+    assert L.fft_exec(vp(p.handle), None, vp(base), None) == codes["FFT_INVALID_POINTER"]
+    assert L.fft_exec(vp(p.handle), vp(base), vp(base + 8 * n * b), None) == 0  # adjacent is fine
+    h = p.handle
+    p.close()
+    assert L.fft_exec(vp(h), vp(base), vp(base), None) == codes["FFT_INVALID_PLAN"]
+    assert L.fft_destroy(vp(h)) == codes["FFT_INVALID_PLAN"]
+    torch.cuda.synchronize()
+
+
+def test_plan_describe_and_alloc_failure(monkeypatch):
+    p = sf.Plan(16384, 3, algorithm=sf.FFT_ALGO_FOUR_STEP)
+    d = p.describe()
+    assert d["algorithm"] == "four_step" and d["workspace_bytes"] == 16384 * 3 * 8
+    assert d["four_step"]["n1"] * d["four_step"]["n2"] == 16384
+    p.close()
+    monkeypatch.setenv("STOCKFFT_FAIL_ALLOC", "1")
+    with pytest.raises(sf.StockfftError) as e:
+        sf.Plan(4096, 3)
+    assert e.value.name == "FFT_ALLOC_FAILED"
+
+
+def test_launch_splitting_matches_single_grid():
+    try:
+        sf.fft_set_launch_limit(3)
+        for n, algo, b in [(256, sf.FFT_ALGO_SINGLE_PASS, 200), (8192, sf.FFT_ALGO_FOUR_STEP, 21)]:
+            x = workloads.plain_normal(n, b, seed=5)
+            sf.clear_plan_cache()
+            y = _host(sf.fft(_gpu(x), algorithm=algo))
+            _check(y, x)
+    finally:
+        sf.fft_set_launch_limit(0)
+        sf.clear_plan_cache()
+
+
+# ------------------------------------------------------------- fused paths
+
+def test_spectral_energy_fused_matches_oracle():
+    x, w = workloads.spectral_energy_inputs()
+    xt, wt = _gpu(x), _gpu(w)
+    total, rows, grad = sf.spectral_energy(xt, wt)
+    rows = _host(rows).astype(np.float64)
+    grad = _host(grad)
+    ref_rows, ref_grad = oracle.spectral_energy(x, w)
+    assert np.max(np.abs(rows - ref_rows) / ref_rows) <= 1e-5
+    assert abs(float(_host(total)[0]) - ref_rows.sum()) / ref_rows.sum() <= 1e-5
+    rel = np.linalg.norm(grad - ref_grad) / np.linalg.norm(ref_grad)
+    assert rel <= 1e-4, rel
+    ok, worst, _, _ = metrics.gate(grad, ref_grad, ref_grad)
+    print(f"spectral energy grad rel {rel:.3e} worst row rel-RMS {worst:.3e}", flush=True)
+    # Central differences on the FP64 oracle (exact: the loss is quadratic).
+    g = np.random.default_rng(0)
+    for _ in range(6):
+        b, i = int(g.integers(512)), int(g.integers(4096))
+        for comp in (1.0, 1j):
+            e = np.zeros((1, 4096), complex)
+            e[0, i] = comp
+            lp = oracle.spectral_energy(x[b:b + 1] + e, w)[0].sum()
+            lm = oracle.spectral_energy(x[b:b + 1] - e, w)[0].sum()
+            fd = (lp - lm) / 2.0
+            got = grad[b, i].real if comp == 1.0 else grad[b, i].imag
+            assert abs(got - fd) <= 1e-4 * np.max(np.abs(ref_grad[b])), (b, i, comp)
+
+
+def test_spectral_energy_loss_only_and_scale():
+    x, w = workloads.spectral_energy_inputs(n=1024, batch=40)
+    xt, wt = _gpu(x), _gpu(w)
+    t1, r1, g1 = sf.spectral_energy(xt, wt, want_grad=False)
+    assert g1 is None
+    t2, r2, g2 = sf.spectral_energy(xt, wt, grad_scale=torch.tensor([-0.5], device=DEV))
+    assert torch.equal(r1, r2)
+    _, ref = oracle.spectral_energy(x, w)
+    rel = np.linalg.norm(_host(g2) - (-0.5) * ref) / np.linalg.norm(0.5 * ref)
+    assert rel <= 1e-4
+
+
+def test_spectral_energy_unit_weight_closed_form():
+    n = 4096
+    x = workloads.plain_normal(n, 8, seed=9)
+    _, rows, grad = sf.spectral_energy(_gpu(x), torch.ones(n, device=DEV))
+    grad = _host(grad)
+    assert np.linalg.norm(grad - 2 * n * x) / np.linalg.norm(2 * n * x) <= 1e-5
+    rows = _host(rows)
+    ref = n * np.sum(np.abs(x.astype(np.complex128)) ** 2, axis=1)
+    assert np.max(np.abs(rows - ref) / ref) <= 1e-5
+
+
+def test_autograd_functions():
+    x, w = workloads.spectral_energy_inputs(n=2048, batch=16)
+    _, ref = oracle.spectral_energy(x, w)
+    xt = _gpu(x).requires_grad_(True)
+    wt = _gpu(w)
+    loss = sf.SpectralEnergyFunction.apply(xt, wt) * 3.0
+    loss.backward()
+    rel = np.linalg.norm(_host(xt.grad) - 3 * ref) / np.linalg.norm(3 * ref)
+    assert rel <= 1e-4, rel
+    # The same gradient through FFTFunction and plain torch elementwise ops.
+    xt2 = _gpu(x).requires_grad_(True)
+    y = sf.FFTFunction.apply(xt2)
+    l2 = (wt ** 2 * (y.real ** 2 + y.imag ** 2)).sum()
+    l2.backward()
+    rel2 = np.linalg.norm(_host(xt2.grad) - ref) / np.linalg.norm(ref)
+    assert rel2 <= 1e-4, rel2
+
+
+def test_matched_filter_matches_oracle():
+    n, b = 4096, 33
+    x = workloads.plain_normal(n, b, seed=12)
+    h = workloads.complex_normal((n,), seed=13)
+    y = _host(sf.matched_filter(_gpu(x), _gpu(h)))
+    ref = oracle.matched_filter(x, h)
+    _, worst, _, _ = metrics.gate(y, ref, x)
+    assert worst <= 5e-6, worst
