@@ -1,0 +1,410 @@
+"""Benchmark of the batched FP32 c2c FFT on one MI355X.
+
+Headline workload (one step): the forward and the backward transform of a
+batch of 256 rows of N = 4096 complex64 values (the paper's Table VI shape),
+inputs resident in HBM.  Throughput follows the paper's convention
+(Section VI-A): 5 N log2 N flops per transform; HBM traffic is counted
+algorithmically as 16 N bytes per transform (read + write, complex64).
+
+Timing: W untimed warmup steps, then K timed steps bracketed by device
+synchronisation, measured with HIP events recorded on the stream the
+kernels are launched on.  Every step uses the next slot of a ring of
+independent buffers whose total footprint exceeds 1 GiB, so the 256 MB
+Infinity Cache cannot serve the inputs from an earlier step.
+
+Beside the headline line the JSON carries: the roofline of the dominant
+kernel, the FP64 oracle timed on the host cores (a baseline, not a target),
+and the comparisons the paper's method implies (fused forward+adjoint vs
+the plain chain, ragged persistent launch vs per-size plain launches,
+four-step vs single-pass at 8192/16384, a same-footprint copy kernel).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-compare]
+                       [--skip-cpu] [--sweep]
+"""
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+N_HEAD, B_HEAD = 4096, 256
+RING_BYTES = 1 << 30
+HBM_PEAK_GBS = 8000.0
+PAPER_CONTEXT = {"gflops": 138.45, "us_per_fft": 1.78, "hardware": "Apple M1 GPU (8 cores)",
+                 "vendor_baseline_gflops": 107.0, "source": "Table VI"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_fft_n4096_b256.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2603_27569_amd", "csrc")
+    for f in ("stockham.hpp", "kernels.hpp", "variants_4096.hip"):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+class Timer:
+    """HIP events recorded on one stream around a block of launches."""
+
+    def __init__(self, torch, stream):
+        self.torch, self.stream = torch, stream
+
+    def run(self, fn, iters, warmup):
+        torch = self.torch
+        with torch.cuda.stream(self.stream):
+            for i in range(warmup):
+                fn(i)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(self.stream):
+            e0.record(self.stream)
+            for i in range(iters):
+                fn(warmup + i)
+            e1.record(self.stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e-3  # seconds
+
+
+def ring_count(bytes_per_slot):
+    return max(2, int(math.ceil(RING_BYTES / bytes_per_slot)))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--no-compare", action="store_true")
+    ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--sweep", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: the batched FFT shards by rows with no exchange, "
+              "and this build runs on a single MI355X; --gpus above 1 is not supported.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2603_27569_amd as sf
+    from paper_2603_27569_amd import metrics, workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.Stream()
+    cs = stream.cuda_stream
+    T = Timer(torch, stream)
+    props = torch.cuda.get_device_properties(dev)
+    log(f"device {props.name} {props.gcnArchName} CUs={props.multi_processor_count}")
+
+    # ------------------------------------------------------------ headline
+    n, b = N_HEAD, B_HEAD
+    slot_bytes = n * b * 8
+    K = ring_count(3 * slot_bytes)
+    x0 = torch.from_numpy(workloads.plain_normal(n, b)).to(dev)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1002)
+    xs = [x0] + [torch.randn(n * b, dtype=torch.complex64, device=dev, generator=gen).view(b, n)
+                 for _ in range(K - 1)]
+    ys = [torch.empty_like(x0) for _ in range(K)]
+    zs = [torch.empty_like(x0) for _ in range(K)]
+    fwd = sf.Plan(n, b, sf.FFT_FORWARD)
+    bwd = sf.Plan(n, b, sf.FFT_BACKWARD)
+    variant = fwd.describe()["variant"]["name"]
+    log(f"headline n={n} batch={b} variant={variant} ring={K} slots")
+
+    def step(i):
+        j = i % K
+        fwd.exec(xs[j].data_ptr(), ys[j].data_ptr(), cs)
+        bwd.exec(ys[j].data_ptr(), zs[j].data_ptr(), cs)
+
+    t_step = T.run(step, args.steps, args.warmup) / args.steps
+    t_fwd = T.run(lambda i: fwd.exec(xs[i % K].data_ptr(), ys[i % K].data_ptr(), cs),
+                  args.steps, args.warmup) / args.steps
+    t_bwd = T.run(lambda i: bwd.exec(ys[i % K].data_ptr(), zs[i % K].data_ptr(), cs),
+                  args.steps, args.warmup) / args.steps
+    flops_step = 2 * metrics.fft_flops(n, b)
+    bytes_launch = metrics.fft_bytes(n, b)
+    gflops = flops_step / t_step / 1e9
+    log(f"step {t_step * 1e6:.2f} us  fwd {t_fwd * 1e6:.2f} us  bwd {t_bwd * 1e6:.2f} us  "
+        f"{gflops:.0f} GFLOPS")
+
+    # accuracy of the timed path on slot 0 (forward) and its backward
+    torch.cuda.synchronize()
+    acc = {}
+    try:
+        import oracle
+        x_h = x0.cpu().numpy()
+        ref = oracle.fft(x_h)
+        ok, worst, med, ab = metrics.gate(ys[0].cpu().numpy(), ref, x_h)
+        okb, worstb, _, _ = metrics.gate(zs[0].cpu().numpy(), oracle.fft(ys[0].cpu().numpy(), inverse=True),
+                                         ys[0].cpu().numpy())
+        acc = {"forward_worst_rel_rms": worst, "forward_median_rel_rms": med,
+               "backward_worst_rel_rms": worstb, "gates_pass": bool(ok and okb)}
+    except Exception as e:  # the checker is optional for the measurement itself
+        acc = {"error": str(e)}
+
+    # -------------------------------------------------------------- roofline
+    t_kernel = (t_fwd + t_bwd) / 2
+    achieved = bytes_launch / t_kernel / 1e9
+    traffic = None
+    try:
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("source_hash") == kernel_source_hash() and tr.get("variant") == variant:
+            traffic = tr["bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        pass
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": f"k_stockham<{variant}>", "algorithmic_bytes_per_launch": bytes_launch,
+                "avg_launch_us": round(t_kernel * 1e6, 3)}
+
+    # ----------------------------------------------------- reference kernels
+    refs = {}
+    cp_src = [xs[j] for j in range(K)]
+    cp_dst = [ys[j] for j in range(K)]
+    t_copy = T.run(lambda i: cp_dst[i % K].copy_(cp_src[i % K]), args.steps, args.warmup) / args.steps
+    refs["device_copy_same_bytes"] = {"us": round(t_copy * 1e6, 3),
+                                      "GBs": round(bytes_launch / t_copy / 1e9, 1)}
+    tiny = torch.zeros(1, device=dev)
+    t_min = T.run(lambda i: tiny.add_(1.0), args.steps, args.warmup) / args.steps
+    refs["minimal_kernel_us"] = round(t_min * 1e6, 3)
+
+    # ------------------------------------------------------------ comparisons
+    comps = {}
+    if not args.no_compare:
+        comps = compare(args, torch, np, sf, metrics, workloads, T, dev, cs)
+    sweep = run_sweep(args, torch, sf, metrics, T, dev, cs) if args.sweep else None
+
+    # ------------------------------------------------------------ cpu baseline
+    cpu = None
+    if not args.skip_cpu:
+        import oracle
+        x_h = x0.cpu().numpy()
+        times = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            yh = oracle.fft(x_h)
+            oracle.fft(yh, inverse=True)
+            times.append(time.perf_counter() - t0)
+        tc = sorted(times)[1]
+        cpu = {"value": round(flops_step / tc / 1e9, 3), "unit": "GFLOPS",
+               "cores": oracle.max_threads(), "kind": "oracle",
+               "sample": f"one full step (forward + backward, {b} rows of N={n}), FP64, median of 3",
+               "seconds_per_step": round(tc, 4)}
+
+    out = {
+        "metric": "c2c FP32 FFT GFLOPS & %HBM peak, N=4096 b=256; ragged/fwd+bwd vs plain",
+        "value": round(gflops, 1),
+        "unit": "GFLOPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_step * 1e3, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "c2c fp32 fft forward+backward, n=4096, batch=256 (complex64 rows)",
+                   "n": n, "batch": b, "variant": variant, "ring_slots": K,
+                   "parallelism": "single gpu"},
+        "pct_hbm_peak": round(100 * 2 * bytes_launch / t_step / 1e9 / HBM_PEAK_GBS, 2),
+        "forward_us": round(t_fwd * 1e6, 3),
+        "backward_us": round(t_bwd * 1e6, 3),
+        "accuracy": acc,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "reference_kernels": refs,
+        "comparisons": comps,
+        "paper_context": PAPER_CONTEXT,
+    }
+    if sweep is not None:
+        out["sweep"] = sweep
+    print(json.dumps(out), flush=True)
+
+
+def compare(args, torch, np, sf, metrics, workloads, T, dev, cs):
+    import oracle
+    comps = {}
+    iters = max(20, args.steps // 5)
+    warm = max(5, args.warmup // 5)
+
+    # Fused forward -> weight -> adjoint (N=4096, batch 512) vs the plain chain.
+    n, b = 4096, 512
+    x_h, w_h = workloads.spectral_energy_inputs(n, b)
+    K = ring_count(2 * n * b * 8)
+    x0 = torch.from_numpy(x_h).to(dev)
+    w = torch.from_numpy(w_h).to(dev)
+    w2x2 = (2.0 * w * w).to(torch.complex64)
+    w2 = (w * w)
+    xs = [x0] + [torch.randn(b, n, dtype=torch.complex64, device=dev) for _ in range(K - 1)]
+    gs = [torch.empty_like(x0) for _ in range(K)]
+    ys = [torch.empty_like(x0) for _ in range(K)]
+    rows = torch.empty(b, device=dev)
+    total = torch.empty(1, device=dev)
+    pf = sf.Plan(n, b, sf.FFT_FORWARD, sf.FFT_ALGO_SINGLE_PASS)
+    pb = sf.Plan(n, b, sf.FFT_BACKWARD, sf.FFT_ALGO_SINGLE_PASS)
+
+    def fused(i):
+        j = i % K
+        sf.fft_exec_spectral_energy(pf.handle, xs[j].data_ptr(), w.data_ptr(), 0, gs[j].data_ptr(),
+                                    rows.data_ptr(), total.data_ptr(), cs)
+
+    def chain(i):
+        j = i % K
+        pf.exec(xs[j].data_ptr(), ys[j].data_ptr(), cs)
+        total.copy_(torch.sum(w2 * (ys[j].real ** 2 + ys[j].imag ** 2)).reshape(1))
+        ys[j].mul_(w2x2)
+        pb.exec(ys[j].data_ptr(), gs[j].data_ptr(), cs)
+
+    def launches_only(i):
+        j = i % K
+        pf.exec(xs[j].data_ptr(), ys[j].data_ptr(), cs)
+        pb.exec(ys[j].data_ptr(), gs[j].data_ptr(), cs)
+
+    t_fused = T.run(fused, iters, warm) / iters
+    g_fused = gs[0].cpu().numpy()
+    t_chain = T.run(chain, iters, warm) / iters
+    g_chain = gs[0].cpu().numpy()
+    t_two = T.run(launches_only, iters, warm) / iters
+    _, ref = oracle.spectral_energy(x_h, w_h)
+    rel_f = float(np.linalg.norm(g_fused - ref) / np.linalg.norm(ref))
+    rel_c = float(np.linalg.norm(g_chain - ref) / np.linalg.norm(ref))
+    comps["fused_forward_adjoint_n4096_b512"] = {
+        "fused_us": round(t_fused * 1e6, 3), "plain_chain_us": round(t_chain * 1e6, 3),
+        "two_launches_us": round(t_two * 1e6, 3),
+        "speedup_vs_chain": round(t_chain / t_fused, 3),
+        "speedup_vs_two_launches": round(t_two / t_fused, 3),
+        "fused_GBs_algorithmic": round(16 * n * b / t_fused / 1e9, 1),
+        "grad_rel_err_fused": rel_f, "grad_rel_err_chain": rel_c,
+        "equal_accuracy_gate": bool(rel_f <= 1e-4 and rel_c <= 1e-4)}
+    log("fused", comps["fused_forward_adjoint_n4096_b512"])
+    del xs, gs, ys
+
+    # Four-step vs single-pass at N=8192 / 16384, batch 1024.
+    for n in (8192, 16384):
+        b = 1024
+        x_h, _ = workloads.chirp_noise(n, b)
+        K = ring_count(2 * n * b * 8)
+        xs = [torch.from_numpy(x_h).to(dev)] + [torch.randn(b, n, dtype=torch.complex64, device=dev)
+                                                for _ in range(K - 1)]
+        ys = [torch.empty_like(xs[0]) for _ in range(K)]
+        rec = {}
+        for name, algo in (("single_pass", sf.FFT_ALGO_SINGLE_PASS), ("four_step", sf.FFT_ALGO_FOUR_STEP)):
+            p = sf.Plan(n, b, sf.FFT_FORWARD, algo)
+            t = T.run(lambda i: p.exec(xs[i % K].data_ptr(), ys[i % K].data_ptr(), cs), iters, warm) / iters
+            p.exec(xs[0].data_ptr(), ys[0].data_ptr(), cs)
+            torch.cuda.synchronize()
+            ok, worst, _, _ = metrics.gate(ys[0].cpu().numpy(), oracle.fft(x_h), x_h)
+            rec[name] = {"us": round(t * 1e6, 3), "GBs_algorithmic": round(16 * n * b / t / 1e9, 1),
+                         "gflops": round(metrics.gflops(n, b, t), 1), "worst_rel_rms": worst,
+                         "gates_pass": ok, "variant": p.describe().get("four_step", p.describe()["variant"])["name"]}
+            p.close()
+        comps[f"single_vs_four_step_n{n}_b{b}"] = rec
+        log(f"n{n}", rec)
+        del xs, ys
+
+    # Ragged persistent launch vs per-size plain launches.
+    try:
+        comps["ragged_2000"] = compare_ragged(args, torch, np, sf, metrics, workloads, T, dev, cs, iters, warm)
+        log("ragged", comps["ragged_2000"])
+    except sf.StockfftError as e:
+        comps["ragged_2000"] = {"error": str(e)}
+    return comps
+
+
+def compare_ragged(args, torch, np, sf, metrics, workloads, T, dev, cs, iters, warm):
+    import oracle
+    sizes, offs, data = workloads.ragged()
+    total = int(sizes.sum())
+    K = ring_count(2 * total * 8)
+    plan = sf.RaggedPlan(sizes)
+    xs = [torch.from_numpy(data).to(dev)] + [torch.randn(total, dtype=torch.complex64, device=dev)
+                                             for _ in range(K - 1)]
+    ys = [torch.empty_like(xs[0]) for _ in range(K)]
+    # grouped copies for the per-size comparator (its best case: contiguous rows)
+    order = [np.nonzero(sizes == s)[0] for s in workloads.SIZES]
+    gx = []
+    gy = []
+    for j in range(K):
+        ins = [torch.empty(len(idx) * s, dtype=torch.complex64, device=dev) if len(idx) else None
+               for idx, s in zip(order, workloads.SIZES)]
+        outs = [torch.empty_like(t) if t is not None else None for t in ins]
+        # gather each size's rows in plan order (device copies, done once)
+        for t, idx, s in zip(ins, order, workloads.SIZES):
+            if t is None:
+                continue
+            src = xs[j]
+            parts = [src[int(offs[i]):int(offs[i]) + int(s)] for i in idx]
+            t.copy_(torch.cat(parts))
+        gx.append(ins)
+        gy.append(outs)
+    t_r = T.run(lambda i: plan.exec(xs[i % K].data_ptr(), ys[i % K].data_ptr(), cs), iters, warm) / iters
+
+    def plain(i):
+        j = i % K
+        plan.exec_plain([t.data_ptr() if t is not None else 0 for t in gx[j]],
+                        [t.data_ptr() if t is not None else 0 for t in gy[j]], cs)
+
+    t_p = T.run(plain, iters, warm) / iters
+    torch.cuda.synchronize()
+    plan.exec(xs[0].data_ptr(), ys[0].data_ptr(), cs)
+    torch.cuda.synchronize()
+    y = ys[0].cpu().numpy()
+    worst = 0.0
+    ok = True
+    for s in workloads.SIZES:
+        idx = np.nonzero(sizes == s)[0]
+        xr = np.stack([data[offs[i]:offs[i] + s] for i in idx])
+        yr = np.stack([y[offs[i]:offs[i] + s] for i in idx])
+        g_ok, w_, _, _ = metrics.gate(yr, oracle.fft(xr), xr)
+        ok &= g_ok
+        worst = max(worst, w_)
+    flops = sum(metrics.fft_flops(int(s)) for s in sizes)
+    return {"transforms": int(len(sizes)), "elements": total,
+            "persistent_graph_us": round(t_r * 1e6, 3), "per_size_plain_us": round(t_p * 1e6, 3),
+            "speedup": round(t_p / t_r, 3), "persistent_GBs_algorithmic": round(16 * total / t_r / 1e9, 1),
+            "persistent_gflops": round(flops / t_r / 1e9, 1), "worst_rel_rms": worst, "gates_pass": bool(ok)}
+
+
+def run_sweep(args, torch, sf, metrics, T, dev, cs):
+    res = {"batch_n4096": [], "size_b1024": []}
+    iters = max(20, args.steps // 5)
+    for b in (1, 4, 16, 64, 128, 256, 512, 1024, 2048, 4096):
+        res["batch_n4096"].append(_time_plain(torch, sf, metrics, T, dev, cs, 4096, b, iters))
+    for n in (256, 512, 1024, 2048, 4096, 8192, 16384):
+        res["size_b1024"].append(_time_plain(torch, sf, metrics, T, dev, cs, n, 1024, iters))
+    return res
+
+
+def _time_plain(torch, sf, metrics, T, dev, cs, n, b, iters):
+    K = ring_count(2 * n * b * 8)
+    K = min(K, 4096)
+    xs = [torch.randn(b, n, dtype=torch.complex64, device=dev) for _ in range(K)]
+    ys = [torch.empty_like(xs[0]) for _ in range(K)]
+    p = sf.Plan(n, b, sf.FFT_FORWARD)
+    t = T.run(lambda i: p.exec(xs[i % K].data_ptr(), ys[i % K].data_ptr(), cs), iters, 10) / iters
+    rec = {"n": n, "batch": b, "us": round(t * 1e6, 3), "gflops": round(metrics.gflops(n, b, t), 1),
+           "pct_hbm": round(100 * 16 * n * b / t / 1e9 / HBM_PEAK_GBS, 2),
+           "variant": p.describe()["variant"]["name"]}
+    p.close()
+    return rec
+
+
+if __name__ == "__main__":
+    main()

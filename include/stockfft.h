@@ -183,6 +183,22 @@ int fft_exec_ragged_plain(fft_ragged_plan_t plan, const void *const *in_by_size,
 int fft_destroy_ragged(fft_ragged_plan_t plan);
 
 /*
+ * Ragged shapes.  Each size has one or more compiled shapes for the
+ * persistent kernel (radix of the passes, lanes per transform, transforms
+ * per task, hence the LDS tile); the autotuner picks one per size.
+ * fft_ragged_shapes: comma-separated shape names for length n, into buf.
+ * fft_tune_set_ragged: use `shape` for length n in ragged plans made later.
+ * fft_tune_query_ragged: the shape ragged plans would use for n, into buf.
+ * fft_tune_clear_ragged: back to the built-in shapes (radix 16 everywhere).
+ * Host only.  Errors: FFT_INVALID_POINTER, FFT_INVALID_SIZE,
+ * FFT_INVALID_ARGUMENT (unknown shape, shape for another length, small buffer).
+ */
+int fft_ragged_shapes(int64_t n, char *buf, int64_t cap);
+int fft_tune_set_ragged(int64_t n, const char *shape);
+int fft_tune_query_ragged(int64_t n, char *buf, int64_t cap);
+int fft_tune_clear_ragged(void);
+
+/*
  * Tuning.  fft_tune_load reads a JSON file written by the project's
  * autotuner: {"arch": "gfx950", "entries": [{"n": N, "batch_min": a,
  * "batch_max": b, "variant": "<name>"}, ...]}.  A missing or unreadable

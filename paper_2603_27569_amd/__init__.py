@@ -29,6 +29,7 @@ __all__ = [
     "fft_plan", "fft_plan_config", "fft_exec", "fft_destroy",
     "fft_exec_spectral_energy", "fft_exec_matched_filter",
     "fft_plan_ragged", "fft_exec_ragged", "fft_exec_ragged_plain", "fft_destroy_ragged",
+    "fft_ragged_shapes", "fft_tune_set_ragged", "fft_tune_query_ragged", "fft_tune_clear_ragged",
     "fft_tune_load", "fft_tune_set", "fft_tune_clear", "fft_tune_query",
     "fft_set_launch_limit",
     "fft_variant_count", "fft_variant_describe", "fft_variant_twiddles",
@@ -98,6 +99,26 @@ def fft_exec_ragged_plain(plan, in_by_size, out_by_size, stream=0):
 
 def fft_destroy_ragged(plan):
     return check("fft_destroy_ragged", lib().fft_destroy_ragged(_vp(plan)))
+
+
+def fft_ragged_shapes(n):
+    buf = ctypes.create_string_buffer(512)
+    check("fft_ragged_shapes", lib().fft_ragged_shapes(int(n), buf, len(buf)))
+    return buf.value.decode().split(",")
+
+
+def fft_tune_set_ragged(n, shape):
+    return check("fft_tune_set_ragged", lib().fft_tune_set_ragged(int(n), shape.encode()))
+
+
+def fft_tune_query_ragged(n):
+    buf = ctypes.create_string_buffer(128)
+    check("fft_tune_query_ragged", lib().fft_tune_query_ragged(int(n), buf, len(buf)))
+    return buf.value.decode()
+
+
+def fft_tune_clear_ragged():
+    return check("fft_tune_clear_ragged", lib().fft_tune_clear_ragged())
 
 
 def fft_tune_load(path):

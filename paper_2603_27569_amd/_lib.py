@@ -42,6 +42,10 @@ SIGNATURES = {
     "fft_exec_ragged": (_int, [_vp, _vp, _vp, _vp]),
     "fft_exec_ragged_plain": (_int, [_vp, _pvp, _pvp, _vp]),
     "fft_destroy_ragged": (_int, [_vp]),
+    "fft_ragged_shapes": (_int, [_i64, ctypes.c_char_p, _i64]),
+    "fft_tune_set_ragged": (_int, [_i64, ctypes.c_char_p]),
+    "fft_tune_query_ragged": (_int, [_i64, ctypes.c_char_p, _i64]),
+    "fft_tune_clear_ragged": (_int, []),
     "fft_tune_load": (_int, [ctypes.c_char_p]),
     "fft_tune_set": (_int, [_i64, _i64, _i64, ctypes.c_char_p]),
     "fft_tune_clear": (_int, []),

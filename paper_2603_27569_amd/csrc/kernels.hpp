@@ -33,7 +33,7 @@ __device__ __forceinline__ void global_store_row(const c32 (&a)[S::E], c32* dst,
 // workgroup owns TPB whole transforms; every pass stays on chip.
 template <class S, bool INV>
 __global__ __launch_bounds__(S::THREADS) void k_stockham(const c32* in, c32* out,
-                                                         const c32* __restrict__ tw, int64_t rows) {
+                                                         const c32* tw, int64_t rows) {
   __shared__ c32 lds_all[S::TPB * S::LDS_ELEMS];
   const int tid = threadIdx.x;
   const int slot = tid / S::T;
@@ -43,7 +43,7 @@ __global__ __launch_bounds__(S::THREADS) void k_stockham(const c32* in, c32* out
   c32* lds = lds_all + slot * S::LDS_ELEMS;
   c32 a[S::E];
   global_load_row<S>(a, in + row * S::N, t, live);
-  run_passes<S, 0, INV>(a, lds, tw, t);
+  run_passes<S, INV>(a, lds, tw, t);
   global_store_row<S>(a, out + row * S::N, t, live);
 }
 
@@ -85,7 +85,7 @@ __device__ __forceinline__ float wave_group_sum(float v) {
 template <class S>
 __global__ __launch_bounds__(S::THREADS) void k_spectral_energy(
     const c32* x, const float* __restrict__ w, const float* __restrict__ scale, c32* grad,
-    float* __restrict__ row_loss, const c32* __restrict__ tw, int64_t rows) {
+    float* __restrict__ row_loss, const c32* tw, int64_t rows) {
   __shared__ c32 lds_all[S::TPB * S::LDS_ELEMS];
   __shared__ float red[(S::THREADS + 63) / 64];
   const int tid = threadIdx.x;
@@ -96,7 +96,7 @@ __global__ __launch_bounds__(S::THREADS) void k_spectral_energy(
   c32* lds = lds_all + slot * S::LDS_ELEMS;
   c32 a[S::E];
   global_load_row<S>(a, x + row * S::N, t, live);
-  run_passes<S, 0, false>(a, lds, tw, t);
+  run_passes<S, false>(a, lds, tw, t);
 
   const float sc = scale ? 2.0f * scale[0] : 2.0f;
   float acc = 0.f;
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(S::THREADS) void k_spectral_energy(
     row_loss[row] = total;
   }
   if (grad == nullptr) return;  // uniform across the workgroup
-  run_passes<S, 0, true>(a, lds, tw, t);
+  run_passes<S, true>(a, lds, tw, t);
   global_store_row<S>(a, grad + row * S::N, t, live);
 }
 
@@ -150,7 +150,7 @@ hipError_t launch_spectral_energy(const void* x, const float* w, const float* sc
 // out = (1/N) F^H(conj(h) .* F x) in one kernel.
 template <class S>
 __global__ __launch_bounds__(S::THREADS) void k_matched_filter(const c32* x, const c32* __restrict__ h,
-                                                               c32* out, const c32* __restrict__ tw,
+                                                               c32* out, const c32* tw,
                                                                int64_t rows) {
   __shared__ c32 lds_all[S::TPB * S::LDS_ELEMS];
   const int tid = threadIdx.x;
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(S::THREADS) void k_matched_filter(const c32* x, con
   c32* lds = lds_all + slot * S::LDS_ELEMS;
   c32 a[S::E];
   global_load_row<S>(a, x + row * S::N, t, live);
-  run_passes<S, 0, false>(a, lds, tw, t);
+  run_passes<S, false>(a, lds, tw, t);
   constexpr float inv_n = 1.0f / float(S::N);  // a power of two: exact
 #pragma unroll
   for (int m = 0; m < S::E; ++m) {
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(S::THREADS) void k_matched_filter(const c32* x, con
     a[m] = c32{y.x * inv_n, y.y * inv_n};
   }
   __syncthreads();
-  run_passes<S, 0, true>(a, lds, tw, t);
+  run_passes<S, true>(a, lds, tw, t);
   global_store_row<S>(a, out + row * S::N, t, live);
 }
 
@@ -203,7 +203,7 @@ constexpr int kXcds = 8;
 
 template <class S, int N1, bool INV>
 __global__ __launch_bounds__(S::THREADS) void k_four_step_columns(const c32* x, c32* y,
-                                                                  const c32* __restrict__ tw,
+                                                                  const c32* tw,
                                                                   int64_t rows) {
   static_assert(S::TPB == 1, "four-step sub-transforms use one transform per workgroup");
   __shared__ c32 lds[S::LDS_ELEMS];
@@ -219,7 +219,7 @@ __global__ __launch_bounds__(S::THREADS) void k_four_step_columns(const c32* x, 
   c32 a[S::E];
 #pragma unroll
   for (int m = 0; m < S::E; ++m) a[m] = src[(int64_t)(t + m * S::T) * N1];
-  run_passes<S, 0, INV>(a, lds, tw, t);
+  run_passes<S, INV>(a, lds, tw, t);
   global_store_row<S>(a, y + (row * N1 + n1) * S::N, t, true);
 }
 

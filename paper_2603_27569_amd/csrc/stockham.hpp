@@ -30,7 +30,9 @@ namespace stockfft {
 
 // ------------------------------------------------------------------ complex
 
-struct c32 {
+// Interleaved complex64; 8-byte aligned so global and LDS accesses are single
+// 64-bit operations.
+struct alignas(8) c32 {
   float x, y;
 };
 
@@ -168,6 +170,13 @@ struct Shape {
     return o;
   }
   static constexpr int TW_ELEMS = tw_off(P);
+  // Twiddles one lane applies in pass p: E/R_p butterflies x (R_p - 1) legs.
+  static constexpr int tw_per_lane(int p) { return p == 0 ? 0 : (E / L::r[p]) * (L::r[p] - 1); }
+  static constexpr int TW_REGS = [] {
+    int m = 1;
+    for (int i = 1; i < P; ++i) m = tw_per_lane(i) > m ? tw_per_lane(i) : m;
+    return m;
+  }();
   static constexpr bool valid() {
     if (ns(P) != N || T * E != N || THREADS > 1024 || THREADS < 1) return false;
     for (int i = 0; i < P; ++i)
@@ -183,21 +192,42 @@ struct Shape {
 
 // ------------------------------------------------------------ one pass
 
-// Twiddle + butterflies of pass p on the lane's registers.
-template <class S, int p, bool INV>
-__device__ __forceinline__ void pass_compute(c32 (&a)[S::E], const c32* __restrict__ tw, int t) {
-  constexpr int R = S::radix(p);
-  constexpr int NS = S::ns(p);
-  constexpr int BPT = S::E / R;
-  if constexpr (NS > 1) {
+// Issues the global loads of the twiddles this lane needs in pass p into
+// registers; the caller consumes them one pass later, so their latency hides
+// behind a whole pass of arithmetic and exchange.
+template <class S, int p>
+__device__ __forceinline__ void load_twiddles(c32 (&w)[S::TW_REGS], const c32* tw, int t) {
+  if constexpr (p > 0 && p < S::P) {
+    constexpr int R = S::radix(p);
+    constexpr int NS = S::ns(p);
+    constexpr int BPT = S::E / R;
     const c32* twp = tw + S::tw_off(p);
 #pragma unroll
     for (int b = 0; b < BPT; ++b) {
       const int k = (t + b * S::T) & (NS - 1);
 #pragma unroll
-      for (int r = 1; r < R; ++r) a[b + r * BPT] = ctw<INV>(a[b + r * BPT], twp[(r - 1) * NS + k]);
+      for (int r = 1; r < R; ++r) w[b * (R - 1) + (r - 1)] = twp[(r - 1) * NS + k];
     }
+    // Keep the loads here: the scheduler would otherwise sink them to their
+    // use, past the exchange barriers, and expose their latency.
+    __builtin_amdgcn_sched_barrier(0);
   }
+}
+
+// Twiddle multiply of pass p (twiddles already in registers), then the next
+// pass's twiddle loads are issued, then the butterflies run.
+template <class S, int p, bool INV>
+__device__ __forceinline__ void pass_compute(c32 (&a)[S::E], c32 (&w)[S::TW_REGS],
+                                             const c32* tw, int t) {
+  constexpr int R = S::radix(p);
+  constexpr int BPT = S::E / R;
+  if constexpr (p > 0) {
+#pragma unroll
+    for (int b = 0; b < BPT; ++b)
+#pragma unroll
+      for (int r = 1; r < R; ++r) a[b + r * BPT] = ctw<INV>(a[b + r * BPT], w[b * (R - 1) + (r - 1)]);
+  }
+  load_twiddles<S, p + 1>(w, tw, t);
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     c32 v[R];
@@ -231,20 +261,30 @@ __device__ __forceinline__ void lds_load_all(c32 (&a)[S::E], const c32* lds, int
 }
 
 // Runs passes p..P-1.  On entry a[] holds the pass-p inputs in the register
-// convention.  On exit a[] holds the transform in natural order, a[m] at
-// position t + m T.  Between passes the data goes through lds, which must be
-// free to overwrite on entry (the caller's barrier).
+// convention and w[] the pass-p twiddles (nothing for p = 0).  On exit a[]
+// holds the transform in natural order, a[m] at position t + m T.  Between
+// passes the data goes through lds, which must be free to overwrite on entry
+// (the caller's barrier).
 template <class S, int p, bool INV>
-__device__ __forceinline__ void run_passes(c32 (&a)[S::E], c32* lds, const c32* __restrict__ tw,
-                                           int t) {
-  pass_compute<S, p, INV>(a, tw, t);
+__device__ __forceinline__ void run_passes_from(c32 (&a)[S::E], c32 (&w)[S::TW_REGS], c32* lds,
+                                                const c32* tw, int t) {
+  pass_compute<S, p, INV>(a, w, tw, t);
   if constexpr (p + 1 < S::P) {
     pass_store_lds<S, p>(a, lds, t);
     __syncthreads();
     lds_load_all<S>(a, lds, t);
     if constexpr (p + 2 < S::P) __syncthreads();  // all reads done before the next overwrite
-    run_passes<S, p + 1, INV>(a, lds, tw, t);
+    run_passes_from<S, p + 1, INV>(a, w, lds, tw, t);
   }
+}
+
+// All passes of one transform.  Called right after the lane's input loads
+// were issued, so the first twiddle loads queue behind them.
+template <class S, bool INV>
+__device__ __forceinline__ void run_passes(c32 (&a)[S::E], c32* lds, const c32* tw,
+                                           int t) {
+  c32 w[S::TW_REGS];
+  run_passes_from<S, 0, INV>(a, w, lds, tw, t);
 }
 
 }  // namespace stockfft

@@ -102,6 +102,26 @@ def test_ragged_plan_validation():
     assert L.fft_plan_ragged(None, arr, 2, -1) == _lib.CODES["FFT_INVALID_POINTER"]
 
 
+def test_ragged_shape_tuning_api():
+    sf.fft_tune_clear_ragged()
+    try:
+        for n in (256, 512, 1024, 2048, 4096, 8192, 16384):
+            shapes = sf.fft_ragged_shapes(n)
+            assert f"ragged_n{n}_e16" in shapes
+            assert sf.fft_tune_query_ragged(n) == f"ragged_n{n}_e16"
+            if n <= 8192:
+                assert f"ragged_n{n}_e8" in shapes
+                sf.fft_tune_set_ragged(n, f"ragged_n{n}_e8")
+                assert sf.fft_tune_query_ragged(n) == f"ragged_n{n}_e8"
+        with pytest.raises(sf.StockfftError):
+            sf.fft_tune_set_ragged(16384, "ragged_n256_e16")
+        with pytest.raises(sf.StockfftError):
+            sf.fft_tune_set_ragged(300, "ragged_n256_e16")
+    finally:
+        sf.fft_tune_clear_ragged()
+    assert sf.fft_tune_query_ragged(1024) == "ragged_n1024_e16"
+
+
 def test_no_device_reported_cleanly():
     try:
         import torch
