@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "internal.hpp"
+#include "json_lite.hpp"
 #include "variants.hpp"
 
 namespace stockfft {
@@ -176,9 +177,12 @@ DeviceGuard::~DeviceGuard() {
 
 namespace {
 
+// One tuning decision: a single-pass variant or a four-step split for the
+// lengths and batch range given.
 struct TuneEntry {
   int64_t n, bmin, bmax;
   const SingleVariant* v;
+  const FourStepVariant* fs;
 };
 
 std::mutex g_tune_mu;
@@ -203,49 +207,36 @@ void load_env_tune_locked();
 
 }  // namespace
 
-const SingleVariant* tuned_variant(int64_t n, int64_t batch) {
+// The tuned choice for (n, batch): the last matching entry, else the built-in
+// single-pass variant.  With single_only, four-step entries are passed over.
+void tuned_choice(int64_t n, int64_t batch, bool single_only, const SingleVariant** sv,
+                  const FourStepVariant** fs) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   load_env_tune_locked();
-  const SingleVariant* pick = nullptr;
-  for (const TuneEntry& e : g_tune)
-    if (e.n == n && batch >= e.bmin && batch <= e.bmax) pick = e.v;
-  return pick ? pick : find_single(builtin_variant(n));
+  *sv = nullptr;
+  *fs = nullptr;
+  for (const TuneEntry& e : g_tune) {
+    if (e.n != n || batch < e.bmin || batch > e.bmax) continue;
+    if (single_only && !e.v) continue;
+    *sv = e.v;
+    *fs = e.fs;
+  }
+  if (!*sv && !*fs) *sv = find_single(builtin_variant(n));
+}
+
+const SingleVariant* tuned_variant(int64_t n, int64_t batch) {
+  const SingleVariant* sv;
+  const FourStepVariant* fs;
+  tuned_choice(n, batch, true, &sv, &fs);
+  return sv;
 }
 
 namespace {
 
-// Minimal reader for the tuner's JSON: every innermost {...} object carrying
-// "n" and "variant" is an entry; "arch" at top level is compared with the
-// device's architecture name when a device is present.
-bool json_find_int(const std::string& obj, const char* key, int64_t* out) {
-  std::string k = std::string("\"") + key + "\"";
-  size_t p = obj.find(k);
-  if (p == std::string::npos) return false;
-  p = obj.find(':', p + k.size());
-  if (p == std::string::npos) return false;
-  const char* s = obj.c_str() + p + 1;
-  char* end = nullptr;
-  errno = 0;
-  long long v = std::strtoll(s, &end, 10);
-  if (end == s || errno) return false;
-  *out = (int64_t)v;
-  return true;
-}
-
-bool json_find_str(const std::string& obj, const char* key, std::string* out) {
-  std::string k = std::string("\"") + key + "\"";
-  size_t p = obj.find(k);
-  if (p == std::string::npos) return false;
-  p = obj.find(':', p + k.size());
-  if (p == std::string::npos) return false;
-  size_t q = obj.find('"', p);
-  if (q == std::string::npos) return false;
-  size_t r = obj.find('"', q + 1);
-  if (r == std::string::npos) return false;
-  *out = obj.substr(q + 1, r - q - 1);
-  return true;
-}
-
+// Applies a tuning document written by the autotuner: "entries" (single-pass
+// or four-step variant per length and batch range) and "ragged" (shape per
+// length).  "arch" is compared with the device's architecture name when a
+// device is present.  Entries naming unknown variants are skipped.
 int load_tune_file_locked(const char* path) {
   FILE* f = std::fopen(path, "rb");
   if (!f) {
@@ -257,45 +248,59 @@ int load_tune_file_locked(const char* path) {
   size_t got;
   while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
   std::fclose(f);
-  std::string arch;
-  if (json_find_str(text, "arch", &arch)) {
+  json::Value doc;
+  if (!json::Parser(text).parse(&doc) || doc.kind != json::Value::Object) {
+    std::fprintf(stderr, "stockfft: tune file %s is not valid JSON; ignored\n", path);
+    return FFT_INVALID_ARGUMENT;
+  }
+  const json::Value* arch = doc.get("arch");
+  if (arch && arch->kind == json::Value::String) {
     int count = 0, dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDeviceCount(&count) == hipSuccess && count > 0 && hipGetDevice(&dev) == hipSuccess &&
         hipGetDeviceProperties(&prop, dev) == hipSuccess &&
-        std::strncmp(prop.gcnArchName, arch.c_str(), arch.size()) != 0) {
+        std::strncmp(prop.gcnArchName, arch->str.c_str(), arch->str.size()) != 0) {
       std::fprintf(stderr, "stockfft: tune file %s is for %s, device is %s; ignored\n", path,
-                   arch.c_str(), prop.gcnArchName);
+                   arch->str.c_str(), prop.gcnArchName);
       return FFT_INVALID_ARGUMENT;
     }
   }
+  auto num = [](const json::Value& o, const char* k, int64_t dflt) {
+    const json::Value* v = o.get(k);
+    if (!v || v->kind != json::Value::Number) return dflt;
+    return v->num >= 9.2e18 ? INT64_MAX : (int64_t)v->num;
+  };
+  auto str = [](const json::Value& o, const char* k) -> const std::string* {
+    const json::Value* v = o.get(k);
+    return v && v->kind == json::Value::String ? &v->str : nullptr;
+  };
   std::vector<TuneEntry> add;
   int skipped = 0;
-  size_t pos = 0;
-  while ((pos = text.find('{', pos)) != std::string::npos) {
-    size_t close = text.find('}', pos);
-    size_t inner = text.find('{', pos + 1);
-    if (close == std::string::npos) break;
-    if (inner != std::string::npos && inner < close) {  // not innermost
-      pos = inner;
-      continue;
+  if (const json::Value* es = doc.get("entries"); es && es->kind == json::Value::Array) {
+    for (const json::Value& e : es->arr) {
+      const std::string* name = str(e, "variant");
+      const int64_t n = num(e, "n", 0);
+      if (!name || !valid_size(n)) {
+        ++skipped;
+        continue;
+      }
+      const SingleVariant* v = find_single(name->c_str());
+      const FourStepVariant* fs = v ? nullptr : find_four_step(name->c_str());
+      if ((!v || v->n != n) && (!fs || fs->n != n)) {
+        ++skipped;
+        continue;
+      }
+      add.push_back({n, num(e, "batch_min", 1), num(e, "batch_max", INT64_MAX), v, fs});
     }
-    std::string obj = text.substr(pos, close - pos + 1);
-    pos = close + 1;
-    int64_t n = 0, bmin = 1, bmax = INT64_MAX;
-    std::string name;
-    if (!json_find_int(obj, "n", &n) || !json_find_str(obj, "variant", &name)) continue;
-    json_find_int(obj, "batch_min", &bmin);
-    json_find_int(obj, "batch_max", &bmax);
-    const SingleVariant* v = find_single(name.c_str());
-    if (!v || v->n != n) {
-      ++skipped;
-      continue;
+  }
+  if (const json::Value* rs = doc.get("ragged"); rs && rs->kind == json::Value::Array) {
+    for (const json::Value& e : rs->arr) {
+      const std::string* shape = str(e, "shape");
+      if (!shape || fft_tune_set_ragged(num(e, "n", 0), shape->c_str()) != FFT_SUCCESS) ++skipped;
     }
-    add.push_back({n, bmin, bmax, v});
   }
   if (skipped)
-    std::fprintf(stderr, "stockfft: %d tune entries in %s name unknown variants; skipped\n",
+    std::fprintf(stderr, "stockfft: %d tune entries in %s are not usable here; skipped\n",
                  skipped, path);
   g_tune.insert(g_tune.end(), add.begin(), add.end());
   return FFT_SUCCESS;
@@ -397,7 +402,8 @@ extern "C" int fft_plan_config(fft_plan_t* plan, int64_t n, int64_t batch, int d
       }
     }
   } else {
-    sv = tuned_variant(n, batch);
+    tuned_choice(n, batch, algorithm == FFT_ALGO_SINGLE_PASS, &sv, &fs);
+    if (fs) sv = find_single(fs->sub_name);
     if (!sv) return FFT_INVALID_SIZE;
   }
 
@@ -526,10 +532,11 @@ extern "C" int fft_tune_set(int64_t n, int64_t batch_min, int64_t batch_max, con
   if (!valid_size(n)) return FFT_INVALID_SIZE;
   if (batch_min < 1 || batch_max < batch_min) return FFT_INVALID_BATCH;
   const SingleVariant* v = find_single(variant);
-  if (!v || v->n != n) return FFT_INVALID_ARGUMENT;
+  const FourStepVariant* f = v ? nullptr : find_four_step(variant);
+  if ((!v || v->n != n) && (!f || f->n != n)) return FFT_INVALID_ARGUMENT;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   load_env_tune_locked();
-  g_tune.push_back({n, batch_min, batch_max, v});
+  g_tune.push_back({n, batch_min, batch_max, v, f});
   return FFT_SUCCESS;
 }
 
@@ -537,7 +544,10 @@ extern "C" int fft_tune_query(int64_t n, int64_t batch, char* buf, int64_t cap) 
   if (!buf) return FFT_INVALID_POINTER;
   if (!valid_size(n)) return FFT_INVALID_SIZE;
   if (batch < 1) return FFT_INVALID_BATCH;
-  const SingleVariant* v = tuned_variant(n, batch);
+  const SingleVariant* v;
+  const FourStepVariant* f;
+  tuned_choice(n, batch, false, &v, &f);
+  if (f) return put_text(f->name, buf, cap);
   if (!v) return FFT_INVALID_SIZE;
   return put_text(v->name, buf, cap);
 }

@@ -1,0 +1,157 @@
+"""Autotuner for the Stockham kernels on the current GPU.
+
+For every transform length and batch bucket it times each compiled kernel
+variant -- values per lane (hence the radix and lanes per transform),
+transforms per workgroup, LDS padding, and for N >= 8192 the four-step
+splits -- through the C ABI, and keeps the fastest.  For the ragged
+persistent kernel it times each compiled shape of every length on a batch
+of that length alone and keeps the fastest.  The result is a JSON file that
+``fft_tune_load`` (or the STOCKFFT_TUNE_CACHE environment variable) applies:
+
+  {"arch": "gfx950", "cus": 256, "hip_runtime": ..., "entries": [
+     {"n": 4096, "batch_min": 129, "batch_max": 1024,
+      "variant": "n4096_e16_b1_p4_r16.16.16", "us": ..., "candidates": {...}}],
+   "ragged": [{"n": 4096, "shape": "ragged_n4096_e16", "us": ...}]}
+
+Timing: back-to-back launches over a ring of independent buffers larger
+than the Infinity Cache, bracketed by HIP events on the launch stream; the
+median of a few repeats.  Every variant computes the same transform (the
+parity tests check each one against the FP64 reference), so the search is
+on speed alone.
+
+Usage: python -m paper_2603_27569_amd.tune [--out tune_gfx950.json] [--quick]
+"""
+import argparse
+import json
+import math
+import statistics
+import sys
+
+from . import (FFT_ALGO_FOUR_STEP, FFT_ALGO_SINGLE_PASS, FFT_FORWARD, Plan, RaggedPlan,
+               fft_ragged_shapes, fft_tune_clear_ragged, fft_tune_set_ragged, variants)
+
+SIZES = (256, 512, 1024, 2048, 4096, 8192, 16384)
+# Batch buckets: (batch_min, batch_max, representative batch timed).
+BUCKETS = ((1, 64, 32), (65, 512, 256), (513, 4096, 2048), (4097, 2 ** 62, 16384))
+RING_BYTES = 1 << 30
+MAX_BYTES = 2 << 30  # cap on one timed buffer
+
+
+def _ring(torch, dev, n, batch):
+    per = n * batch * 8
+    k = max(2, math.ceil(RING_BYTES / (2 * per)))
+    xs = [torch.randn(batch, n, dtype=torch.complex64, device=dev) for _ in range(k)]
+    ys = [torch.empty_like(xs[0]) for _ in range(k)]
+    return xs, ys
+
+
+def _time(torch, stream, fn, iters, warmup=5, repeats=3):
+    with torch.cuda.stream(stream):
+        for i in range(warmup):
+            fn(i)
+    torch.cuda.synchronize()
+    res = []
+    for _ in range(repeats):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            e0.record(stream)
+            for i in range(iters):
+                fn(i)
+            e1.record(stream)
+        torch.cuda.synchronize()
+        res.append(e0.elapsed_time(e1) * 1e3 / iters)
+    return statistics.median(res)
+
+
+def candidates(n):
+    out = []
+    for v in variants():
+        if v["n"] != n:
+            continue
+        algo = FFT_ALGO_FOUR_STEP if v["kind"] == "four_step" else FFT_ALGO_SINGLE_PASS
+        out.append((v["name"], algo))
+    return out
+
+
+def tune_plain(torch, dev, stream, sizes=SIZES, buckets=BUCKETS, iters=30, log=print):
+    entries = []
+    for n in sizes:
+        for bmin, bmax, b in buckets:
+            while n * b * 8 > MAX_BYTES and b > 1:
+                b //= 2
+            xs, ys = _ring(torch, dev, n, b)
+            k = len(xs)
+            times = {}
+            cs = stream.cuda_stream
+            for name, algo in candidates(n):
+                p = Plan(n, b, FFT_FORWARD, algo, name)
+                times[name] = _time(torch, stream,
+                                    lambda i: p.exec(xs[i % k].data_ptr(), ys[i % k].data_ptr(), cs),
+                                    iters)
+                p.close()
+            best = min(times, key=times.get)
+            log(f"tune n={n} batch={b} -> {best} {times[best]:.2f} us")
+            entries.append({"n": n, "batch_min": bmin, "batch_max": bmax, "variant": best,
+                            "timed_batch": b, "us": round(times[best], 3),
+                            "candidates": {k2: round(v, 3) for k2, v in times.items()}})
+            del xs, ys
+    return entries
+
+
+def tune_ragged(torch, dev, stream, count_per_size=256, iters=20, log=print):
+    """Time each ragged shape of each length on a single-length batch."""
+    out = []
+    cs = stream.cuda_stream
+    try:
+        for n in SIZES:
+            sizes = [n] * count_per_size
+            total = n * count_per_size
+            k = max(2, math.ceil(RING_BYTES / (2 * total * 8)))
+            xs = [torch.randn(total, dtype=torch.complex64, device=dev) for _ in range(k)]
+            ys = [torch.empty_like(xs[0]) for _ in range(k)]
+            times = {}
+            for shape in fft_ragged_shapes(n):
+                fft_tune_set_ragged(n, shape)
+                p = RaggedPlan(sizes)
+                times[shape] = _time(torch, stream,
+                                     lambda i: p.exec(xs[i % k].data_ptr(), ys[i % k].data_ptr(), cs),
+                                     iters)
+                p.close()
+            best = min(times, key=times.get)
+            log(f"tune ragged n={n} -> {best} {times[best]:.2f} us")
+            out.append({"n": n, "shape": best, "us": round(times[best], 3),
+                        "candidates": {k2: round(v, 3) for k2, v in times.items()}})
+            del xs, ys
+    finally:
+        fft_tune_clear_ragged()
+    return out
+
+
+def run(out_path, quick=False, log=print):
+    import torch
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    props = torch.cuda.get_device_properties(dev)
+    buckets = BUCKETS if not quick else ((1, 2 ** 62, 1024),)
+    entries = tune_plain(torch, dev, stream, buckets=buckets, iters=10 if quick else 30, log=log)
+    ragged = tune_ragged(torch, dev, stream, count_per_size=64 if quick else 256,
+                         iters=5 if quick else 20, log=log)
+    doc = {"arch": props.gcnArchName.split(":")[0], "cus": props.multi_processor_count,
+           "hip_runtime": getattr(torch.version, "hip", None), "entries": entries, "ragged": ragged}
+    with open(out_path, "w") as f:
+        json.dump(doc, f, indent=1)
+    return doc
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--out", default="tune_gfx950.json")
+    ap.add_argument("--quick", action="store_true")
+    a = ap.parse_args(argv)
+    run(a.out, a.quick, log=lambda *x: print(*x, file=sys.stderr, flush=True))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -102,6 +102,29 @@ def test_ragged_plan_validation():
     assert L.fft_plan_ragged(None, arr, 2, -1) == _lib.CODES["FFT_INVALID_POINTER"]
 
 
+def test_tune_file_with_four_step_and_ragged_entries(tmp_path):
+    sf.fft_tune_clear()
+    sf.fft_tune_clear_ragged()
+    try:
+        p = tmp_path / "t.json"
+        p.write_text(json.dumps({"arch": "gfx950", "cus": 256, "entries": [
+            {"n": 16384, "batch_min": 1, "batch_max": 8, "variant": "fs16384_4x4096", "us": 1.0},
+            {"n": 16384, "batch_min": 9, "batch_max": 10 ** 12, "variant": "n16384_e32_b1_p4_r16.16.16.4"},
+            {"n": 512, "batch_min": 1, "batch_max": 10 ** 12, "variant": "n512_e8_b4_p4_r8.8.8",
+             "candidates": {"n512_e4_b2_p4_r4.4.4.4.2": 3.0}}],
+            "ragged": [{"n": 2048, "shape": "ragged_n2048_e8", "us": 2.0}]}))
+        sf.fft_tune_load(str(p))
+        assert sf.fft_tune_query(16384, 4) == "fs16384_4x4096"
+        assert sf.fft_tune_query(16384, 1024) == "n16384_e32_b1_p4_r16.16.16.4"
+        assert sf.fft_tune_query(512, 77) == "n512_e8_b4_p4_r8.8.8"
+        assert sf.fft_tune_query_ragged(2048) == "ragged_n2048_e8"
+        sf.fft_tune_set(8192, 1, 10, "fs8192_2x4096")
+        assert sf.fft_tune_query(8192, 3) == "fs8192_2x4096"
+    finally:
+        sf.fft_tune_clear()
+        sf.fft_tune_clear_ragged()
+
+
 def test_ragged_shape_tuning_api():
     sf.fft_tune_clear_ragged()
     try:
@@ -256,6 +279,11 @@ def test_tune_table_set_query_load(tmp_path):
         assert sf.fft_tune_query(2048, 5) == "n2048_e8_b1_p4_r8.8.8.4"
         with pytest.raises(sf.StockfftError):
             sf.fft_tune_load(str(tmp_path / "missing.json"))
+        bad = tmp_path / "bad.json"
+        for text in ('{"entries": [', '{"entries": [{"n": 2048,}]}', "[1, 2", '{"a" 1}'):
+            bad.write_text(text)
+            with pytest.raises(sf.StockfftError):
+                sf.fft_tune_load(str(bad))
         assert sf.fft_tune_query(2048, 5) == "n2048_e8_b1_p4_r8.8.8.4"
     finally:
         sf.fft_tune_clear()

@@ -1,0 +1,54 @@
+"""The autotuner end to end on a restricted search, and plans honouring it."""
+import json
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2603_27569_amd as sf
+from paper_2603_27569_amd import metrics, tune, workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def test_tuner_restricted_search_and_load(tmp_path):
+    dev = torch.device("cuda:0")
+    s = torch.cuda.Stream()
+    entries = tune.tune_plain(torch, dev, s, sizes=(256, 8192), buckets=((1, 2 ** 62, 64),),
+                              iters=3, log=lambda *a: None)
+    assert {e["n"] for e in entries} == {256, 8192}
+    for e in entries:
+        assert e["variant"] in e["candidates"]
+        assert e["us"] == min(e["candidates"].values())
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"arch": "gfx950", "entries": entries, "ragged": []}))
+    sf.fft_tune_clear()
+    try:
+        sf.fft_tune_load(str(path))
+        for e in entries:
+            assert sf.fft_tune_query(e["n"], 64) == e["variant"]
+            x = workloads.plain_normal(e["n"], 5, seed=1)
+            p = sf.Plan(e["n"], 5)
+            d = p.describe()
+            chosen = d.get("four_step", d["variant"])["name"]
+            assert chosen == e["variant"]
+            xt = torch.from_numpy(x).to(dev)
+            y = torch.empty_like(xt)
+            p.exec(xt.data_ptr(), y.data_ptr(), torch.cuda.current_stream().cuda_stream)
+            torch.cuda.synchronize()
+            ok, worst, _, _ = metrics.gate(y.cpu().numpy(), oracle.fft(x), x)
+            assert ok, worst
+            p.close()
+    finally:
+        sf.fft_tune_clear()
+
+
+def test_ragged_shape_tuner():
+    dev = torch.device("cuda:0")
+    s = torch.cuda.Stream()
+    out = tune.tune_ragged(torch, dev, s, count_per_size=8, iters=2, log=lambda *a: None)
+    assert [o["n"] for o in out] == list(workloads.SIZES)
+    for o in out:
+        assert o["shape"] in sf.fft_ragged_shapes(o["n"])
+    assert sf.fft_tune_query_ragged(4096) == "ragged_n4096_e16"  # tuner leaves no state
