@@ -189,15 +189,39 @@ std::mutex g_tune_mu;
 std::vector<TuneEntry> g_tune;
 bool g_env_tune_done = false;
 
-// Built-in choices per size (used when no tuning entry matches).
-const char* builtin_variant(int64_t n) {
+// Built-in choices: the autotuner's result on MI355X (gfx950, 256 CUs), the
+// same table as the package's tune_gfx950.json.  Tuning entries added at run
+// time take precedence.
+struct BuiltinEntry {
+  int64_t n, bmin, bmax;
+  const char* name;
+};
+const BuiltinEntry kBuiltin[] = {
+    {256, 1, 64, "n256_e16_b16_p4_r16.16"},
+    {256, 65, INT64_MAX, "n256_e8_b8_p4_r8.8.4"},
+    {512, 1, 64, "n512_e8_b4_p4_r8.8.8"},
+    {512, 65, 4096, "n512_e16_b2_p4_r16.16.2"},
+    {512, 4097, INT64_MAX, "n512_e8_b4_p4_r8.8.8"},
+    {1024, 1, 64, "n1024_e16_b1_p4_r16.16.4"},
+    {1024, 65, 512, "n1024_e8_b2_p4_r8.8.8.2"},
+    {1024, 513, INT64_MAX, "n1024_e16_b1_p4_r16.16.4"},
+    {2048, 1, 64, "n2048_e4_b1_p4_r4.4.4.4.4.2"},
+    {2048, 65, 512, "n2048_e8_b1_p4_r8.8.8.4"},
+    {2048, 513, INT64_MAX, "n2048_e16_b1_p4_r16.16.8"},
+    {4096, 1, 64, "n4096_e8_b1_p4_r8.8.8.8"},
+    {4096, 65, 4096, "n4096_e16_b1_p5_r16.16.16"},
+    {4096, 4097, INT64_MAX, "n4096_e32_b1_p4_r16.16.16"},
+    {8192, 1, 64, "fs8192_4x2048"},
+    {8192, 65, INT64_MAX, "n8192_e32_b1_p4_r16.16.16.2"},
+    {16384, 1, 64, "fs16384_8x2048"},
+    {16384, 65, 4096, "n16384_e16_b1_p4_r16.16.16.4"},
+    {16384, 4097, INT64_MAX, "n16384_e32_b1_p4_r16.16.16.4"},
+};
+
+// Single-pass fallback when a four-step choice is not wanted.
+const char* builtin_single(int64_t n) {
   switch (n) {
-    case 256: return "n256_e16_b16_p4_r16.16";
-    case 512: return "n512_e16_b8_p4_r16.16.2";
-    case 1024: return "n1024_e16_b4_p4_r16.16.4";
-    case 2048: return "n2048_e16_b2_p4_r16.16.8";
-    case 4096: return "n4096_e16_b1_p4_r16.16.16";
-    case 8192: return "n8192_e16_b1_p4_r16.16.16.2";
+    case 8192: return "n8192_e32_b1_p4_r16.16.16.2";
     case 16384: return "n16384_e16_b1_p4_r16.16.16.4";
     default: return nullptr;
   }
@@ -215,13 +239,20 @@ void tuned_choice(int64_t n, int64_t batch, bool single_only, const SingleVarian
   load_env_tune_locked();
   *sv = nullptr;
   *fs = nullptr;
+  for (const BuiltinEntry& b : kBuiltin) {
+    if (b.n != n || batch < b.bmin || batch > b.bmax) continue;
+    const SingleVariant* v = find_single(b.name);
+    const FourStepVariant* f = v ? nullptr : find_four_step(b.name);
+    if (single_only && !v) v = find_single(builtin_single(n)), f = nullptr;
+    *sv = v;
+    *fs = f;
+  }
   for (const TuneEntry& e : g_tune) {
     if (e.n != n || batch < e.bmin || batch > e.bmax) continue;
     if (single_only && !e.v) continue;
     *sv = e.v;
     *fs = e.fs;
   }
-  if (!*sv && !*fs) *sv = find_single(builtin_variant(n));
 }
 
 const SingleVariant* tuned_variant(int64_t n, int64_t batch) {

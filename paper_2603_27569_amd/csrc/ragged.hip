@@ -159,8 +159,9 @@ int shape_index(const char* name) {
   return -1;
 }
 
-// Built-in per-size shape (radix-16 for every size).
-int builtin_shape(int64_t n) { return ilog2(n) - 8; }
+// Built-in per-size shape: the autotuner's choice on MI355X (radix-8 lanes for
+// N <= 8192, radix-16 for 16384, the only shape that fits).
+int builtin_shape(int64_t n) { return n == 16384 ? 6 : 7 + ilog2(n) - 8; }
 
 std::mutex g_rtune_mu;
 int g_rtune[7] = {-1, -1, -1, -1, -1, -1, -1};

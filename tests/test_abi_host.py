@@ -125,12 +125,27 @@ def test_tune_file_with_four_step_and_ragged_entries(tmp_path):
         sf.fft_tune_clear_ragged()
 
 
+def test_builtin_table_is_the_shipped_tuner_output():
+    """The library's built-in choices equal the autotuner's MI355X result
+    shipped with the package (tune_gfx950.json)."""
+    sf.fft_tune_clear()
+    sf.fft_tune_clear_ragged()
+    doc = json.load(open(os.path.join(ROOT, "paper_2603_27569_amd", "tune_gfx950.json")))
+    assert doc["arch"] == "gfx950"
+    for e in doc["entries"]:
+        for b in (e["batch_min"], e["timed_batch"], min(e["batch_max"], 10 ** 9)):
+            assert sf.fft_tune_query(e["n"], b) == e["variant"], (e["n"], b)
+    for r in doc["ragged"]:
+        assert sf.fft_tune_query_ragged(r["n"]) == r["shape"]
+
+
 def test_ragged_shape_tuning_api():
     sf.fft_tune_clear_ragged()
     try:
         for n in (256, 512, 1024, 2048, 4096, 8192, 16384):
             shapes = sf.fft_ragged_shapes(n)
             assert f"ragged_n{n}_e16" in shapes
+            sf.fft_tune_set_ragged(n, f"ragged_n{n}_e16")
             assert sf.fft_tune_query_ragged(n) == f"ragged_n{n}_e16"
             if n <= 8192:
                 assert f"ragged_n{n}_e8" in shapes
@@ -142,7 +157,8 @@ def test_ragged_shape_tuning_api():
             sf.fft_tune_set_ragged(300, "ragged_n256_e16")
     finally:
         sf.fft_tune_clear_ragged()
-    assert sf.fft_tune_query_ragged(1024) == "ragged_n1024_e16"
+    assert sf.fft_tune_query_ragged(1024) == "ragged_n1024_e8"
+    assert sf.fft_tune_query_ragged(16384) == "ragged_n16384_e16"
 
 
 def test_no_device_reported_cleanly():
@@ -265,10 +281,10 @@ def test_twiddle_tables_rounded_once_from_fp64():
 def test_tune_table_set_query_load(tmp_path):
     sf.fft_tune_clear()
     try:
-        assert sf.fft_tune_query(4096, 256) == "n4096_e16_b1_p4_r16.16.16"
+        assert sf.fft_tune_query(4096, 256) == "n4096_e16_b1_p5_r16.16.16"
         sf.fft_tune_set(4096, 1, 100, "n4096_e8_b1_p4_r8.8.8.8")
         assert sf.fft_tune_query(4096, 50) == "n4096_e8_b1_p4_r8.8.8.8"
-        assert sf.fft_tune_query(4096, 256) == "n4096_e16_b1_p4_r16.16.16"
+        assert sf.fft_tune_query(4096, 256) == "n4096_e16_b1_p5_r16.16.16"
         with pytest.raises(sf.StockfftError):
             sf.fft_tune_set(4096, 1, 10, "n256_e16_b16_p4_r16.16")
         p = tmp_path / "tune.json"
