@@ -197,25 +197,26 @@ struct BuiltinEntry {
   const char* name;
 };
 const BuiltinEntry kBuiltin[] = {
-    {256, 1, 64, "n256_e16_b16_p4_r16.16"},
-    {256, 65, INT64_MAX, "n256_e8_b8_p4_r8.8.4"},
-    {512, 1, 64, "n512_e8_b4_p4_r8.8.8"},
-    {512, 65, 4096, "n512_e16_b2_p4_r16.16.2"},
-    {512, 4097, INT64_MAX, "n512_e8_b4_p4_r8.8.8"},
-    {1024, 1, 64, "n1024_e16_b1_p4_r16.16.4"},
-    {1024, 65, 512, "n1024_e8_b2_p4_r8.8.8.2"},
-    {1024, 513, INT64_MAX, "n1024_e16_b1_p4_r16.16.4"},
-    {2048, 1, 64, "n2048_e4_b1_p4_r4.4.4.4.4.2"},
+    {256, 1, 4096, "n256_e16_b4_p4_r16.16"},
+    {256, 4097, INT64_MAX, "n256_e8_b8_p4_r8.8.4"},
+    {512, 1, 64, "n512_e4_b2_p4_r4.4.4.4.2"},
+    {512, 65, 4096, "n512_e8_b4_p4_r8.8.8"},
+    {512, 4097, INT64_MAX, "n512_e16_b2_p4_r16.16.2"},
+    {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4"},
+    {1024, 65, INT64_MAX, "n1024_e16_b1_p4_r16.16.4"},
+    {2048, 1, 64, "n2048_e16_b1_p4_r16.16.8"},
     {2048, 65, 512, "n2048_e8_b1_p4_r8.8.8.4"},
     {2048, 513, INT64_MAX, "n2048_e16_b1_p4_r16.16.8"},
-    {4096, 1, 64, "n4096_e8_b1_p4_r8.8.8.8"},
-    {4096, 65, 4096, "n4096_e16_b1_p5_r16.16.16"},
+    {4096, 1, 64, "n4096_e16_b1_p4_r16.16.16"},
+    {4096, 65, 512, "n4096_e16_b1_p5_r16.16.16"},
+    {4096, 513, 4096, "n4096_e16_b1_p0_r16.16.16"},
     {4096, 4097, INT64_MAX, "n4096_e32_b1_p4_r16.16.16"},
     {8192, 1, 64, "fs8192_4x2048"},
-    {8192, 65, INT64_MAX, "n8192_e32_b1_p4_r16.16.16.2"},
+    {8192, 65, 512, "n8192_e32_b1_p4_r16.16.16.2"},
+    {8192, 513, INT64_MAX, "n8192_e32_c2_b1_p4_r16.16.16.2"},
     {16384, 1, 64, "fs16384_8x2048"},
-    {16384, 65, 4096, "n16384_e16_b1_p4_r16.16.16.4"},
-    {16384, 4097, INT64_MAX, "n16384_e32_b1_p4_r16.16.16.4"},
+    {16384, 65, 512, "n16384_e16_b1_p4_r16.16.16.4"},
+    {16384, 513, INT64_MAX, "n16384_e32_c2_b1_p4_r16.16.16.4"},
 };
 
 // Single-pass fallback when a four-step choice is not wanted.
@@ -598,10 +599,10 @@ extern "C" int fft_tune_clear(void) {
 // --------------------------------------------------------- introspection
 
 static int barriers_of(const SingleVariant& v) {
-  // One barrier after each LDS write and one after each LDS read that is
-  // followed by another write: the first pass reads and the last pass writes
-  // global memory directly.
-  return v.npass >= 2 ? 2 * v.npass - 3 : 0;
+  // Per exchange round one barrier after the writes and one after the reads,
+  // except after the reads of the last round of the last exchange (the last
+  // pass writes global memory directly, as the first pass reads it).
+  return v.npass >= 2 ? 2 * v.chunks * (v.npass - 1) - 1 : 0;
 }
 
 static std::string radices_json(const SingleVariant& v) {
@@ -618,10 +619,10 @@ static std::string describe_single(const SingleVariant& v) {
   std::snprintf(buf, sizeof buf,
                 "{\"kind\":\"single\",\"name\":\"%s\",\"n\":%d,\"values_per_lane\":%d,"
                 "\"lanes_per_transform\":%d,\"transforms_per_workgroup\":%d,\"pad_log2\":%d,"
-                "\"passes\":%d,\"radices\":%s,\"threads\":%d,\"lds_bytes\":%d,"
-                "\"twiddle_entries\":%d,\"barriers\":%d}",
+                "\"passes\":%d,\"radices\":%s,\"exchange_rounds\":%d,\"threads\":%d,"
+                "\"lds_bytes\":%d,\"twiddle_entries\":%d,\"barriers\":%d}",
                 v.name, v.n, v.e, v.t, v.tpb, v.padlog, v.npass, radices_json(v).c_str(),
-                v.threads, v.lds_bytes, v.tw_elems, barriers_of(v));
+                v.chunks, v.threads, v.lds_bytes, v.tw_elems, barriers_of(v));
   return buf;
 }
 

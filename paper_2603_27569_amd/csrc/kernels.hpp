@@ -32,7 +32,7 @@ __device__ __forceinline__ void global_store_row(const c32 (&a)[S::E], c32* dst,
 // One dispatch per batch (the paper's synthesis rule 1, Section IV-D): each
 // workgroup owns TPB whole transforms; every pass stays on chip.
 template <class S, bool INV>
-__global__ __launch_bounds__(S::THREADS) void k_stockham(const c32* in, c32* out,
+__global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham(const c32* in, c32* out,
                                                          const c32* tw, int64_t rows) {
   __shared__ c32 lds_all[S::TPB * S::LDS_ELEMS];
   const int tid = threadIdx.x;
@@ -83,7 +83,7 @@ __device__ __forceinline__ float wave_group_sum(float v) {
 // Reads x once and writes the gradient once: 16 N bytes per row against the
 // 48 N of three separate launches.
 template <class S>
-__global__ __launch_bounds__(S::THREADS) void k_spectral_energy(
+__global__ __launch_bounds__(S::THREADS, S::WPE) void k_spectral_energy(
     const c32* x, const float* __restrict__ w, const float* __restrict__ scale, c32* grad,
     float* __restrict__ row_loss, const c32* tw, int64_t rows) {
   __shared__ c32 lds_all[S::TPB * S::LDS_ELEMS];
@@ -149,7 +149,7 @@ hipError_t launch_spectral_energy(const void* x, const float* w, const float* sc
 // Range compression (the paper's future work on SAR pipeline fusion):
 // out = (1/N) F^H(conj(h) .* F x) in one kernel.
 template <class S>
-__global__ __launch_bounds__(S::THREADS) void k_matched_filter(const c32* x, const c32* __restrict__ h,
+__global__ __launch_bounds__(S::THREADS, S::WPE) void k_matched_filter(const c32* x, const c32* __restrict__ h,
                                                                c32* out, const c32* tw,
                                                                int64_t rows) {
   __shared__ c32 lds_all[S::TPB * S::LDS_ELEMS];
@@ -202,7 +202,7 @@ hipError_t launch_matched_filter(const void* x, const void* h, void* out, const 
 constexpr int kXcds = 8;
 
 template <class S, int N1, bool INV>
-__global__ __launch_bounds__(S::THREADS) void k_four_step_columns(const c32* x, c32* y,
+__global__ __launch_bounds__(S::THREADS, S::WPE) void k_four_step_columns(const c32* x, c32* y,
                                                                   const c32* tw,
                                                                   int64_t rows) {
   static_assert(S::TPB == 1, "four-step sub-transforms use one transform per workgroup");

@@ -1,15 +1,23 @@
 // Ragged batches: transforms of different power-of-two lengths, packed one
 // after another, run by one persistent kernel launched from a hipGraph.
 //
-// Every persistent workgroup has 1024 lanes and the LDS of the largest shape
-// (a whole 16384-point transform plus pad).  Work is cut into tasks of one
-// size class each; a task is as many transforms of that size as one
-// workgroup holds under the shape chosen for the size (the radix / lanes per
-// transform / LDS tile picked by the autotuner).  Tasks are ordered longest
-// transform first and taken from a device queue counter, so the big
-// transforms start early and the small ones fill the tail.  The counter
-// resets itself: the last workgroup to leave clears it, so the graph holds a
-// single kernel node and no memset.
+// One persistent workgroup of 512 lanes per CU works through a queue of
+// tasks; a task is as many transforms of one length as the workgroup holds
+// under the shape chosen for that length (radix, lanes per transform and
+// exchange tile, picked by the autotuner), 8192 or 16384 elements.  Tasks are
+// grouped by length, longest first (longest processing time first), and
+// handed out by one device counter.
+//
+// The workgroup is software-pipelined: it takes its next ticket and issues the
+// global loads of that task into a second register set before it computes
+// the current one, so a CU keeps loading while it computes.  That needs the
+// register file (about 250 VGPRs per lane, one workgroup per CU) instead of a
+// second resident workgroup.  The queue code is one pipelined loop per
+// length, in queue order: tickets only grow, so a workgroup carries its
+// ticket from one length's loop to the next and never returns.
+//
+// The counter resets itself: the last workgroup to leave clears it, so the
+// graph holds a single kernel node and no memset.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,27 +34,30 @@
 namespace stockfft {
 namespace {
 
-constexpr int kRaggedThreads = 1024;
+constexpr int kRaggedThreads = 512;
+constexpr int kClasses = 7;  // lengths 256 << c, c = 0..6
 
-// Candidate shapes per size class, all with 1024 lanes per workgroup.
-// Radix-16 passes (16 values per lane, 16384 / N transforms per task):
-using G256 = Shape<256, 16, 64, 4, 16, 16>;
-using G512 = Shape<512, 16, 32, 4, 16, 16, 2>;
-using G1024 = Shape<1024, 16, 16, 4, 16, 16, 4>;
-using G2048 = Shape<2048, 16, 8, 4, 16, 16, 8>;
-using G4096 = Shape<4096, 16, 4, 4, 16, 16, 16>;
-using G8192 = Shape<8192, 16, 2, 4, 16, 16, 16, 2>;
-using G16384 = Shape<16384, 16, 1, 4, 16, 16, 16, 4>;
-// Radix-8 passes (8 values per lane, twice the lanes per transform):
-using H256 = Shape<256, 8, 32, 4, 8, 8, 4>;
-using H512 = Shape<512, 8, 16, 4, 8, 8, 8>;
-using H1024 = Shape<1024, 8, 8, 4, 8, 8, 8, 2>;
-using H2048 = Shape<2048, 8, 4, 4, 8, 8, 8, 4>;
-using H4096 = Shape<4096, 8, 2, 4, 8, 8, 8, 8>;
-using H8192 = Shape<8192, 8, 1, 4, 8, 8, 8, 8, 2>;
+// Two candidate shapes per length, all 512 lanes with at most an 8192-element
+// (+ pad) exchange tile.  A: 32 values per lane, two-round exchanges, 16384
+// elements per task.  B: 16 values per lane, whole-tile exchanges, 8192
+// elements per task (for 16384, B is the radix-16 order of the A shape).
+using A256 = ShapeX<2, false, 2, 256, 32, 64, 4, 16, 16>;
+using A512 = ShapeX<2, false, 2, 512, 32, 32, 4, 16, 16, 2>;
+using A1024 = ShapeX<2, false, 2, 1024, 32, 16, 4, 16, 16, 4>;
+using A2048 = ShapeX<2, false, 2, 2048, 32, 8, 4, 16, 16, 8>;
+using A4096 = ShapeX<2, false, 2, 4096, 32, 4, 4, 16, 16, 16>;
+using A8192 = ShapeX<2, false, 2, 8192, 32, 2, 4, 16, 16, 16, 2>;
+using A16384 = ShapeX<2, false, 2, 16384, 32, 1, 4, 8, 16, 16, 8>;
+using B256 = ShapeX<1, true, 2, 256, 16, 32, 4, 16, 16>;
+using B512 = ShapeX<1, true, 2, 512, 16, 16, 4, 16, 16, 2>;
+using B1024 = ShapeX<1, true, 2, 1024, 16, 8, 4, 16, 16, 4>;
+using B2048 = ShapeX<1, true, 2, 2048, 16, 4, 4, 16, 16, 8>;
+using B4096 = ShapeX<1, true, 2, 4096, 16, 2, 4, 16, 16, 16>;
+using B8192 = ShapeX<1, true, 2, 8192, 16, 1, 4, 16, 16, 16, 2>;
+using B16384 = ShapeX<2, false, 2, 16384, 32, 1, 4, 16, 16, 16, 4>;
 
-constexpr int kNumShapes = 13;
-constexpr int kLdsElems = G16384::LDS_ELEMS;
+constexpr int kNumShapes = 2 * kClasses;  // shape 2c + alt
+constexpr int kLdsElems = B8192::LDS_ELEMS;
 
 struct ShapeInfo {
   const char* name;
@@ -62,23 +73,23 @@ constexpr ShapeInfo info(const char* name) {
 }
 
 const ShapeInfo kShapes[kNumShapes] = {
-    info<G256>("ragged_n256_e16"),   info<G512>("ragged_n512_e16"),
-    info<G1024>("ragged_n1024_e16"), info<G2048>("ragged_n2048_e16"),
-    info<G4096>("ragged_n4096_e16"), info<G8192>("ragged_n8192_e16"),
-    info<G16384>("ragged_n16384_e16"), info<H256>("ragged_n256_e8"),
-    info<H512>("ragged_n512_e8"),    info<H1024>("ragged_n1024_e8"),
-    info<H2048>("ragged_n2048_e8"),  info<H4096>("ragged_n4096_e8"),
-    info<H8192>("ragged_n8192_e8"),
+    info<A256>("ragged_n256_e32c2"),       info<B256>("ragged_n256_e16"),
+    info<A512>("ragged_n512_e32c2"),       info<B512>("ragged_n512_e16"),
+    info<A1024>("ragged_n1024_e32c2"),     info<B1024>("ragged_n1024_e16"),
+    info<A2048>("ragged_n2048_e32c2"),     info<B2048>("ragged_n2048_e16"),
+    info<A4096>("ragged_n4096_e32c2"),     info<B4096>("ragged_n4096_e16"),
+    info<A8192>("ragged_n8192_e32c2"),     info<B8192>("ragged_n8192_e16"),
+    info<A16384>("ragged_n16384_e32c2_r8"), info<B16384>("ragged_n16384_e32c2_r16"),
 };
 
 struct Task {
-  int32_t shape;  // index into kShapes
+  int64_t first;  // index of the task's first transform offset in item_off
   int32_t count;  // transforms in this task (<= the shape's TPB)
-  int64_t first;  // index of the first transform's offset in item_off
+  int32_t pad;
 };
 
 struct Queue {
-  int next;  // next task to hand out
+  int next;  // next ticket to hand out
   int done;  // workgroups that have left
 };
 
@@ -89,60 +100,94 @@ struct RaggedArgs {
   const int64_t* item_off;
   Queue* queue;
   int ntasks;
-  const c32* tw[kNumShapes];
+  int end[kClasses];      // one past the last ticket of length 256 << c
+  int alt[kClasses];      // shape chosen for length 256 << c (0 = A, 1 = B)
+  const c32* tw[kClasses];  // twiddle table of the chosen shape
 };
 
-// One task body per shape, kept out of line: inlined together into the one
-// dispatching kernel, the thirteen bodies' register arrays would no longer
-// be promoted to VGPRs.
-template <class S, bool INV>
-__device__ __noinline__ void run_task(const c32* in, c32* out, const int64_t* item_off,
-                                      int64_t first, int count, c32* lds_all, const c32* tw) {
-  static_assert(S::THREADS == kRaggedThreads, "ragged shapes use 1024 lanes");
-  static_assert(S::TPB * S::LDS_ELEMS <= kLdsElems, "shape exceeds the persistent LDS");
+__device__ __forceinline__ int take_ticket(Queue* q, int* s_ticket) {
+  if (threadIdx.x == 0) *s_ticket = atomicAdd(&q->next, 1);
+  __syncthreads();
+  const int v = *s_ticket;
+  __syncthreads();  // every lane has read it before lane 0 overwrites it
+  return v;
+}
+
+// Issues the global loads of task tk's rows into b (the shape's load pattern).
+template <class S>
+__device__ __forceinline__ void fetch(c32 (&b)[S::E], const RaggedArgs& A, const Task& tk) {
   const int tid = threadIdx.x;
   const int slot = tid / S::T;
   const int t = tid - slot * S::T;
-  const bool live = slot < count;
-  const int64_t off = live ? item_off[first + slot] : 0;
-  c32* lds = lds_all + slot * S::LDS_ELEMS;
-  c32 a[S::E];
-  global_load_row<S>(a, in + off, t, live);
-  run_passes<S, INV>(a, lds, tw, t);
-  global_store_row<S>(a, out + off, t, live);
+  const bool live = slot < tk.count;
+  const int64_t off = live ? A.item_off[tk.first + slot] : 0;
+  global_load_row<S>(b, A.in + off, t, live);
+}
+
+template <class S, bool INV>
+__device__ __forceinline__ void compute_store(c32 (&a)[S::E], const RaggedArgs& A, const Task& tk,
+                                              c32* lds_all, const c32* tw) {
+  // An optimization barrier: keeps the table loads inside the task loop
+  // (hoisted out of it they would stay live across every task).
+  asm volatile("" : "+s"(tw));
+  const int tid = threadIdx.x;
+  const int slot = tid / S::T;
+  const int t = tid - slot * S::T;
+  const bool live = slot < tk.count;
+  const int64_t off = live ? A.item_off[tk.first + slot] : 0;
+  run_passes<S, INV>(a, lds_all + slot * S::LDS_ELEMS, tw, t);
+  global_store_row<S>(a, A.out + off, t, live);
+}
+
+// Processes tickets below `end` (all of one length) with shape S, loading
+// task i+1 while computing task i.  Returns the first ticket at or past end.
+template <class S, bool INV>
+__device__ __forceinline__ int run_class(int ticket, int end, const RaggedArgs& A, c32* lds_all,
+                                         int* s_ticket, const c32* tw) {
+  static_assert(S::THREADS == kRaggedThreads, "ragged shapes use 512 lanes");
+  static_assert(S::TPB * S::LDS_ELEMS <= kLdsElems, "shape exceeds the exchange tile");
+  if (ticket >= end) return ticket;
+  Task tc = A.tasks[ticket];
+  c32 b[S::E];
+  fetch<S>(b, A, tc);
+  for (;;) {
+    c32 a[S::E];
+#pragma unroll
+    for (int m = 0; m < S::E; ++m) a[m] = b[m];
+    const int nxt = take_ticket(A.queue, s_ticket);
+    Task tn = tc;
+    if (nxt < end) {
+      tn = A.tasks[nxt];
+      fetch<S>(b, A, tn);
+    }
+    compute_store<S, INV>(a, A, tc, lds_all, tw);
+    if (nxt >= end) return nxt;
+    tc = tn;
+  }
+}
+
+template <class SA, class SB, bool INV>
+__device__ __forceinline__ int run_length(int c, int ticket, const RaggedArgs& A, c32* lds_all,
+                                          int* s_ticket) {
+  if (A.alt[c] == 0) return run_class<SA, INV>(ticket, A.end[c], A, lds_all, s_ticket, A.tw[c]);
+  return run_class<SB, INV>(ticket, A.end[c], A, lds_all, s_ticket, A.tw[c]);
 }
 
 template <bool INV>
-__global__ __launch_bounds__(kRaggedThreads) void k_ragged(RaggedArgs A) {
+__global__ __launch_bounds__(kRaggedThreads, 2) void k_ragged(RaggedArgs A) {
   __shared__ c32 lds_all[kLdsElems];
-  __shared__ int s_task;
-  for (;;) {
-    if (threadIdx.x == 0) s_task = atomicAdd(&A.queue->next, 1);
-    __syncthreads();
-    const int task = s_task;
-    __syncthreads();  // every lane has read s_task before lane 0 rewrites it
-    if (task >= A.ntasks) break;
-    const Task tk = A.tasks[task];
-    switch (tk.shape) {
-      case 0: run_task<G256, INV>(A.in, A.out, A.item_off, tk.first, tk.count, lds_all, A.tw[0]); break;
-      case 1: run_task<G512, INV>(A.in, A.out, A.item_off, tk.first, tk.count, lds_all, A.tw[1]); break;
-      case 2: run_task<G1024, INV>(A.in, A.out, A.item_off, tk.first, tk.count, lds_all, A.tw[2]); break;
-      case 3: run_task<G2048, INV>(A.in, A.out, A.item_off, tk.first, tk.count, lds_all, A.tw[3]); break;
-      case 4: run_task<G4096, INV>(A.in, A.out, A.item_off, tk.first, tk.count, lds_all, A.tw[4]); break;
-      case 5: run_task<G8192, INV>(A.in, A.out, A.item_off, tk.first, tk.count, lds_all, A.tw[5]); break;
-      case 6: run_task<G16384, INV>(A.in, A.out, A.item_off, tk.first, tk.count, lds_all, A.tw[6]); break;
-      case 7: run_task<H256, INV>(A.in, A.out, A.item_off, tk.first, tk.count, lds_all, A.tw[7]); break;
-      case 8: run_task<H512, INV>(A.in, A.out, A.item_off, tk.first, tk.count, lds_all, A.tw[8]); break;
-      case 9: run_task<H1024, INV>(A.in, A.out, A.item_off, tk.first, tk.count, lds_all, A.tw[9]); break;
-      case 10: run_task<H2048, INV>(A.in, A.out, A.item_off, tk.first, tk.count, lds_all, A.tw[10]); break;
-      case 11: run_task<H4096, INV>(A.in, A.out, A.item_off, tk.first, tk.count, lds_all, A.tw[11]); break;
-      default: run_task<H8192, INV>(A.in, A.out, A.item_off, tk.first, tk.count, lds_all, A.tw[12]); break;
-    }
-    __syncthreads();  // the task's last LDS reads are done before the next task writes
-  }
-  // Every workgroup took exactly one out-of-range ticket before arriving
-  // here, so when the last one arrives nobody touches the counter again in
-  // this launch: it resets both counters for the next launch.
+  __shared__ int s_ticket;
+  int ticket = take_ticket(A.queue, &s_ticket);
+  ticket = run_length<A16384, B16384, INV>(6, ticket, A, lds_all, &s_ticket);
+  ticket = run_length<A8192, B8192, INV>(5, ticket, A, lds_all, &s_ticket);
+  ticket = run_length<A4096, B4096, INV>(4, ticket, A, lds_all, &s_ticket);
+  ticket = run_length<A2048, B2048, INV>(3, ticket, A, lds_all, &s_ticket);
+  ticket = run_length<A1024, B1024, INV>(2, ticket, A, lds_all, &s_ticket);
+  ticket = run_length<A512, B512, INV>(1, ticket, A, lds_all, &s_ticket);
+  ticket = run_length<A256, B256, INV>(0, ticket, A, lds_all, &s_ticket);
+  // Every workgroup leaves holding exactly one ticket at or past ntasks, so
+  // when the last one arrives nobody touches the counter again in this
+  // launch: it resets both counters for the next launch.
   if (threadIdx.x == 0) {
     __threadfence();
     const int d = atomicAdd(&A.queue->done, 1);
@@ -159,12 +204,13 @@ int shape_index(const char* name) {
   return -1;
 }
 
-// Built-in per-size shape: the autotuner's choice on MI355X (radix-8 lanes for
-// N <= 8192, radix-16 for 16384, the only shape that fits).
-int builtin_shape(int64_t n) { return n == 16384 ? 6 : 7 + ilog2(n) - 8; }
+// Built-in per-length shape: the autotuner's choice on MI355X (the package's
+// tune_gfx950.json).
+constexpr int kBuiltinShape[kClasses] = {0, 3, 4, 7, 8, 11, 12};
+int builtin_shape(int64_t n) { return kBuiltinShape[ilog2(n) - 8]; }
 
 std::mutex g_rtune_mu;
-int g_rtune[7] = {-1, -1, -1, -1, -1, -1, -1};
+int g_rtune[kClasses] = {-1, -1, -1, -1, -1, -1, -1};
 
 }  // namespace
 }  // namespace stockfft
@@ -178,12 +224,12 @@ struct stockfft_ragged_s {
   int64_t total = 0;  // sum of sizes (elements)
   int ntasks = 0;
   int grid = 0;
-  int shape_of_class[7] = {};
+  int shape_of_class[kClasses] = {};
   int64_t class_count[7] = {};
   Task* d_tasks = nullptr;
   int64_t* d_off = nullptr;
   Queue* d_queue = nullptr;
-  void* d_tw[kNumShapes] = {};
+  void* d_tw[kClasses] = {};
   RaggedArgs args{};
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -265,7 +311,9 @@ extern "C" int fft_plan_ragged(fft_ragged_plan_t* plan, const int64_t* sizes, in
     const int64_t k = (int64_t)item_off.size() - first;
     p->class_count[c] = k;
     for (int64_t j = 0; j < k; j += tpb)
-      tasks.push_back(Task{shape, (int32_t)std::min<int64_t>(tpb, k - j), first + j});
+      tasks.push_back(Task{first + j, (int32_t)std::min<int64_t>(tpb, k - j), 0});
+    p->args.end[c] = (int)tasks.size();
+    p->args.alt[c] = shape & 1;
   }
   p->ntasks = (int)tasks.size();
 
@@ -278,13 +326,11 @@ extern "C" int fft_plan_ragged(fft_ragged_plan_t* plan, const int64_t* sizes, in
   p->grid = std::max(1, std::min(cus, p->ntasks));
 
   std::vector<float> tw;
-  for (int s = 0; s < kNumShapes && !rc; ++s) {
-    bool used = false;
-    for (int c = 0; c < 7; ++c) used |= p->shape_of_class[c] == s;
-    if (!used) continue;
-    SingleVariant v = as_variant(kShapes[s]);
+  for (int c = 0; c < kClasses && !rc; ++c) {
+    if (p->class_count[c] == 0) continue;
+    SingleVariant v = as_variant(kShapes[p->shape_of_class[c]]);
     build_stockham_twiddles(v, tw);
-    rc = upload(tw, &p->d_tw[s]);
+    rc = upload(tw, &p->d_tw[c]);
   }
   if (!rc) {
     e = hipMalloc((void**)&p->d_tasks, tasks.size() * sizeof(Task));
@@ -300,7 +346,7 @@ extern "C" int fft_plan_ragged(fft_ragged_plan_t* plan, const int64_t* sizes, in
     if (e != hipSuccess) rc = hip_fail(e);
   }
   // Per-size plain plans for the comparison entry point.
-  for (int c = 0; c < 7 && !rc; ++c)
+  for (int c = 0; c < kClasses && !rc; ++c)
     if (p->class_count[c] > 0)
       rc = fft_plan(&p->plain[c], int64_t(256) << c, p->class_count[c], direction);
   if (rc) {
@@ -311,7 +357,7 @@ extern "C" int fft_plan_ragged(fft_ragged_plan_t* plan, const int64_t* sizes, in
   p->args.item_off = p->d_off;
   p->args.queue = p->d_queue;
   p->args.ntasks = p->ntasks;
-  for (int s = 0; s < kNumShapes; ++s) p->args.tw[s] = static_cast<const c32*>(p->d_tw[s]);
+  for (int c = 0; c < kClasses; ++c) p->args.tw[c] = static_cast<const c32*>(p->d_tw[c]);
   register_handle(p);
   *plan = p;
   return FFT_SUCCESS;

@@ -146,9 +146,25 @@ struct RadixList {
 
 // N points, E values per lane, TPB transforms per workgroup, LDS pad of one
 // element every 2^PADLOG (0 = no pad), radices of the passes in order.
-template <int N_, int E_, int TPB_, int PADLOG_, int... Rs>
-struct Shape {
+//
+// C > 1 splits every exchange into C rounds through a buffer of N/C elements
+// (plus pad): the transform stays whole in registers and the LDS is only the
+// pipe between them, so a large transform needs a fraction of the LDS and
+// several workgroups fit on one CU.  In the exchange after pass p, butterfly
+// b of a lane writes only to chunk floor(b C / BPT_p) and read slot m comes
+// from chunk floor(m C / E), both known at compile time, provided C divides
+// BPT_p = E / R_p and Ns_{p+1} <= N / C (checked below).
+//
+// PF = true loads each pass's twiddles one pass ahead (latency hidden behind a
+// pass, registers spent); PF = false loads them at the start of their pass
+// (for shapes that need the registers for occupancy).  WPE is the minimum
+// number of waves per SIMD the compiler must allow for (1 = no constraint).
+template <int C_, bool PF_, int WPE_, int N_, int E_, int TPB_, int PADLOG_, int... Rs>
+struct ShapeX {
   using L = RadixList<Rs...>;
+  static constexpr int C = C_;
+  static constexpr bool PF = PF_;
+  static constexpr int WPE = WPE_;
   static constexpr int N = N_;
   static constexpr int E = E_;
   static constexpr int T = N_ / E_;
@@ -156,7 +172,8 @@ struct Shape {
   static constexpr int PADLOG = PADLOG_;
   static constexpr int P = L::P;
   static constexpr int THREADS = T * TPB;
-  static constexpr int LDS_ELEMS = N + (PADLOG ? (N >> PADLOG) : 0);
+  static constexpr int CHUNK = N / C;
+  static constexpr int LDS_ELEMS = CHUNK + (PADLOG ? (CHUNK >> PADLOG) : 0);
   static constexpr int radix(int p) { return L::r[p]; }
   static constexpr int ns(int p) {
     int s = 1;
@@ -179,8 +196,11 @@ struct Shape {
   }();
   static constexpr bool valid() {
     if (ns(P) != N || T * E != N || THREADS > 1024 || THREADS < 1) return false;
+    if (C < 1 || N % C != 0) return false;
     for (int i = 0; i < P; ++i)
       if (E % L::r[i] != 0) return false;
+    for (int i = 0; i + 1 < P; ++i)
+      if ((E / L::r[i]) % C != 0 || ns(i + 1) > CHUNK) return false;
     return true;
   }
   static_assert(valid(), "inconsistent Stockham shape");
@@ -190,11 +210,15 @@ struct Shape {
   }
 };
 
+// The common case: whole-transform exchange buffer, twiddles one pass ahead.
+template <int N_, int E_, int TPB_, int PADLOG_, int... Rs>
+using Shape = ShapeX<1, true, 1, N_, E_, TPB_, PADLOG_, Rs...>;
+
 // ------------------------------------------------------------ one pass
 
 // Issues the global loads of the twiddles this lane needs in pass p into
-// registers; the caller consumes them one pass later, so their latency hides
-// behind a whole pass of arithmetic and exchange.
+// registers.  With prefetch the caller consumes them one pass later, so their
+// latency hides behind a whole pass of arithmetic and exchange.
 template <class S, int p>
 __device__ __forceinline__ void load_twiddles(c32 (&w)[S::TW_REGS], const c32* tw, int t) {
   if constexpr (p > 0 && p < S::P) {
@@ -208,26 +232,48 @@ __device__ __forceinline__ void load_twiddles(c32 (&w)[S::TW_REGS], const c32* t
 #pragma unroll
       for (int r = 1; r < R; ++r) w[b * (R - 1) + (r - 1)] = twp[(r - 1) * NS + k];
     }
-    // Keep the loads here: the scheduler would otherwise sink them to their
-    // use, past the exchange barriers, and expose their latency.
-    __builtin_amdgcn_sched_barrier(0);
+    // Keep prefetched loads here: the scheduler would otherwise sink them to
+    // their use, past the exchange barriers, and expose their latency.
+    if constexpr (S::PF) __builtin_amdgcn_sched_barrier(0);
   }
 }
 
-// Twiddle multiply of pass p (twiddles already in registers), then the next
-// pass's twiddle loads are issued, then the butterflies run.
+// Twiddle multiply and butterflies of pass p.  With prefetch, w[] holds the
+// pass-p twiddles on entry and the pass-(p+1) loads are issued after they
+// are applied; without, the pass-p twiddles are loaded here.
 template <class S, int p, bool INV>
 __device__ __forceinline__ void pass_compute(c32 (&a)[S::E], c32 (&w)[S::TW_REGS],
                                              const c32* tw, int t) {
   constexpr int R = S::radix(p);
   constexpr int BPT = S::E / R;
+  if constexpr (!S::PF) {
+    // One butterfly at a time: its R - 1 twiddles are loaded, applied and
+    // dead before the next butterfly's are needed (fewest live registers).
+    constexpr int NS = S::ns(p);
+#pragma unroll
+    for (int b = 0; b < BPT; ++b) {
+      c32 v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = a[b + r * BPT];
+      if constexpr (p > 0) {
+        const c32* twp = tw + S::tw_off(p);
+        const int k = (t + b * S::T) & (NS - 1);
+#pragma unroll
+        for (int r = 1; r < R; ++r) v[r] = ctw<INV>(v[r], twp[(r - 1) * NS + k]);
+      }
+      Dft<R, INV>::run(v);
+#pragma unroll
+      for (int r = 0; r < R; ++r) a[b + r * BPT] = v[r];
+    }
+    return;
+  }
   if constexpr (p > 0) {
 #pragma unroll
     for (int b = 0; b < BPT; ++b)
 #pragma unroll
       for (int r = 1; r < R; ++r) a[b + r * BPT] = ctw<INV>(a[b + r * BPT], w[b * (R - 1) + (r - 1)]);
   }
-  load_twiddles<S, p + 1>(w, tw, t);
+  if constexpr (S::PF) load_twiddles<S, p + 1>(w, tw, t);
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     c32 v[R];
@@ -239,41 +285,47 @@ __device__ __forceinline__ void pass_compute(c32 (&a)[S::E], c32 (&w)[S::TW_REGS
   }
 }
 
-// Write pass p's outputs into the exchange buffer at the Stockham positions.
+// Exchange after pass p: write the outputs to their Stockham positions and
+// read the next pass's inputs (positions t + m T), in C rounds of N/C
+// elements.  The buffer must be free on entry; it is free again on return
+// unless the next pass is the last (which reads nothing more from it).
 template <class S, int p>
-__device__ __forceinline__ void pass_store_lds(const c32 (&a)[S::E], c32* lds, int t) {
+__device__ __forceinline__ void exchange(c32 (&a)[S::E], c32* lds, int t) {
   constexpr int R = S::radix(p);
   constexpr int NS = S::ns(p);
   constexpr int BPT = S::E / R;
+  constexpr int BPC = BPT / S::C;  // butterflies per chunk
+  constexpr int MPC = S::E / S::C;  // read slots per chunk
+  c32 nxt[S::E];
 #pragma unroll
-  for (int b = 0; b < BPT; ++b) {
-    const int j = t + b * S::T;
-    const int base = (j / NS) * NS * R + (j & (NS - 1));
+  for (int h = 0; h < S::C; ++h) {
+    if (h > 0) __syncthreads();  // the previous round's reads are done
 #pragma unroll
-    for (int k = 0; k < R; ++k) lds[S::pidx(base + k * NS)] = a[b + k * BPT];
+    for (int b = h * BPC; b < (h + 1) * BPC; ++b) {
+      const int j = t + b * S::T;
+      const int base = (j / NS) * NS * R + (j & (NS - 1)) - h * S::CHUNK;
+#pragma unroll
+      for (int k = 0; k < R; ++k) lds[S::pidx(base + k * NS)] = a[b + k * BPT];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = h * MPC; m < (h + 1) * MPC; ++m) nxt[m] = lds[S::pidx(t + m * S::T - h * S::CHUNK)];
   }
-}
-
-template <class S>
-__device__ __forceinline__ void lds_load_all(c32 (&a)[S::E], const c32* lds, int t) {
 #pragma unroll
-  for (int m = 0; m < S::E; ++m) a[m] = lds[S::pidx(t + m * S::T)];
+  for (int m = 0; m < S::E; ++m) a[m] = nxt[m];
+  if constexpr (p + 2 < S::P) __syncthreads();  // all reads done before the next overwrite
 }
 
 // Runs passes p..P-1.  On entry a[] holds the pass-p inputs in the register
-// convention and w[] the pass-p twiddles (nothing for p = 0).  On exit a[]
-// holds the transform in natural order, a[m] at position t + m T.  Between
-// passes the data goes through lds, which must be free to overwrite on entry
-// (the caller's barrier).
+// convention (and, with prefetch, w[] the pass-p twiddles).  On exit a[]
+// holds the transform in natural order, a[m] at position t + m T.  The
+// exchange buffer must be free to overwrite on entry (the caller's barrier).
 template <class S, int p, bool INV>
 __device__ __forceinline__ void run_passes_from(c32 (&a)[S::E], c32 (&w)[S::TW_REGS], c32* lds,
                                                 const c32* tw, int t) {
   pass_compute<S, p, INV>(a, w, tw, t);
   if constexpr (p + 1 < S::P) {
-    pass_store_lds<S, p>(a, lds, t);
-    __syncthreads();
-    lds_load_all<S>(a, lds, t);
-    if constexpr (p + 2 < S::P) __syncthreads();  // all reads done before the next overwrite
+    exchange<S, p>(a, lds, t);
     run_passes_from<S, p + 1, INV>(a, w, lds, tw, t);
   }
 }

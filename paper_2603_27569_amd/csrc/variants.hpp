@@ -34,6 +34,7 @@ struct SingleVariant {
   const char* name;
   int n, e, t, tpb, padlog, npass;
   int radix[kMaxPasses];
+  int chunks;  // exchange rounds per pass (the LDS holds N / chunks elements per transform)
   int threads;
   int lds_bytes;
   int tw_elems;

@@ -4,6 +4,7 @@
 #include "variant_maker.hpp"
 
 using stockfft::Shape;
+using stockfft::ShapeX;
 using stockfft::make_variant;
 
 STOCKFFT_VARIANT_GROUP(variants_large,
@@ -11,4 +12,7 @@ STOCKFFT_VARIANT_GROUP(variants_large,
   make_variant<Shape<8192, 16, 1, 4, 16, 16, 16, 2>>("n8192_e16_b1_p4_r16.16.16.2"),
   make_variant<Shape<8192, 32, 1, 4, 16, 16, 16, 2>>("n8192_e32_b1_p4_r16.16.16.2"),
   make_variant<Shape<16384, 16, 1, 4, 16, 16, 16, 4>>("n16384_e16_b1_p4_r16.16.16.4"),
-  make_variant<Shape<16384, 32, 1, 4, 16, 16, 16, 4>>("n16384_e32_b1_p4_r16.16.16.4"))
+  make_variant<Shape<16384, 32, 1, 4, 16, 16, 16, 4>>("n16384_e32_b1_p4_r16.16.16.4"),
+  // Two-round exchanges: half the LDS, two (16384) or four (8192) workgroups per CU.
+  make_variant<ShapeX<2, false, 4, 16384, 32, 1, 4, 16, 16, 16, 4>>("n16384_e32_c2_b1_p4_r16.16.16.4"),
+  make_variant<ShapeX<2, false, 4, 8192, 32, 1, 4, 16, 16, 16, 2>>("n8192_e32_c2_b1_p4_r16.16.16.2"))

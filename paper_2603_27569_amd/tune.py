@@ -4,14 +4,14 @@ For every transform length and batch bucket it times each compiled kernel
 variant -- values per lane (hence the radix and lanes per transform),
 transforms per workgroup, LDS padding, and for N >= 8192 the four-step
 splits -- through the C ABI, and keeps the fastest.  For the ragged
-persistent kernel it times each compiled shape of every length on a batch
-of that length alone and keeps the fastest.  The result is a JSON file that
+persistent kernel it picks one compiled shape per length by coordinate
+descent on a mixed ragged batch.  The result is a JSON file that
 ``fft_tune_load`` (or the STOCKFFT_TUNE_CACHE environment variable) applies:
 
   {"arch": "gfx950", "cus": 256, "hip_runtime": ..., "entries": [
      {"n": 4096, "batch_min": 129, "batch_max": 1024,
       "variant": "n4096_e16_b1_p4_r16.16.16", "us": ..., "candidates": {...}}],
-   "ragged": [{"n": 4096, "shape": "ragged_n4096_e16", "us": ...}]}
+   "ragged": [{"n": 4096, "shape": "ragged_n4096_e16", "batch_us": ...}]}
 
 Timing: back-to-back launches over a ring of independent buffers larger
 than the Infinity Cache, bracketed by HIP events on the launch stream; the
@@ -99,33 +99,57 @@ def tune_plain(torch, dev, stream, sizes=SIZES, buckets=BUCKETS, iters=30, log=p
     return entries
 
 
-def tune_ragged(torch, dev, stream, count_per_size=256, iters=20, log=print):
-    """Time each ragged shape of each length on a single-length batch."""
-    out = []
+def tune_ragged(torch, dev, stream, sizes=None, iters=20, sweeps=2, log=print):
+    """Choose the ragged kernel's shape per length on a mixed ragged batch.
+
+    The shapes interact (they share the persistent workgroups and the task
+    queue), so they are tuned together: coordinate descent over the lengths,
+    each step timing every shape of one length with the others fixed.  The
+    default batch is 2000 lengths drawn log-uniformly from 256..16384."""
+    if sizes is None:
+        from .workloads import ragged_sizes
+        sizes = ragged_sizes()
+    sizes = [int(s) for s in sizes]
+    total = sum(sizes)
+    k = max(2, math.ceil(RING_BYTES / (2 * total * 8)))
+    xs = [torch.randn(total, dtype=torch.complex64, device=dev) for _ in range(k)]
+    ys = [torch.empty_like(xs[0]) for _ in range(k)]
     cs = stream.cuda_stream
+    present = sorted(set(sizes), reverse=True)
+    choice = {n: fft_ragged_shapes(n)[0] for n in present}
+    history = {n: {} for n in present}
+
+    def timed():
+        for n, sh in choice.items():
+            fft_tune_set_ragged(n, sh)
+        p = RaggedPlan(sizes)
+        us = _time(torch, stream, lambda i: p.exec(xs[i % k].data_ptr(), ys[i % k].data_ptr(), cs),
+                   iters)
+        p.close()
+        return us
+
     try:
-        for n in SIZES:
-            sizes = [n] * count_per_size
-            total = n * count_per_size
-            k = max(2, math.ceil(RING_BYTES / (2 * total * 8)))
-            xs = [torch.randn(total, dtype=torch.complex64, device=dev) for _ in range(k)]
-            ys = [torch.empty_like(xs[0]) for _ in range(k)]
-            times = {}
-            for shape in fft_ragged_shapes(n):
-                fft_tune_set_ragged(n, shape)
-                p = RaggedPlan(sizes)
-                times[shape] = _time(torch, stream,
-                                     lambda i: p.exec(xs[i % k].data_ptr(), ys[i % k].data_ptr(), cs),
-                                     iters)
-                p.close()
-            best = min(times, key=times.get)
-            log(f"tune ragged n={n} -> {best} {times[best]:.2f} us")
-            out.append({"n": n, "shape": best, "us": round(times[best], 3),
-                        "candidates": {k2: round(v, 3) for k2, v in times.items()}})
-            del xs, ys
+        best_us = timed()
+        for _ in range(sweeps):
+            for n in present:
+                for shape in fft_ragged_shapes(n):
+                    if shape == choice[n]:
+                        history[n][shape] = round(best_us, 3)
+                        continue
+                    old = choice[n]
+                    choice[n] = shape
+                    us = timed()
+                    history[n][shape] = round(us, 3)
+                    if us < best_us:
+                        best_us = us
+                    else:
+                        choice[n] = old
+                log(f"tune ragged n={n} -> {choice[n]} (batch {best_us:.2f} us)")
     finally:
         fft_tune_clear_ragged()
-    return out
+    del xs, ys
+    return [{"n": n, "shape": choice[n], "batch_us": round(best_us, 3), "candidates": history[n]}
+            for n in sorted(present)]
 
 
 def run(out_path, quick=False, log=print):
@@ -135,8 +159,8 @@ def run(out_path, quick=False, log=print):
     props = torch.cuda.get_device_properties(dev)
     buckets = BUCKETS if not quick else ((1, 2 ** 62, 1024),)
     entries = tune_plain(torch, dev, stream, buckets=buckets, iters=10 if quick else 30, log=log)
-    ragged = tune_ragged(torch, dev, stream, count_per_size=64 if quick else 256,
-                         iters=5 if quick else 20, log=log)
+    ragged = tune_ragged(torch, dev, stream, iters=5 if quick else 20, sweeps=1 if quick else 2,
+                         log=log)
     doc = {"arch": props.gcnArchName.split(":")[0], "cus": props.multi_processor_count,
            "hip_runtime": getattr(torch.version, "hip", None), "entries": entries, "ragged": ragged}
     with open(out_path, "w") as f:

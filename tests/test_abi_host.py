@@ -112,12 +112,12 @@ def test_tune_file_with_four_step_and_ragged_entries(tmp_path):
             {"n": 16384, "batch_min": 9, "batch_max": 10 ** 12, "variant": "n16384_e32_b1_p4_r16.16.16.4"},
             {"n": 512, "batch_min": 1, "batch_max": 10 ** 12, "variant": "n512_e8_b4_p4_r8.8.8",
              "candidates": {"n512_e4_b2_p4_r4.4.4.4.2": 3.0}}],
-            "ragged": [{"n": 2048, "shape": "ragged_n2048_e8", "us": 2.0}]}))
+            "ragged": [{"n": 2048, "shape": "ragged_n2048_e16", "us": 2.0}]}))
         sf.fft_tune_load(str(p))
         assert sf.fft_tune_query(16384, 4) == "fs16384_4x4096"
         assert sf.fft_tune_query(16384, 1024) == "n16384_e32_b1_p4_r16.16.16.4"
         assert sf.fft_tune_query(512, 77) == "n512_e8_b4_p4_r8.8.8"
-        assert sf.fft_tune_query_ragged(2048) == "ragged_n2048_e8"
+        assert sf.fft_tune_query_ragged(2048) == "ragged_n2048_e16"
         sf.fft_tune_set(8192, 1, 10, "fs8192_2x4096")
         assert sf.fft_tune_query(8192, 3) == "fs8192_2x4096"
     finally:
@@ -141,24 +141,22 @@ def test_builtin_table_is_the_shipped_tuner_output():
 
 def test_ragged_shape_tuning_api():
     sf.fft_tune_clear_ragged()
+    builtin = {n: sf.fft_tune_query_ragged(n) for n in (256, 512, 1024, 2048, 4096, 8192, 16384)}
     try:
-        for n in (256, 512, 1024, 2048, 4096, 8192, 16384):
+        for n in builtin:
             shapes = sf.fft_ragged_shapes(n)
-            assert f"ragged_n{n}_e16" in shapes
-            sf.fft_tune_set_ragged(n, f"ragged_n{n}_e16")
-            assert sf.fft_tune_query_ragged(n) == f"ragged_n{n}_e16"
-            if n <= 8192:
-                assert f"ragged_n{n}_e8" in shapes
-                sf.fft_tune_set_ragged(n, f"ragged_n{n}_e8")
-                assert sf.fft_tune_query_ragged(n) == f"ragged_n{n}_e8"
+            assert len(shapes) == 2 and builtin[n] in shapes
+            assert all(sh.startswith(f"ragged_n{n}_") for sh in shapes)
+            for sh in shapes:
+                sf.fft_tune_set_ragged(n, sh)
+                assert sf.fft_tune_query_ragged(n) == sh
         with pytest.raises(sf.StockfftError):
-            sf.fft_tune_set_ragged(16384, "ragged_n256_e16")
+            sf.fft_tune_set_ragged(16384, sf.fft_ragged_shapes(256)[0])
         with pytest.raises(sf.StockfftError):
-            sf.fft_tune_set_ragged(300, "ragged_n256_e16")
+            sf.fft_tune_set_ragged(300, sf.fft_ragged_shapes(256)[0])
     finally:
         sf.fft_tune_clear_ragged()
-    assert sf.fft_tune_query_ragged(1024) == "ragged_n1024_e8"
-    assert sf.fft_tune_query_ragged(16384) == "ragged_n16384_e16"
+    assert {n: sf.fft_tune_query_ragged(n) for n in builtin} == builtin
 
 
 def test_no_device_reported_cleanly():
@@ -191,10 +189,14 @@ def test_variant_inventory():
         assert v["lanes_per_transform"] * v["values_per_lane"] == v["n"]
         assert all(v["values_per_lane"] % r == 0 for r in v["radices"])
         assert v["threads"] == v["lanes_per_transform"] * v["transforms_per_workgroup"] <= 1024
-        pad = (v["n"] >> v["pad_log2"]) if v["pad_log2"] else 0
-        assert v["lds_bytes"] == v["transforms_per_workgroup"] * (v["n"] + pad) * 8
+        chunk = v["n"] // v["exchange_rounds"]
+        pad = (chunk >> v["pad_log2"]) if v["pad_log2"] else 0
+        assert v["lds_bytes"] == v["transforms_per_workgroup"] * (chunk + pad) * 8
         assert v["lds_bytes"] <= 160 * 1024  # gfx950 LDS per workgroup
-        assert v["barriers"] == (2 * v["passes"] - 3 if v["passes"] > 1 else 0)
+        c = v["exchange_rounds"]
+        assert v["barriers"] == (2 * c * (v["passes"] - 1) - 1 if v["passes"] > 1 else 0)
+        if c > 1:  # every exchange pass splits evenly into the rounds
+            assert all((v["values_per_lane"] // r) % c == 0 for r in v["radices"][:-1])
 
 
 def test_paper_table_v_radix4_shapes():
