@@ -144,14 +144,15 @@ int fft_exec_matched_filter(fft_plan_t plan, const void *x, const void *h, void 
  * fft_plan_ragged -- plan a ragged batch: `count` transforms of different
  * power-of-two lengths, packed one after another in one buffer (transform i
  * starts at element offset sum_{j<i} sizes[j]).  All run in one persistent
- * kernel launch, captured once in a hipGraph; workgroups take work items
- * from a device queue in longest-first order and run each size with its own
- * tuned shape.
+ * kernel launch, captured once in a hipGraph.  Each length runs with its
+ * own tuned shape; the transforms are grouped into tasks of about equal
+ * cost, dealt to the workgroups once, here, by a longest-first list schedule
+ * (no device queue or atomic).
  *   sizes      host array of `count` lengths, each a power of two in
  *              [256, 16384]; copied, the caller keeps ownership.
  *   count      >= 1.
  *   direction  FFT_FORWARD or FFT_BACKWARD.
- * The plan owns its descriptors, twiddle tables, queue counters and graph.
+ * The plan owns its task lists, twiddle tables and graph.
  * Errors: FFT_INVALID_POINTER, FFT_INVALID_SIZE (with the first bad entry),
  * FFT_INVALID_BATCH (count < 1), FFT_INVALID_DIRECTION, FFT_NO_DEVICE,
  * FFT_ALLOC_FAILED, FFT_HIP_ERROR.
@@ -163,7 +164,7 @@ int fft_plan_ragged(fft_ragged_plan_t *plan, const int64_t *sizes, int64_t count
  * transform.  in/out: device, sum(sizes) complex64, 8-byte aligned; in == out
  * allowed.  The first call on a stream instantiates the graph; later calls
  * update its pointer arguments and relaunch it.  Asynchronous; the plan must
- * not run on two streams at once (shared queue counter).
+ * not run on two streams at once (calls rewrite its one graph's arguments).
  * Errors: FFT_INVALID_PLAN, FFT_INVALID_POINTER, FFT_MISALIGNED, FFT_OVERLAP,
  * FFT_HIP_ERROR.
  */

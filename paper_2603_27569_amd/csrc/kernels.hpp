@@ -66,10 +66,10 @@ hipError_t launch_single(const void* in, void* out, const void* tw, int64_t batc
   return hipGetLastError();
 }
 
-// Sum v over the T lanes that own one transform.  Returns the total in lane
-// t == 0 of each transform (other lanes: partial values).  `red` holds one
-// float per wave; the caller places a barrier between this call's LDS write
-// and finish_row_sum().
+// Sum v over the lanes of one wave that own the same transform (all 64 lanes
+// when a transform spans several waves).  Every one of those lanes returns
+// the wave's sum; a transform wider than a wave adds its waves' sums
+// afterwards.
 template <class S>
 __device__ __forceinline__ float wave_group_sum(float v) {
   constexpr int W = S::T < 64 ? S::T : 64;

@@ -1,29 +1,35 @@
 // Ragged batches: transforms of different power-of-two lengths, packed one
 // after another, run by one persistent kernel launched from a hipGraph.
 //
-// One persistent workgroup of 512 lanes per CU works through a queue of
+// One persistent workgroup of 512 lanes per CU works through a list of
 // tasks; a task is as many transforms of one length as the workgroup holds
 // under the shape chosen for that length (radix, lanes per transform and
-// exchange tile, picked by the autotuner), 8192 or 16384 elements.  Tasks are
-// grouped by length, longest first (longest processing time first), and
-// handed out by one device counter.
+// exchange tile, picked by the autotuner): 8192 or 16384 elements, so tasks
+// cost about the same.  The plan deals the tasks out on the host with
+// Graham's longest-processing-time list schedule (longest length first, each
+// task to the least-loaded workgroup) and stores every workgroup's tasks
+// contiguously, so a workgroup knows its next task without any device
+// atomic or queue.
 //
-// The workgroup is software-pipelined: it takes its next ticket and issues the
-// global loads of that task into a second register set before it computes
-// the current one, so a CU keeps loading while it computes.  That needs the
-// register file (about 250 VGPRs per lane, one workgroup per CU) instead of a
-// second resident workgroup.  The queue code is one pipelined loop per
-// length, in queue order: tickets only grow, so a workgroup carries its
-// ticket from one length's loop to the next and never returns.
-//
-// The counter resets itself: the last workgroup to leave clears it, so the
-// graph holds a single kernel node and no memset.
+// For shapes with 16 values per lane the workgroup is software-pipelined: it
+// issues the global loads of its next task into a second register set before
+// it computes the current one, so a CU keeps loading while it computes (that
+// needs the register file, about 250 VGPRs per lane, instead of a second
+// resident workgroup).  Because vector memory counters retire in order on
+// CDNA, nothing inside a task may wait on a global load issued after that
+// prefetch: the twiddles of every pass but the last are staged in LDS once
+// per length, and the last pass's twiddles are loaded into registers before
+// the prefetch is issued.  Shapes with 32 values per lane have no registers
+// left for a second task and run their tasks one after another.  The code is
+// one loop per length, longest first; a workgroup carries its list position
+// from one length's loop to the next and never returns to an earlier one.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <queue>
 #include <string>
 #include <vector>
 
@@ -48,16 +54,18 @@ using A2048 = ShapeX<2, false, 2, 2048, 32, 8, 4, 16, 16, 8>;
 using A4096 = ShapeX<2, false, 2, 4096, 32, 4, 4, 16, 16, 16>;
 using A8192 = ShapeX<2, false, 2, 8192, 32, 2, 4, 16, 16, 16, 2>;
 using A16384 = ShapeX<2, false, 2, 16384, 32, 1, 4, 8, 16, 16, 8>;
-using B256 = ShapeX<1, true, 2, 256, 16, 32, 4, 16, 16>;
-using B512 = ShapeX<1, true, 2, 512, 16, 16, 4, 16, 16, 2>;
-using B1024 = ShapeX<1, true, 2, 1024, 16, 8, 4, 16, 16, 4>;
-using B2048 = ShapeX<1, true, 2, 2048, 16, 4, 4, 16, 16, 8>;
-using B4096 = ShapeX<1, true, 2, 4096, 16, 2, 4, 16, 16, 16>;
-using B8192 = ShapeX<1, true, 2, 8192, 16, 1, 4, 16, 16, 16, 2>;
+using B256 = ShapeX<1, false, 2, 256, 16, 32, 4, 16, 16>;
+using B512 = ShapeX<1, false, 2, 512, 16, 16, 4, 16, 16, 2>;
+using B1024 = ShapeX<1, false, 2, 1024, 16, 8, 4, 16, 16, 4>;
+using B2048 = ShapeX<1, false, 2, 2048, 16, 4, 4, 16, 16, 8>;
+using B4096 = ShapeX<1, false, 2, 4096, 16, 2, 4, 16, 16, 16>;
+using B8192 = ShapeX<1, false, 2, 8192, 16, 1, 4, 16, 16, 16, 2>;
 using B16384 = ShapeX<2, false, 2, 16384, 32, 1, 4, 16, 16, 16, 4>;
 
 constexpr int kNumShapes = 2 * kClasses;  // shape 2c + alt
 constexpr int kLdsElems = B8192::LDS_ELEMS;
+// Staged twiddles: the entries of every pass but the last, largest over shapes.
+constexpr int kTabElems = 4080;
 
 struct ShapeInfo {
   const char* name;
@@ -85,12 +93,7 @@ const ShapeInfo kShapes[kNumShapes] = {
 struct Task {
   int64_t first;  // index of the task's first transform offset in item_off
   int32_t count;  // transforms in this task (<= the shape's TPB)
-  int32_t pad;
-};
-
-struct Queue {
-  int next;  // next ticket to hand out
-  int done;  // workgroups that have left
+  int32_t cls;    // length class: the transforms have length 256 << cls
 };
 
 struct RaggedArgs {
@@ -98,20 +101,10 @@ struct RaggedArgs {
   c32* out;
   const Task* tasks;
   const int64_t* item_off;
-  Queue* queue;
-  int ntasks;
-  int end[kClasses];      // one past the last ticket of length 256 << c
-  int alt[kClasses];      // shape chosen for length 256 << c (0 = A, 1 = B)
+  const int* wg_begin;      // workgroup w runs tasks [wg_begin[w], wg_begin[w + 1])
+  int alt[kClasses];        // shape chosen for length 256 << c (0 = A, 1 = B)
   const c32* tw[kClasses];  // twiddle table of the chosen shape
 };
-
-__device__ __forceinline__ int take_ticket(Queue* q, int* s_ticket) {
-  if (threadIdx.x == 0) *s_ticket = atomicAdd(&q->next, 1);
-  __syncthreads();
-  const int v = *s_ticket;
-  __syncthreads();  // every lane has read it before lane 0 overwrites it
-  return v;
-}
 
 // Issues the global loads of task tk's rows into b (the shape's load pattern).
 template <class S>
@@ -124,78 +117,91 @@ __device__ __forceinline__ void fetch(c32 (&b)[S::E], const RaggedArgs& A, const
   global_load_row<S>(b, A.in + off, t, live);
 }
 
+// Processes this workgroup's consecutive tasks of length class c, from
+// position pos of its list (which ends at end), with shape S; loads task i+1
+// while computing task i.  Returns the position of its first task of a
+// later class (or end).
 template <class S, bool INV>
-__device__ __forceinline__ void compute_store(c32 (&a)[S::E], const RaggedArgs& A, const Task& tk,
-                                              c32* lds_all, const c32* tw) {
-  // An optimization barrier: keeps the table loads inside the task loop
-  // (hoisted out of it they would stay live across every task).
-  asm volatile("" : "+s"(tw));
+__device__ __forceinline__ int run_class(int c, int pos, int end, const RaggedArgs& A,
+                                         c32* lds_all, c32* tab, const c32* tw) {
+  static_assert(S::THREADS == kRaggedThreads, "ragged shapes use 512 lanes");
+  static_assert(S::TPB * S::LDS_ELEMS <= kLdsElems, "shape exceeds the exchange tile");
+  static_assert(S::tw_off(S::P - 1) <= kTabElems, "staged twiddles exceed their LDS region");
+  if (pos >= end || A.tasks[pos].cls != c) return pos;
   const int tid = threadIdx.x;
   const int slot = tid / S::T;
   const int t = tid - slot * S::T;
-  const bool live = slot < tk.count;
-  const int64_t off = live ? A.item_off[tk.first + slot] : 0;
-  run_passes<S, INV>(a, lds_all + slot * S::LDS_ELEMS, tw, t);
-  global_store_row<S>(a, A.out + off, t, live);
-}
-
-// Processes tickets below `end` (all of one length) with shape S, loading
-// task i+1 while computing task i.  Returns the first ticket at or past end.
-template <class S, bool INV>
-__device__ __forceinline__ int run_class(int ticket, int end, const RaggedArgs& A, c32* lds_all,
-                                         int* s_ticket, const c32* tw) {
-  static_assert(S::THREADS == kRaggedThreads, "ragged shapes use 512 lanes");
-  static_assert(S::TPB * S::LDS_ELEMS <= kLdsElems, "shape exceeds the exchange tile");
-  if (ticket >= end) return ticket;
-  Task tc = A.tasks[ticket];
-  c32 b[S::E];
-  fetch<S>(b, A, tc);
-  for (;;) {
-    c32 a[S::E];
-#pragma unroll
-    for (int m = 0; m < S::E; ++m) a[m] = b[m];
-    const int nxt = take_ticket(A.queue, s_ticket);
-    Task tn = tc;
-    if (nxt < end) {
-      tn = A.tasks[nxt];
-      fetch<S>(b, A, tn);
+  if constexpr (S::E > 16) {
+    // 32 values per lane leave no registers for a second task: no pipelining,
+    // and so no ordering constraint on the twiddle loads, which come from
+    // the global table one butterfly at a time.
+    for (;;) {
+      const Task tc = A.tasks[pos];
+      c32 a[S::E];
+      fetch<S>(a, A, tc);
+      const bool live = slot < tc.count;
+      const int64_t off = live ? A.item_off[tc.first + slot] : 0;
+      run_passes<S, INV>(a, lds_all + slot * S::LDS_ELEMS, tw, t);
+      global_store_row<S>(a, A.out + off, t, live);
+      __syncthreads();  // the task's last exchange reads are done before the next task writes
+      ++pos;
+      if (pos >= end || A.tasks[pos].cls != c) return pos;
     }
-    compute_store<S, INV>(a, A, tc, lds_all, tw);
-    if (nxt >= end) return nxt;
-    tc = tn;
+  } else {
+    // Stage the twiddles of passes 1 .. P-2 (the previous class's are no
+    // longer read).
+    __syncthreads();
+    for (int i = tid; i < S::tw_off(S::P - 1); i += kRaggedThreads) tab[i] = tw[i];
+    __syncthreads();
+    Task tc = A.tasks[pos];
+    c32 b[S::E];
+    fetch<S>(b, A, tc);
+    for (;;) {
+      c32 a[S::E];
+#pragma unroll
+      for (int m = 0; m < S::E; ++m) a[m] = b[m];
+      c32 wl[S::TW_REGS];
+      load_twiddles<S, S::P - 1>(wl, tw, t);  // issued before the prefetch
+      __builtin_amdgcn_sched_barrier(0);     // and kept before it
+      const int nxt = pos + 1;
+      const bool more = nxt < end && A.tasks[nxt].cls == c;
+      Task tn = tc;
+      if (more) {
+        tn = A.tasks[nxt];
+        fetch<S>(b, A, tn);
+      }
+      const bool live = slot < tc.count;
+      const int64_t off = live ? A.item_off[tc.first + slot] : 0;
+      run_passes_tiered_from<S, 0, INV>(a, wl, lds_all + slot * S::LDS_ELEMS, tab, t);
+      global_store_row<S>(a, A.out + off, t, live);
+      __syncthreads();  // the task's last exchange reads are done before the next task writes
+      if (!more) return nxt;
+      pos = nxt;
+      tc = tn;
+    }
   }
 }
 
 template <class SA, class SB, bool INV>
-__device__ __forceinline__ int run_length(int c, int ticket, const RaggedArgs& A, c32* lds_all,
-                                          int* s_ticket) {
-  if (A.alt[c] == 0) return run_class<SA, INV>(ticket, A.end[c], A, lds_all, s_ticket, A.tw[c]);
-  return run_class<SB, INV>(ticket, A.end[c], A, lds_all, s_ticket, A.tw[c]);
+__device__ __forceinline__ int run_length(int c, int pos, int end, const RaggedArgs& A,
+                                          c32* lds_all, c32* tab) {
+  if (A.alt[c] == 0) return run_class<SA, INV>(c, pos, end, A, lds_all, tab, A.tw[c]);
+  return run_class<SB, INV>(c, pos, end, A, lds_all, tab, A.tw[c]);
 }
 
 template <bool INV>
 __global__ __launch_bounds__(kRaggedThreads, 2) void k_ragged(RaggedArgs A) {
   __shared__ c32 lds_all[kLdsElems];
-  __shared__ int s_ticket;
-  int ticket = take_ticket(A.queue, &s_ticket);
-  ticket = run_length<A16384, B16384, INV>(6, ticket, A, lds_all, &s_ticket);
-  ticket = run_length<A8192, B8192, INV>(5, ticket, A, lds_all, &s_ticket);
-  ticket = run_length<A4096, B4096, INV>(4, ticket, A, lds_all, &s_ticket);
-  ticket = run_length<A2048, B2048, INV>(3, ticket, A, lds_all, &s_ticket);
-  ticket = run_length<A1024, B1024, INV>(2, ticket, A, lds_all, &s_ticket);
-  ticket = run_length<A512, B512, INV>(1, ticket, A, lds_all, &s_ticket);
-  ticket = run_length<A256, B256, INV>(0, ticket, A, lds_all, &s_ticket);
-  // Every workgroup leaves holding exactly one ticket at or past ntasks, so
-  // when the last one arrives nobody touches the counter again in this
-  // launch: it resets both counters for the next launch.
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const int d = atomicAdd(&A.queue->done, 1);
-    if (d == (int)gridDim.x - 1) {
-      atomicExch(&A.queue->next, 0);
-      atomicExch(&A.queue->done, 0);
-    }
-  }
+  __shared__ c32 tab[kTabElems];
+  const int end = A.wg_begin[blockIdx.x + 1];
+  int pos = A.wg_begin[blockIdx.x];
+  pos = run_length<A16384, B16384, INV>(6, pos, end, A, lds_all, tab);
+  pos = run_length<A8192, B8192, INV>(5, pos, end, A, lds_all, tab);
+  pos = run_length<A4096, B4096, INV>(4, pos, end, A, lds_all, tab);
+  pos = run_length<A2048, B2048, INV>(3, pos, end, A, lds_all, tab);
+  pos = run_length<A1024, B1024, INV>(2, pos, end, A, lds_all, tab);
+  pos = run_length<A512, B512, INV>(1, pos, end, A, lds_all, tab);
+  pos = run_length<A256, B256, INV>(0, pos, end, A, lds_all, tab);
 }
 
 int shape_index(const char* name) {
@@ -206,7 +212,7 @@ int shape_index(const char* name) {
 
 // Built-in per-length shape: the autotuner's choice on MI355X (the package's
 // tune_gfx950.json).
-constexpr int kBuiltinShape[kClasses] = {0, 3, 4, 7, 8, 11, 12};
+constexpr int kBuiltinShape[kClasses] = {1, 3, 4, 6, 8, 11, 12};
 int builtin_shape(int64_t n) { return kBuiltinShape[ilog2(n) - 8]; }
 
 std::mutex g_rtune_mu;
@@ -228,7 +234,7 @@ struct stockfft_ragged_s {
   int64_t class_count[7] = {};
   Task* d_tasks = nullptr;
   int64_t* d_off = nullptr;
-  Queue* d_queue = nullptr;
+  int* d_wg = nullptr;
   void* d_tw[kClasses] = {};
   RaggedArgs args{};
   hipGraph_t graph = nullptr;
@@ -243,7 +249,7 @@ static void free_ragged(stockfft_ragged_s* p) {
   if (p->graph) (void)hipGraphDestroy(p->graph);
   if (p->d_tasks) (void)hipFree(p->d_tasks);
   if (p->d_off) (void)hipFree(p->d_off);
-  if (p->d_queue) (void)hipFree(p->d_queue);
+  if (p->d_wg) (void)hipFree(p->d_wg);
   for (void* t : p->d_tw)
     if (t) (void)hipFree(t);
   for (fft_plan_t q : p->plain)
@@ -311,8 +317,7 @@ extern "C" int fft_plan_ragged(fft_ragged_plan_t* plan, const int64_t* sizes, in
     const int64_t k = (int64_t)item_off.size() - first;
     p->class_count[c] = k;
     for (int64_t j = 0; j < k; j += tpb)
-      tasks.push_back(Task{first + j, (int32_t)std::min<int64_t>(tpb, k - j), 0});
-    p->args.end[c] = (int)tasks.size();
+      tasks.push_back(Task{first + j, (int32_t)std::min<int64_t>(tpb, k - j), c});
     p->args.alt[c] = shape & 1;
   }
   p->ntasks = (int)tasks.size();
@@ -324,6 +329,37 @@ extern "C" int fft_plan_ragged(fft_ragged_plan_t* plan, const int64_t* sizes, in
     return hip_fail(e);
   }
   p->grid = std::max(1, std::min(cus, p->ntasks));
+
+  // List schedule (Graham's longest-processing-time rule): tasks, longest
+  // length first, each go to the workgroup with the least work so far.  A
+  // task's cost counts its memory traffic (live transforms) and its
+  // arithmetic (every slot computes, live or not).  Each workgroup's tasks are
+  // then laid out contiguously, still longest length first.
+  std::vector<int> owner(tasks.size());
+  {
+    using Load = std::pair<int64_t, int>;
+    std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
+    for (int w = 0; w < p->grid; ++w) heap.push(Load{0, w});
+    for (size_t i = 0; i < tasks.size(); ++i) {
+      const Task& tk = tasks[i];
+      const int64_t n = int64_t(256) << tk.cls;
+      const int64_t cost = n * (int64_t(16) * tk.count +
+                                int64_t(kShapes[p->shape_of_class[tk.cls]].tpb) * ilog2(n));
+      Load l = heap.top();
+      heap.pop();
+      owner[i] = l.second;
+      heap.push(Load{l.first + cost, l.second});
+    }
+  }
+  std::vector<int> wg_begin(p->grid + 1, 0);
+  for (int w : owner) ++wg_begin[w + 1];
+  for (int w = 0; w < p->grid; ++w) wg_begin[w + 1] += wg_begin[w];
+  {
+    std::vector<int> fill(wg_begin.begin(), wg_begin.end() - 1);
+    std::vector<Task> listed(tasks.size());
+    for (size_t i = 0; i < tasks.size(); ++i) listed[fill[owner[i]]++] = tasks[i];
+    tasks.swap(listed);
+  }
 
   std::vector<float> tw;
   for (int c = 0; c < kClasses && !rc; ++c) {
@@ -340,8 +376,10 @@ extern "C" int fft_plan_ragged(fft_ragged_plan_t* plan, const int64_t* sizes, in
     if (e == hipSuccess)
       e = hipMemcpy(p->d_off, item_off.data(), item_off.size() * sizeof(int64_t),
                     hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc((void**)&p->d_queue, sizeof(Queue));
-    if (e == hipSuccess) e = hipMemset(p->d_queue, 0, sizeof(Queue));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_wg, wg_begin.size() * sizeof(int));
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_wg, wg_begin.data(), wg_begin.size() * sizeof(int),
+                    hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) rc = hip_fail(e);
   }
@@ -355,8 +393,7 @@ extern "C" int fft_plan_ragged(fft_ragged_plan_t* plan, const int64_t* sizes, in
   }
   p->args.tasks = p->d_tasks;
   p->args.item_off = p->d_off;
-  p->args.queue = p->d_queue;
-  p->args.ntasks = p->ntasks;
+  p->args.wg_begin = p->d_wg;
   for (int c = 0; c < kClasses; ++c) p->args.tw[c] = static_cast<const c32*>(p->d_tw[c]);
   register_handle(p);
   *plan = p;

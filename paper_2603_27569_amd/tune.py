@@ -102,8 +102,8 @@ def tune_plain(torch, dev, stream, sizes=SIZES, buckets=BUCKETS, iters=30, log=p
 def tune_ragged(torch, dev, stream, sizes=None, iters=20, sweeps=2, log=print):
     """Choose the ragged kernel's shape per length on a mixed ragged batch.
 
-    The shapes interact (they share the persistent workgroups and the task
-    queue), so they are tuned together: coordinate descent over the lengths,
+    The shapes interact (they share the persistent workgroups and the list
+    schedule), so they are tuned together: coordinate descent over the lengths,
     each step timing every shape of one length with the others fixed.  The
     default batch is 2000 lengths drawn log-uniformly from 256..16384."""
     if sizes is None:

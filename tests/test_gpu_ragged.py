@@ -1,5 +1,5 @@
 """Ragged batches: the persistent hipGraph launch against the FP64 oracle,
-transform by transform, plus graph re-use, queue self-reset and per-size
+transform by transform, plus graph re-use with new pointers and per-size
 shape choices."""
 import numpy as np
 import pytest
@@ -59,14 +59,14 @@ def test_ragged_small_sets(sizes):
     plan.close()
 
 
-def test_ragged_graph_reuse_new_pointers_and_queue_reset():
+def test_ragged_graph_reuse_new_pointers():
     sizes, _, data = workloads.ragged(count=300, seed=77)
     plan = sf.RaggedPlan(sizes)
     x1 = torch.from_numpy(data).to(DEV)
     x2 = x1 * (0.5 - 0.25j)
     outs = []
     # Same pointers twice, then new pointers, then the first ones again: every
-    # launch must do the whole batch (the queue counter resets itself).
+    # launch must do the whole batch, into the buffers of that call.
     for xin in (x1, x1, x2, x1):
         y = torch.full_like(x1, complex(float("nan"), 0.0))
         sf.ragged_fft(xin, plan, out=y)
