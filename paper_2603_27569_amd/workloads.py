@@ -18,6 +18,9 @@ for it:
                   the chirp support                                   (seed 1003)
   spectral_energy N=4096, batch 512, x ~ N(0, 1); W ~ U[0, 1) float32  (1004/1104)
   ragged          2000 transforms, sizes 2^U{8..14}, N(0, 1) values   (seed 1005)
+  range_compression  N=4096, 256 lines: chirp_noise rows and a matched
+                  filter given directly in frequency: unit-modulus quadratic
+                  phase over the swept band, zero outside        (seed 1006)
 """
 import numpy as np
 
@@ -132,3 +135,22 @@ def ragged(count=2000, seed=1005):
     total = int(sizes.sum())
     data = complex_normal((total,), seed + 7919)
     return sizes, offsets, data
+
+
+def range_compression_inputs(n=4096, batch=256, seed=1006, beta=0.5):
+    """SAR range-compression block (4096 bins x 256 lines): rows from
+    chirp_noise and a filter spectrum h of length n.  h is the stationary-phase
+    form of a linear-FM chirp spectrum, written down directly: for frequency
+    bins f = k/n (centred, in cycles/sample) inside the band |f| < beta/2,
+    h[k] = exp(i*pi*L*f^2/beta) with L = n/4, else 0.
+
+    Returns (x complex64 [batch, n], h complex64 [n])."""
+    x, _ = chirp_noise(n, batch, seed)
+    k = np.arange(n, dtype=np.float64)
+    f = np.where(k < n / 2, k, k - n) / n
+    L = n // 4
+    ph = np.pi * L * f * f / beta
+    inband = np.abs(f) < beta / 2
+    re = np.where(inband, np.cos(ph), 0.0)
+    im = np.where(inband, np.sin(ph), 0.0)
+    return x, _to_c64(re, im)
