@@ -146,8 +146,8 @@ int fft_exec_matched_filter(fft_plan_t plan, const void *x, const void *h, void 
  * starts at element offset sum_{j<i} sizes[j]).  All run in one persistent
  * kernel launch, captured once in a hipGraph.  Each length runs with its
  * own tuned shape; the transforms are grouped into tasks of about equal
- * cost, dealt to the workgroups once, here, by a longest-first list schedule
- * (no device queue or atomic).
+ * cost, dealt to the workgroups (two per CU) once, here, by a longest-first
+ * list schedule on measured task costs (no device queue or atomic).
  *   sizes      host array of `count` lengths, each a power of two in
  *              [256, 16384]; copied, the caller keeps ownership.
  *   count      >= 1.
@@ -169,6 +169,15 @@ int fft_plan_ragged(fft_ragged_plan_t *plan, const int64_t *sizes, int64_t count
  * FFT_HIP_ERROR.
  */
 int fft_exec_ragged(fft_ragged_plan_t plan, const void *in, void *out, void *stream);
+
+/*
+ * fft_exec_ragged_direct -- the same persistent kernel as fft_exec_ragged,
+ * started with a plain kernel launch instead of the plan's graph (for callers
+ * that capture it into a graph of their own, or that want the lower launch
+ * cost: about 4 us less per call on ROCm 7 with one MI355X).  Same arguments,
+ * results and errors as fft_exec_ragged; the plan's graph is not touched.
+ */
+int fft_exec_ragged_direct(fft_ragged_plan_t plan, const void *in, void *out, void *stream);
 
 /*
  * fft_exec_ragged_plain -- the same ragged batch by plain launches: one

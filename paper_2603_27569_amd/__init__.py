@@ -28,7 +28,8 @@ __all__ = [
     "FFT_ALGO_FOUR_STEP", "StockfftError", "STATUS", "CODES",
     "fft_plan", "fft_plan_config", "fft_exec", "fft_destroy",
     "fft_exec_spectral_energy", "fft_exec_matched_filter",
-    "fft_plan_ragged", "fft_exec_ragged", "fft_exec_ragged_plain", "fft_destroy_ragged",
+    "fft_plan_ragged", "fft_exec_ragged", "fft_exec_ragged_direct", "fft_exec_ragged_plain",
+    "fft_destroy_ragged",
     "fft_ragged_shapes", "fft_tune_set_ragged", "fft_tune_query_ragged", "fft_tune_clear_ragged",
     "fft_tune_load", "fft_tune_set", "fft_tune_clear", "fft_tune_query",
     "fft_set_launch_limit",
@@ -87,6 +88,11 @@ def fft_plan_ragged(sizes, direction):
 
 def fft_exec_ragged(plan, in_ptr, out_ptr, stream=0):
     return check("fft_exec_ragged", lib().fft_exec_ragged(
+        _vp(plan), _vp(in_ptr), _vp(out_ptr), _vp(stream)))
+
+
+def fft_exec_ragged_direct(plan, in_ptr, out_ptr, stream=0):
+    return check("fft_exec_ragged_direct", lib().fft_exec_ragged_direct(
         _vp(plan), _vp(in_ptr), _vp(out_ptr), _vp(stream)))
 
 
@@ -224,6 +230,9 @@ class RaggedPlan:
     def exec(self, in_ptr, out_ptr, stream=0):
         fft_exec_ragged(self.handle, in_ptr, out_ptr, stream)
 
+    def exec_direct(self, in_ptr, out_ptr, stream=0):
+        fft_exec_ragged_direct(self.handle, in_ptr, out_ptr, stream)
+
     def exec_plain(self, in_by_size, out_by_size, stream=0):
         fft_exec_ragged_plain(self.handle, in_by_size, out_by_size, stream)
 
@@ -353,13 +362,15 @@ def matched_filter(x, h, out=None):
     return out
 
 
-def ragged_fft(packed, plan, out=None):
-    """Transforms every row of a packed ragged buffer with a RaggedPlan."""
+def ragged_fft(packed, plan, out=None, graph=True):
+    """Transforms every row of a packed ragged buffer with a RaggedPlan (its
+    hipGraph, or with graph=False a plain launch of the same kernel)."""
     import torch
     _check_tensor(packed, "packed")
     if out is None:
         out = torch.empty_like(packed)
-    plan.exec(packed.data_ptr(), out.data_ptr(), _stream(packed.device))
+    run = plan.exec if graph else plan.exec_direct
+    run(packed.data_ptr(), out.data_ptr(), _stream(packed.device))
     return out
 
 

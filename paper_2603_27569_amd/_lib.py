@@ -40,6 +40,7 @@ SIGNATURES = {
     "fft_exec_matched_filter": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "fft_plan_ragged": (_int, [_pvp, ctypes.POINTER(_i64), _i64, _int]),
     "fft_exec_ragged": (_int, [_vp, _vp, _vp, _vp]),
+    "fft_exec_ragged_direct": (_int, [_vp, _vp, _vp, _vp]),
     "fft_exec_ragged_plain": (_int, [_vp, _pvp, _pvp, _vp]),
     "fft_destroy_ragged": (_int, [_vp]),
     "fft_ragged_shapes": (_int, [_i64, ctypes.c_char_p, _i64]),

@@ -1,28 +1,22 @@
 // Ragged batches: transforms of different power-of-two lengths, packed one
-// after another, run by one persistent kernel launched from a hipGraph.
+// after another, run by one persistent kernel.
 //
-// One persistent workgroup of 512 lanes per CU works through a list of
-// tasks; a task is as many transforms of one length as the workgroup holds
-// under the shape chosen for that length (radix, lanes per transform and
-// exchange tile, picked by the autotuner): 8192 or 16384 elements, so tasks
-// cost about the same.  The plan deals the tasks out on the host with
-// Graham's longest-processing-time list schedule (longest length first, each
-// task to the least-loaded workgroup) and stores every workgroup's tasks
-// contiguously, so a workgroup knows its next task without any device
+// Two persistent workgroups of 512 lanes per CU (at most 128 VGPRs and a
+// 68 KiB exchange tile each) work through a list of tasks; a task is as many
+// transforms of one length as the workgroup holds under the shape chosen for
+// that length (values per lane, exchange rounds, radix order; picked by the
+// autotuner): 16384 or 8192 elements, so tasks cost about the same.  The plan
+// deals the tasks out on the host with Graham's longest-processing-time list
+// schedule, costing each task by its shape's measured duration, and stores
+// every workgroup's tasks contiguously, longest length first, with the start
+// of each length in a small per-workgroup table; the kernel needs no device
 // atomic or queue.
 //
-// For shapes with 16 values per lane the workgroup is software-pipelined: it
-// issues the global loads of its next task into a second register set before
-// it computes the current one, so a CU keeps loading while it computes (that
-// needs the register file, about 250 VGPRs per lane, instead of a second
-// resident workgroup).  Because vector memory counters retire in order on
-// CDNA, nothing inside a task may wait on a global load issued after that
-// prefetch: the twiddles of every pass but the last are staged in LDS once
-// per length, and the last pass's twiddles are loaded into registers before
-// the prefetch is issued.  Shapes with 32 values per lane have no registers
-// left for a second task and run their tasks one after another.  The code is
-// one loop per length, longest first; a workgroup carries its list position
-// from one length's loop to the next and never returns to an earlier one.
+// A workgroup runs its tasks one after another; the second workgroup on the
+// CU overlaps its loads and stores with this one's arithmetic (measured
+// faster on MI355X than one software-pipelined workgroup per CU holding two
+// tasks in registers).  The next task's descriptor and row offsets are
+// loaded while the current one computes.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -43,29 +37,28 @@ namespace {
 constexpr int kRaggedThreads = 512;
 constexpr int kClasses = 7;  // lengths 256 << c, c = 0..6
 
-// Two candidate shapes per length, all 512 lanes with at most an 8192-element
-// (+ pad) exchange tile.  A: 32 values per lane, two-round exchanges, 16384
-// elements per task.  B: 16 values per lane, whole-tile exchanges, 8192
-// elements per task (for 16384, B is the radix-16 order of the A shape).
-using A256 = ShapeX<2, false, 2, 256, 32, 64, 4, 16, 16>;
-using A512 = ShapeX<2, false, 2, 512, 32, 32, 4, 16, 16, 2>;
-using A1024 = ShapeX<2, false, 2, 1024, 32, 16, 4, 16, 16, 4>;
-using A2048 = ShapeX<2, false, 2, 2048, 32, 8, 4, 16, 16, 8>;
-using A4096 = ShapeX<2, false, 2, 4096, 32, 4, 4, 16, 16, 16>;
-using A8192 = ShapeX<2, false, 2, 8192, 32, 2, 4, 16, 16, 16, 2>;
-using A16384 = ShapeX<2, false, 2, 16384, 32, 1, 4, 8, 16, 16, 8>;
-using B256 = ShapeX<1, false, 2, 256, 16, 32, 4, 16, 16>;
-using B512 = ShapeX<1, false, 2, 512, 16, 16, 4, 16, 16, 2>;
-using B1024 = ShapeX<1, false, 2, 1024, 16, 8, 4, 16, 16, 4>;
-using B2048 = ShapeX<1, false, 2, 2048, 16, 4, 4, 16, 16, 8>;
-using B4096 = ShapeX<1, false, 2, 4096, 16, 2, 4, 16, 16, 16>;
-using B8192 = ShapeX<1, false, 2, 8192, 16, 1, 4, 16, 16, 16, 2>;
-using B16384 = ShapeX<2, false, 2, 16384, 32, 1, 4, 16, 16, 16, 4>;
+// Two candidate shapes per length, all 512 lanes, at most 128 VGPRs (two
+// workgroups per CU) and at most an 8192-element (+ pad) exchange tile.
+// A: 32 values per lane, two-round exchanges, 16384 elements per task.
+// B: 16 values per lane, whole-tile exchanges, 8192 elements per task (for
+// 16384, B is the radix-16 order of the A shape).
+using A256 = ShapeX<2, false, 4, 256, 32, 64, 4, 16, 16>;
+using A512 = ShapeX<2, false, 4, 512, 32, 32, 4, 16, 16, 2>;
+using A1024 = ShapeX<2, false, 4, 1024, 32, 16, 4, 16, 16, 4>;
+using A2048 = ShapeX<2, false, 4, 2048, 32, 8, 4, 16, 16, 8>;
+using A4096 = ShapeX<2, false, 4, 4096, 32, 4, 4, 16, 16, 16>;
+using A8192 = ShapeX<2, false, 4, 8192, 32, 2, 4, 16, 16, 16, 2>;
+using A16384 = ShapeX<2, false, 4, 16384, 32, 1, 4, 8, 16, 16, 8>;
+using B256 = ShapeX<1, false, 4, 256, 16, 32, 4, 16, 16>;
+using B512 = ShapeX<1, false, 4, 512, 16, 16, 4, 16, 16, 2>;
+using B1024 = ShapeX<1, false, 4, 1024, 16, 8, 4, 16, 16, 4>;
+using B2048 = ShapeX<1, false, 4, 2048, 16, 4, 4, 16, 16, 8>;
+using B4096 = ShapeX<1, false, 4, 4096, 16, 2, 4, 16, 16, 16>;
+using B8192 = ShapeX<1, false, 4, 8192, 16, 1, 4, 16, 16, 16, 2>;
+using B16384 = ShapeX<2, false, 4, 16384, 32, 1, 4, 16, 16, 16, 4>;
 
 constexpr int kNumShapes = 2 * kClasses;  // shape 2c + alt
 constexpr int kLdsElems = B8192::LDS_ELEMS;
-// Staged twiddles: the entries of every pass but the last, largest over shapes.
-constexpr int kTabElems = 4080;
 
 struct ShapeInfo {
   const char* name;
@@ -90,6 +83,19 @@ const ShapeInfo kShapes[kNumShapes] = {
     info<A16384>("ragged_n16384_e32c2_r8"), info<B16384>("ragged_n16384_e32c2_r16"),
 };
 
+// Duration of one full task of each shape in microseconds, two workgroups per
+// CU and every CU busy (median over about a thousand tasks of that shape on
+// an MI355X).  The list schedule uses them as task costs.
+constexpr float kShapeTaskUs[kNumShapes] = {
+    16.80f, 6.88f,   // 256
+    18.34f, 8.26f,   // 512
+    20.18f, 8.92f,   // 1024
+    19.00f, 9.76f,   // 2048
+    19.56f, 9.88f,   // 4096
+    21.76f, 11.64f,  // 8192
+    26.16f, 23.72f,  // 16384
+};
+
 struct Task {
   int64_t first;  // index of the task's first transform offset in item_off
   int32_t count;  // transforms in this task (<= the shape's TPB)
@@ -101,107 +107,77 @@ struct RaggedArgs {
   c32* out;
   const Task* tasks;
   const int64_t* item_off;
-  const int* wg_begin;      // workgroup w runs tasks [wg_begin[w], wg_begin[w + 1])
+  // Workgroup w runs tasks [r[0], r[7]) of the list, r = wg_cls + 8w; its
+  // tasks of length 256 << c are [r[6 - c], r[7 - c]).
+  const int* wg_cls;
   int alt[kClasses];        // shape chosen for length 256 << c (0 = A, 1 = B)
   const c32* tw[kClasses];  // twiddle table of the chosen shape
 };
 
-// Issues the global loads of task tk's rows into b (the shape's load pattern).
-template <class S>
-__device__ __forceinline__ void fetch(c32 (&b)[S::E], const RaggedArgs& A, const Task& tk) {
-  const int tid = threadIdx.x;
-  const int slot = tid / S::T;
-  const int t = tid - slot * S::T;
-  const bool live = slot < tk.count;
-  const int64_t off = live ? A.item_off[tk.first + slot] : 0;
-  global_load_row<S>(b, A.in + off, t, live);
-}
-
-// Processes this workgroup's consecutive tasks of length class c, from
-// position pos of its list (which ends at end), with shape S; loads task i+1
-// while computing task i.  Returns the position of its first task of a
-// later class (or end).
+// Runs this workgroup's tasks [pos, end) of one length one after another (no
+// prefetch of rows; a second resident workgroup overlaps its loads instead).
+// The next task's descriptor and row offsets are loaded while the current
+// task computes, so only a workgroup's first task of a length waits on them.
 template <class S, bool INV>
-__device__ __forceinline__ int run_class(int c, int pos, int end, const RaggedArgs& A,
-                                         c32* lds_all, c32* tab, const c32* tw) {
+__device__ __forceinline__ void run_class_serial(int pos, int end, const RaggedArgs& A,
+                                                 c32* lds_all, const c32* tw) {
   static_assert(S::THREADS == kRaggedThreads, "ragged shapes use 512 lanes");
   static_assert(S::TPB * S::LDS_ELEMS <= kLdsElems, "shape exceeds the exchange tile");
-  static_assert(S::tw_off(S::P - 1) <= kTabElems, "staged twiddles exceed their LDS region");
-  if (pos >= end || A.tasks[pos].cls != c) return pos;
+  if (pos >= end) return;
   const int tid = threadIdx.x;
   const int slot = tid / S::T;
   const int t = tid - slot * S::T;
-  if constexpr (S::E > 16) {
-    // 32 values per lane leave no registers for a second task: no pipelining,
-    // and so no ordering constraint on the twiddle loads, which come from
-    // the global table one butterfly at a time.
-    for (;;) {
-      const Task tc = A.tasks[pos];
-      c32 a[S::E];
-      fetch<S>(a, A, tc);
-      const bool live = slot < tc.count;
-      const int64_t off = live ? A.item_off[tc.first + slot] : 0;
-      run_passes<S, INV>(a, lds_all + slot * S::LDS_ELEMS, tw, t);
-      global_store_row<S>(a, A.out + off, t, live);
-      __syncthreads();  // the task's last exchange reads are done before the next task writes
-      ++pos;
-      if (pos >= end || A.tasks[pos].cls != c) return pos;
+  Task tc = A.tasks[pos];
+  int64_t off = slot < tc.count ? A.item_off[tc.first + slot] : 0;
+  for (;;) {
+    const bool live = slot < tc.count;
+    c32 a[S::E];
+    global_load_row<S>(a, A.in + off, t, live);
+    const bool more = pos + 1 < end;
+    Task tn = tc;
+    int64_t off_n = 0;
+    if (more) {
+      tn = A.tasks[pos + 1];
+      if (slot < tn.count) off_n = A.item_off[tn.first + slot];
     }
-  } else {
-    // Stage the twiddles of passes 1 .. P-2 (the previous class's are no
-    // longer read).
-    __syncthreads();
-    for (int i = tid; i < S::tw_off(S::P - 1); i += kRaggedThreads) tab[i] = tw[i];
-    __syncthreads();
-    Task tc = A.tasks[pos];
-    c32 b[S::E];
-    fetch<S>(b, A, tc);
-    for (;;) {
-      c32 a[S::E];
-#pragma unroll
-      for (int m = 0; m < S::E; ++m) a[m] = b[m];
-      c32 wl[S::TW_REGS];
-      load_twiddles<S, S::P - 1>(wl, tw, t);  // issued before the prefetch
-      __builtin_amdgcn_sched_barrier(0);     // and kept before it
-      const int nxt = pos + 1;
-      const bool more = nxt < end && A.tasks[nxt].cls == c;
-      Task tn = tc;
-      if (more) {
-        tn = A.tasks[nxt];
-        fetch<S>(b, A, tn);
-      }
-      const bool live = slot < tc.count;
-      const int64_t off = live ? A.item_off[tc.first + slot] : 0;
-      run_passes_tiered_from<S, 0, INV>(a, wl, lds_all + slot * S::LDS_ELEMS, tab, t);
-      global_store_row<S>(a, A.out + off, t, live);
-      __syncthreads();  // the task's last exchange reads are done before the next task writes
-      if (!more) return nxt;
-      pos = nxt;
-      tc = tn;
-    }
+    // The table pointer and the lane index are made opaque inside the loop so
+    // that the compiler does not hoist every pass's twiddle loads and LDS
+    // addresses out of it (they would then all stay live across tasks).
+    const c32* twl = tw;
+    int tl = t;
+    asm volatile("" : "+s"(twl), "+v"(tl));
+    run_passes<S, INV>(a, lds_all + slot * S::LDS_ELEMS, twl, tl);
+    global_store_row<S>(a, A.out + off, t, live);
+    __syncthreads();  // the task's last exchange reads are done before the next task writes
+    if (!more) return;
+    ++pos;
+    tc = tn;
+    off = off_n;
   }
 }
 
 template <class SA, class SB, bool INV>
-__device__ __forceinline__ int run_length(int c, int pos, int end, const RaggedArgs& A,
-                                          c32* lds_all, c32* tab) {
-  if (A.alt[c] == 0) return run_class<SA, INV>(c, pos, end, A, lds_all, tab, A.tw[c]);
-  return run_class<SB, INV>(c, pos, end, A, lds_all, tab, A.tw[c]);
+__device__ __forceinline__ void run_length_serial(int c, const int* r, const RaggedArgs& A,
+                                                  c32* lds_all) {
+  if (A.alt[c] == 0)
+    run_class_serial<SA, INV>(r[6 - c], r[7 - c], A, lds_all, A.tw[c]);
+  else
+    run_class_serial<SB, INV>(r[6 - c], r[7 - c], A, lds_all, A.tw[c]);
 }
 
 template <bool INV>
-__global__ __launch_bounds__(kRaggedThreads, 2) void k_ragged(RaggedArgs A) {
+__global__ __launch_bounds__(kRaggedThreads, 4) void k_ragged(RaggedArgs A) {
   __shared__ c32 lds_all[kLdsElems];
-  __shared__ c32 tab[kTabElems];
-  const int end = A.wg_begin[blockIdx.x + 1];
-  int pos = A.wg_begin[blockIdx.x];
-  pos = run_length<A16384, B16384, INV>(6, pos, end, A, lds_all, tab);
-  pos = run_length<A8192, B8192, INV>(5, pos, end, A, lds_all, tab);
-  pos = run_length<A4096, B4096, INV>(4, pos, end, A, lds_all, tab);
-  pos = run_length<A2048, B2048, INV>(3, pos, end, A, lds_all, tab);
-  pos = run_length<A1024, B1024, INV>(2, pos, end, A, lds_all, tab);
-  pos = run_length<A512, B512, INV>(1, pos, end, A, lds_all, tab);
-  pos = run_length<A256, B256, INV>(0, pos, end, A, lds_all, tab);
+  int r[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) r[i] = A.wg_cls[8 * blockIdx.x + i];
+  run_length_serial<A16384, B16384, INV>(6, r, A, lds_all);
+  run_length_serial<A8192, B8192, INV>(5, r, A, lds_all);
+  run_length_serial<A4096, B4096, INV>(4, r, A, lds_all);
+  run_length_serial<A2048, B2048, INV>(3, r, A, lds_all);
+  run_length_serial<A1024, B1024, INV>(2, r, A, lds_all);
+  run_length_serial<A512, B512, INV>(1, r, A, lds_all);
+  run_length_serial<A256, B256, INV>(0, r, A, lds_all);
 }
 
 int shape_index(const char* name) {
@@ -212,7 +188,7 @@ int shape_index(const char* name) {
 
 // Built-in per-length shape: the autotuner's choice on MI355X (the package's
 // tune_gfx950.json).
-constexpr int kBuiltinShape[kClasses] = {1, 3, 4, 6, 8, 11, 12};
+constexpr int kBuiltinShape[kClasses] = {0, 3, 4, 6, 9, 10, 13};
 int builtin_shape(int64_t n) { return kBuiltinShape[ilog2(n) - 8]; }
 
 std::mutex g_rtune_mu;
@@ -328,27 +304,36 @@ extern "C" int fft_plan_ragged(fft_ragged_plan_t* plan, const int64_t* sizes, in
     free_ragged(p);
     return hip_fail(e);
   }
-  p->grid = std::max(1, std::min(cus, p->ntasks));
+  p->grid = std::max(1, std::min(2 * cus, p->ntasks));  // two workgroups per CU
 
   // List schedule (Graham's longest-processing-time rule): tasks, longest
   // length first, each go to the workgroup with the least work so far.  A
-  // task's cost counts its memory traffic (live transforms) and its
-  // arithmetic (every slot computes, live or not).  Each workgroup's tasks are
-  // then laid out contiguously, still longest length first.
+  // task costs its shape's measured duration, scaled down for a partly
+  // filled task: half of it (the loads and stores) is taken as proportional to
+  // the live transforms, the other half (the arithmetic of every slot) not.
+  // Each workgroup's tasks are then laid out contiguously, still longest
+  // length first.
   std::vector<int> owner(tasks.size());
   {
-    using Load = std::pair<int64_t, int>;
+    using Load = std::pair<double, int>;
     std::priority_queue<Load, std::vector<Load>, std::greater<Load>> heap;
     for (int w = 0; w < p->grid; ++w) heap.push(Load{0, w});
+    std::vector<double> cost(tasks.size());
+    std::vector<size_t> order(tasks.size());
     for (size_t i = 0; i < tasks.size(); ++i) {
       const Task& tk = tasks[i];
-      const int64_t n = int64_t(256) << tk.cls;
-      const int64_t cost = n * (int64_t(16) * tk.count +
-                                int64_t(kShapes[p->shape_of_class[tk.cls]].tpb) * ilog2(n));
+      const int shape = p->shape_of_class[tk.cls];
+      const double fill = double(tk.count) / kShapes[shape].tpb;
+      cost[i] = kShapeTaskUs[shape] * (0.5 + 0.5 * fill);
+      order[i] = i;
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return cost[a] > cost[b]; });
+    for (size_t i : order) {
       Load l = heap.top();
       heap.pop();
       owner[i] = l.second;
-      heap.push(Load{l.first + cost, l.second});
+      heap.push(Load{l.first + cost[i], l.second});
     }
   }
   std::vector<int> wg_begin(p->grid + 1, 0);
@@ -359,6 +344,16 @@ extern "C" int fft_plan_ragged(fft_ragged_plan_t* plan, const int64_t* sizes, in
     std::vector<Task> listed(tasks.size());
     for (size_t i = 0; i < tasks.size(); ++i) listed[fill[owner[i]]++] = tasks[i];
     tasks.swap(listed);
+  }
+  // Per workgroup: where each length's tasks begin in its slice, then its end.
+  std::vector<int> wg_cls(8 * (size_t)p->grid);
+  for (int w = 0; w < p->grid; ++w) {
+    int q = wg_begin[w];
+    for (int k = 0; k < kClasses; ++k) {
+      wg_cls[8 * w + k] = q;
+      while (q < wg_begin[w + 1] && tasks[q].cls == 6 - k) ++q;
+    }
+    wg_cls[8 * w + 7] = q;
   }
 
   std::vector<float> tw;
@@ -376,9 +371,9 @@ extern "C" int fft_plan_ragged(fft_ragged_plan_t* plan, const int64_t* sizes, in
     if (e == hipSuccess)
       e = hipMemcpy(p->d_off, item_off.data(), item_off.size() * sizeof(int64_t),
                     hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = hipMalloc((void**)&p->d_wg, wg_begin.size() * sizeof(int));
+    if (e == hipSuccess) e = hipMalloc((void**)&p->d_wg, wg_cls.size() * sizeof(int));
     if (e == hipSuccess)
-      e = hipMemcpy(p->d_wg, wg_begin.data(), wg_begin.size() * sizeof(int),
+      e = hipMemcpy(p->d_wg, wg_cls.data(), wg_cls.size() * sizeof(int),
                     hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) rc = hip_fail(e);
@@ -393,7 +388,8 @@ extern "C" int fft_plan_ragged(fft_ragged_plan_t* plan, const int64_t* sizes, in
   }
   p->args.tasks = p->d_tasks;
   p->args.item_off = p->d_off;
-  p->args.wg_begin = p->d_wg;
+  p->args.wg_cls = p->d_wg;
+
   for (int c = 0; c < kClasses; ++c) p->args.tw[c] = static_cast<const c32*>(p->d_tw[c]);
   register_handle(p);
   *plan = p;
@@ -416,11 +412,17 @@ static hipKernelNodeParams ragged_node_params(stockfft_ragged_s* p, void** argv)
   return kp;
 }
 
-extern "C" int fft_exec_ragged(fft_ragged_plan_t plan, const void* in, void* out, void* stream) {
+static int check_ragged_exec(fft_ragged_plan_t plan, const void* in, void* out) {
   if (!plan || !live_handle(plan)) return FFT_INVALID_PLAN;
   if (!in || !out) return FFT_INVALID_POINTER;
   if (!aligned8(in) || !aligned8(out)) return FFT_MISALIGNED;
   if (ranges_partially_overlap(in, out, (size_t)plan->total * 8)) return FFT_OVERLAP;
+  return FFT_SUCCESS;
+}
+
+extern "C" int fft_exec_ragged(fft_ragged_plan_t plan, const void* in, void* out, void* stream) {
+  const int rc = check_ragged_exec(plan, in, out);
+  if (rc) return rc;
   DeviceGuard g(plan->device);
   const bool changed = plan->args.in != in || plan->args.out != out;
   plan->args.in = static_cast<const c32*>(in);
@@ -436,6 +438,22 @@ extern "C" int fft_exec_ragged(fft_ragged_plan_t plan, const void* in, void* out
     e = hipGraphExecKernelNodeSetParams(plan->exec, plan->node, &kp);
   }
   if (e == hipSuccess) e = hipGraphLaunch(plan->exec, (hipStream_t)stream);
+  return e == hipSuccess ? FFT_SUCCESS : hip_fail(e);
+}
+
+extern "C" int fft_exec_ragged_direct(fft_ragged_plan_t plan, const void* in, void* out,
+                                      void* stream) {
+  const int rc = check_ragged_exec(plan, in, out);
+  if (rc) return rc;
+  DeviceGuard g(plan->device);
+  RaggedArgs args = plan->args;
+  args.in = static_cast<const c32*>(in);
+  args.out = static_cast<c32*>(out);
+  void* argv[1] = {&args};
+  const void* fn = plan->direction == FFT_BACKWARD ? reinterpret_cast<const void*>(&k_ragged<true>)
+                                                   : reinterpret_cast<const void*>(&k_ragged<false>);
+  const hipError_t e = hipLaunchKernel(fn, dim3((unsigned)plan->grid), dim3(kRaggedThreads), argv,
+                                       0, (hipStream_t)stream);
   return e == hipSuccess ? FFT_SUCCESS : hip_fail(e);
 }
 

@@ -330,36 +330,6 @@ __device__ __forceinline__ void run_passes_from(c32 (&a)[S::E], c32 (&w)[S::TW_R
   }
 }
 
-// Tiered twiddles (for shapes without prefetch): passes 1 .. P-2 read their
-// twiddles from `tab` (a copy of the first tw_off(P-1) table entries, e.g.
-// staged in LDS), the last pass from `wl`, registers the caller loaded with
-// load_twiddles<S, P-1>.  No global load is waited on inside the transform.
-template <class S, int p, bool INV>
-__device__ __forceinline__ void run_passes_tiered_from(c32 (&a)[S::E],
-                                                       const c32 (&wl)[S::TW_REGS], c32* lds,
-                                                       const c32* tab, int t) {
-  static_assert(!S::PF, "tiered twiddles are for shapes that load twiddles in their pass");
-  if constexpr (p + 1 < S::P) {
-    c32 unused[S::TW_REGS];
-    pass_compute<S, p, INV>(a, unused, tab, t);
-    exchange<S, p>(a, lds, t);
-    run_passes_tiered_from<S, p + 1, INV>(a, wl, lds, tab, t);
-  } else {
-    constexpr int R = S::radix(p);
-    constexpr int BPT = S::E / R;
-#pragma unroll
-    for (int b = 0; b < BPT; ++b) {
-      c32 v[R];
-      v[0] = a[b];
-#pragma unroll
-      for (int r = 1; r < R; ++r) v[r] = ctw<INV>(a[b + r * BPT], wl[b * (R - 1) + (r - 1)]);
-      Dft<R, INV>::run(v);
-#pragma unroll
-      for (int r = 0; r < R; ++r) a[b + r * BPT] = v[r];
-    }
-  }
-}
-
 // All passes of one transform.  Called right after the lane's input loads
 // were issued, so the first twiddle loads queue behind them.
 template <class S, bool INV>

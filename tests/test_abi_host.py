@@ -87,6 +87,7 @@ def test_exec_and_destroy_reject_bad_handles():
         _lib.CODES["FFT_INVALID_PLAN"]
     assert L.fft_exec_matched_filter(None, None, None, None, None) == _lib.CODES["FFT_INVALID_PLAN"]
     assert L.fft_exec_ragged(None, None, None, None) == _lib.CODES["FFT_INVALID_PLAN"]
+    assert L.fft_exec_ragged_direct(None, None, None, None) == _lib.CODES["FFT_INVALID_PLAN"]
     assert L.fft_destroy_ragged(None) == 0
 
 

@@ -1,6 +1,6 @@
-"""Ragged batches: the persistent hipGraph launch against the FP64 oracle,
-transform by transform, plus graph re-use with new pointers and per-size
-shape choices."""
+"""Ragged batches: the persistent kernel (its hipGraph and its plain launch)
+against the FP64 oracle, transform by transform, plus graph re-use with new
+pointers, per-size shape choices and the list schedule's edge cases."""
 import numpy as np
 import pytest
 
@@ -26,22 +26,44 @@ def _check_ragged(y, x, sizes, inverse=False):
     return worst
 
 
-def _run(plan, x):
+def _run(plan, x, graph=True):
     xt = torch.from_numpy(x).to(DEV)
     y = torch.full_like(xt, complex(float("nan"), float("nan")))
-    sf.ragged_fft(xt, plan, out=y)
+    sf.ragged_fft(xt, plan, out=y, graph=graph)
     torch.cuda.synchronize()
     return y
 
 
+@pytest.mark.parametrize("graph", [True, False], ids=["graph", "direct"])
 @pytest.mark.parametrize("inverse", [False, True], ids=["fwd", "bwd"])
-def test_ragged_2000_matches_oracle(inverse):
+def test_ragged_2000_matches_oracle(inverse, graph):
     sizes, offs, data = workloads.ragged()
     plan = sf.RaggedPlan(sizes, sf.FFT_BACKWARD if inverse else sf.FFT_FORWARD)
-    y = _run(plan, data).cpu().numpy()
+    y = _run(plan, data, graph).cpu().numpy()
     worst = _check_ragged(y, data, sizes, inverse)
-    print(f"ragged 2000 inverse={inverse}: worst rel-RMS {worst:.3e}", flush=True)
+    print(f"ragged 2000 inverse={inverse} graph={graph}: worst rel-RMS {worst:.3e}", flush=True)
     plan.close()
+
+
+def test_ragged_graph_and_direct_launch_agree_bitwise():
+    sizes, _, data = workloads.ragged(count=400, seed=31)
+    plan = sf.RaggedPlan(sizes)
+    a = _run(plan, data, graph=True)
+    b = _run(plan, data, graph=False)
+    c = _run(plan, data, graph=True)
+    assert torch.equal(a, b) and torch.equal(a, c)
+    plan.close()
+
+
+def test_ragged_more_workgroups_than_tasks_and_many_tasks():
+    # 3 transforms: fewer tasks than workgroups (most workgroups idle).
+    # 20000 transforms of 256: many tasks per workgroup.
+    for sizes in ([16384, 8192, 256], [256] * 20000):
+        sizes = np.array(sizes, dtype=np.int64)
+        x = workloads.complex_normal((int(sizes.sum()),), seed=int(sizes.size))
+        plan = sf.RaggedPlan(sizes)
+        _check_ragged(_run(plan, x).cpu().numpy(), x, sizes)
+        plan.close()
 
 
 @pytest.mark.parametrize("sizes", [
@@ -131,7 +153,11 @@ def test_ragged_exec_errors():
     base = buf.data_ptr()
     assert L.fft_exec_ragged(vp(plan.handle), vp(base + 4), vp(base + 8 * 1024), None) == sf.CODES["FFT_MISALIGNED"]
     assert L.fft_exec_ragged(vp(plan.handle), vp(base), vp(base + 8), None) == sf.CODES["FFT_OVERLAP"]
+    assert L.fft_exec_ragged_direct(vp(plan.handle), vp(base + 4), vp(base + 8 * 1024), None) == \
+        sf.CODES["FFT_MISALIGNED"]
+    assert L.fft_exec_ragged_direct(vp(plan.handle), vp(base), vp(base + 8), None) == sf.CODES["FFT_OVERLAP"]
     h = plan.handle
     plan.close()
     assert L.fft_exec_ragged(vp(h), vp(base), vp(base), None) == sf.CODES["FFT_INVALID_PLAN"]
+    assert L.fft_exec_ragged_direct(vp(h), vp(base), vp(base), None) == sf.CODES["FFT_INVALID_PLAN"]
     torch.cuda.synchronize()
