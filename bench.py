@@ -17,7 +17,7 @@ kernel, the FP64 oracle timed on the host cores (a baseline, not a target),
 and the comparisons the paper's method implies (fused forward+adjoint vs
 the plain chain, fused range compression vs its unfused chain, ragged
 persistent launch vs per-size plain launches, four-step vs single-pass at
-8192/16384, a same-footprint copy kernel).  The accuracy figures reported
+8192/16384, the four-step at 2^16 and 2^20, a same-footprint copy kernel).  The accuracy figures reported
 here are against numpy's FP64 FFT (an independent library routine); the
 parity tests against the oracle are the test suite's job.
 
@@ -371,6 +371,29 @@ def compare(args, torch, np, sf, metrics, workloads, T, dev, cs):
             p.close()
         comps[f"single_vs_four_step_n{n}_b{b}"] = rec
         log(f"n{n}", rec)
+        del xs, ys
+
+    # Lengths beyond one LDS-resident transform: the four-step only (two
+    # passes over HBM, so at most half the algorithmic rate of the peak).
+    for n, b in ((1 << 16, 256), (1 << 20, 16)):
+        x_h = workloads.complex_normal((b, n), seed=1006 + n % 997)
+        K = ring_count(2 * n * b * 8)
+        xs = [torch.from_numpy(x_h).to(dev)] + [torch.randn(b, n, dtype=torch.complex64, device=dev)
+                                                for _ in range(K - 1)]
+        ys = [torch.empty_like(xs[0]) for _ in range(K)]
+        p = sf.Plan(n, b, sf.FFT_FORWARD)
+        t = T.run(lambda i: p.exec(xs[i % K].data_ptr(), ys[i % K].data_ptr(), cs), iters, warm) / iters
+        p.exec(xs[0].data_ptr(), ys[0].data_ptr(), cs)
+        torch.cuda.synchronize()
+        rows = min(b, 4)
+        ok, worst, _, _ = metrics.gate(ys[0][:rows].cpu().numpy(), ref_fft(np, x_h[:rows]), x_h[:rows])
+        comps[f"four_step_n{n}_b{b}"] = {
+            "us": round(t * 1e6, 3), "GBs_algorithmic": round(16 * n * b / t / 1e9, 1),
+            "GBs_moved_two_passes": round(32 * n * b / t / 1e9, 1),
+            "gflops": round(metrics.gflops(n, b, t), 1), "worst_rel_rms_checked_rows": worst,
+            "gates_pass": bool(ok), "variant": p.describe()["four_step"]["name"]}
+        log(f"four-step n{n}", comps[f"four_step_n{n}_b{b}"])
+        p.close()
         del xs, ys
 
     # Ragged persistent launch vs per-size plain launches.

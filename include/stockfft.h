@@ -37,7 +37,7 @@ typedef struct stockfft_ragged_s *fft_ragged_plan_t;
 
 enum fft_status {
   FFT_SUCCESS = 0,
-  FFT_INVALID_SIZE = 1,      /* N not a power of two in [256, 16384] */
+  FFT_INVALID_SIZE = 1,      /* N not a power of two in [256, 2^20] ([256, 16384] ragged) */
   FFT_INVALID_BATCH = 2,     /* batch < 1, or batch * N * 8 overflows */
   FFT_INVALID_DIRECTION = 3, /* direction not FFT_FORWARD / FFT_BACKWARD */
   FFT_INVALID_POINTER = 4,   /* a required pointer is NULL */
@@ -63,7 +63,10 @@ enum fft_status {
  * fft_plan -- create a plan for `batch` transforms of length `n`.
  * Section II-A (definition), Section IV-D (synthesis rules).
  *   plan       out: the new handle; set to NULL on any error.
- *   n          transform length, a power of two in [256, 16384].
+ *   n          transform length, a power of two in [256, 1048576].  Up to
+ *              16384 a whole transform fits in one CU's LDS and a single-pass
+ *              kernel is available; above it only the four-step (eq. (3),
+ *              Section IV-D rule 3: N1 x 16384 with N1 <= 64) exists.
  *   batch      number of rows, >= 1.
  *   direction  FFT_FORWARD or FFT_BACKWARD.
  * The plan owns device memory for its twiddle tables (computed in FP64 on
@@ -80,8 +83,9 @@ int fft_plan(fft_plan_t *plan, int64_t n, int64_t batch, int direction);
  *   algorithm  FFT_ALGO_AUTO, FFT_ALGO_SINGLE_PASS or FFT_ALGO_FOUR_STEP.
  *   variant    NULL for the tuned choice, or a variant name listed by
  *              fft_variant_describe() of the matching kind and length.
- * Errors: as fft_plan, plus FFT_UNSUPPORTED (no four-step split for n) and
- * FFT_INVALID_ARGUMENT (unknown algorithm or variant name).
+ * Errors: as fft_plan, plus FFT_UNSUPPORTED (no four-step split for n, or
+ * FFT_ALGO_SINGLE_PASS with n > 16384) and FFT_INVALID_ARGUMENT (unknown
+ * algorithm or variant name).
  */
 int fft_plan_config(fft_plan_t *plan, int64_t n, int64_t batch, int direction, int algorithm,
                     const char *variant);

@@ -83,7 +83,8 @@ const FourStepVariant* find_four_step(const char* name) {
   return nullptr;
 }
 
-bool valid_size(int64_t n) { return n >= 256 && n <= 16384 && (n & (n - 1)) == 0; }
+bool valid_size(int64_t n) { return n >= 256 && n <= kMaxN && (n & (n - 1)) == 0; }
+bool valid_single_size(int64_t n) { return valid_size(n) && n <= kMaxSinglePassN; }
 
 int ilog2(int64_t n) {
   int l = 0;
@@ -117,17 +118,28 @@ void build_stockham_twiddles(const SingleVariant& v, std::vector<float>& out) {
   }
 }
 
-// Four-step table: entry [n1 - 1][k2] = W_N^{n1 k2}, n1 in [1, N1), k2 in [0, N2).
-void build_four_step_twiddles(int n1c, int n2c, std::vector<float>& out) {
+// Four-step second-stage table.  Full layout: entry [n1 - 1][k2] = W_N^{n1 k2},
+// n1 in [1, N1), k2 in [0, N2).  Two-level layout (large N): lo[j] = W_N^j for
+// j < 2^s, hi[j] = W_N^{j 2^s} for j < N / 2^s (s = floor(log2 N / 2)), so
+// W_N^m = hi[m >> s] lo[m mod 2^s]; then W_N1^j for j < N1.
+void build_four_step_twiddles(const FourStepVariant& f, std::vector<float>& out) {
   out.clear();
-  const int64_t N = (int64_t)n1c * n2c;
-  for (int n1 = 1; n1 < n1c; ++n1)
-    for (int64_t k2 = 0; k2 < n2c; ++k2) {
-      float re, im;
-      root_f32(n1 * k2, N, &re, &im);
-      out.push_back(re);
-      out.push_back(im);
-    }
+  const int64_t N = (int64_t)f.n1 * f.n2;
+  auto put = [&](int64_t m, int64_t L) {
+    float re, im;
+    root_f32(m, L, &re, &im);
+    out.push_back(re);
+    out.push_back(im);
+  };
+  if (!f.two_level) {
+    for (int n1 = 1; n1 < f.n1; ++n1)
+      for (int64_t k2 = 0; k2 < f.n2; ++k2) put(n1 * k2, N);
+    return;
+  }
+  const int s = ilog2(N) / 2;
+  for (int64_t j = 0; j < (int64_t(1) << s); ++j) put(j, N);
+  for (int64_t j = 0; j < (N >> s); ++j) put(j << s, N);
+  for (int j = 0; j < f.n1; ++j) put(j, f.n1);
 }
 
 int upload(const std::vector<float>& host, void** dev) {
@@ -251,6 +263,11 @@ void tuned_choice(int64_t n, int64_t batch, bool single_only, const SingleVarian
     *sv = e.v;
     *fs = e.fs;
   }
+  // Beyond one LDS-resident transform only the four-step exists: its first
+  // registered split unless a tuning entry chose another.
+  if (!*sv && !*fs && !single_only && n > kMaxSinglePassN)
+    for (int i = 0; i < num_four_step() && !*fs; ++i)
+      if (four_step_at(i).n == n) *fs = &four_step_at(i);
 }
 
 const SingleVariant* tuned_variant(int64_t n, int64_t batch) {
@@ -406,6 +423,7 @@ extern "C" int fft_plan_config(fft_plan_t* plan, int64_t n, int64_t batch, int d
       algorithm != FFT_ALGO_FOUR_STEP)
     return FFT_INVALID_ARGUMENT;
 
+  if (algorithm == FFT_ALGO_SINGLE_PASS && n > kMaxSinglePassN) return FFT_UNSUPPORTED;
   const SingleVariant* sv = nullptr;
   const FourStepVariant* fs = nullptr;
   if (algorithm == FFT_ALGO_FOUR_STEP) {
@@ -454,7 +472,7 @@ extern "C" int fft_plan_config(fft_plan_t* plan, int64_t n, int64_t batch, int d
   build_stockham_twiddles(*sv, host);
   rc = upload(host, &p->d_tw);
   if (!rc && fs) {
-    build_four_step_twiddles(fs->n1, fs->n2, host);
+    build_four_step_twiddles(*fs, host);
     rc = upload(host, &p->d_tw4);
     if (!rc) {
       p->ws_bytes = (size_t)n * (size_t)batch * 8;
@@ -623,12 +641,20 @@ static std::string describe_single(const SingleVariant& v) {
   return buf;
 }
 
+static int64_t four_step_table_entries(const FourStepVariant& f) {
+  if (!f.two_level) return (int64_t)(f.n1 - 1) * f.n2;
+  const int64_t N = (int64_t)f.n1 * f.n2;
+  const int s = ilog2(N) / 2;
+  return (int64_t(1) << s) + (N >> s) + f.n1;
+}
+
 static std::string describe_four_step(const FourStepVariant& f) {
   char buf[384];
   std::snprintf(buf, sizeof buf,
                 "{\"kind\":\"four_step\",\"name\":\"%s\",\"n\":%d,\"n1\":%d,\"n2\":%d,"
-                "\"sub_variant\":\"%s\",\"twiddle_entries\":%d}",
-                f.name, f.n, f.n1, f.n2, f.sub_name, f.tw_sub_elems + (f.n1 - 1) * f.n2);
+                "\"sub_variant\":\"%s\",\"two_level_twiddles\":%s,\"twiddle_entries\":%lld}",
+                f.name, f.n, f.n1, f.n2, f.sub_name, f.two_level ? "true" : "false",
+                (long long)(f.tw_sub_elems + four_step_table_entries(f)));
   return buf;
 }
 
@@ -655,7 +681,7 @@ extern "C" int fft_variant_twiddles(int index, float* out, int64_t cap_complex, 
     const SingleVariant* sub = find_single(f.sub_name);
     if (!sub) return FFT_INVALID_ARGUMENT;
     build_stockham_twiddles(*sub, host);
-    build_four_step_twiddles(f.n1, f.n2, tw4);
+    build_four_step_twiddles(f, tw4);
     host.insert(host.end(), tw4.begin(), tw4.end());
   }
   *count = (int64_t)host.size() / 2;
@@ -681,7 +707,9 @@ extern "C" int fft_plan_describe(fft_plan_t plan, char* buf, int64_t cap) {
 extern "C" const char* fft_status_string(int status) {
   switch (status) {
     case FFT_SUCCESS: return "success";
-    case FFT_INVALID_SIZE: return "invalid size: N must be a power of two in [256, 16384]";
+    case FFT_INVALID_SIZE:
+      return "invalid size: N must be a power of two in [256, 1048576] ([256, 16384] for ragged "
+             "batches)";
     case FFT_INVALID_BATCH: return "invalid batch";
     case FFT_INVALID_DIRECTION: return "invalid direction: use FFT_FORWARD (-1) or FFT_BACKWARD (+1)";
     case FFT_INVALID_POINTER: return "null pointer";

@@ -1,5 +1,8 @@
-// Four-step variants (the paper's synthesis rule 2, Section IV-D, with the
-// splits of Section V-D eq. (7)-(8) plus N2 = 2048 alternatives).
+// Four-step variants: the paper's synthesis rule 2 (Section IV-D) with the
+// splits of Section V-D eq. (7)-(8) plus N2 = 2048 alternatives, and the same
+// decomposition for lengths beyond one LDS-resident transform (rule 3's
+// multi-level case): N = N1 x 16384 up to 2^20, the second stage's N1-point
+// DFTs (N1 <= 64) done in registers with two-level twiddles.
 #include "kernels.hpp"
 
 namespace stockfft {
@@ -7,18 +10,32 @@ namespace stockfft {
 namespace {
 using Sub4096 = Shape<4096, 16, 1, 4, 16, 16, 16>;
 using Sub2048 = Shape<2048, 16, 1, 4, 16, 16, 8>;
+using Sub16384 = ShapeX<2, false, 4, 16384, 32, 1, 4, 16, 16, 16, 4>;
+constexpr const char* kSub16384 = "n16384_e32_c2_b1_p4_r16.16.16.4";
 }  // namespace
 
 const FourStepVariant* four_step_variants(int* count) {
   static const FourStepVariant table[] = {
     {"fs8192_2x4096", 8192, 2, 4096, "n4096_e16_b1_p4_r16.16.16", Sub4096::TW_ELEMS,
-     &launch_four_step_columns<Sub4096, 2>, &launch_four_step_combine<2, 4096>},
+     &launch_four_step_columns<Sub4096, 2>, &launch_four_step_combine<2, 4096, false>, false},
     {"fs8192_4x2048", 8192, 4, 2048, "n2048_e16_b1_p4_r16.16.8", Sub2048::TW_ELEMS,
-     &launch_four_step_columns<Sub2048, 4>, &launch_four_step_combine<4, 2048>},
+     &launch_four_step_columns<Sub2048, 4>, &launch_four_step_combine<4, 2048, false>, false},
     {"fs16384_4x4096", 16384, 4, 4096, "n4096_e16_b1_p4_r16.16.16", Sub4096::TW_ELEMS,
-     &launch_four_step_columns<Sub4096, 4>, &launch_four_step_combine<4, 4096>},
+     &launch_four_step_columns<Sub4096, 4>, &launch_four_step_combine<4, 4096, false>, false},
     {"fs16384_8x2048", 16384, 8, 2048, "n2048_e16_b1_p4_r16.16.8", Sub2048::TW_ELEMS,
-     &launch_four_step_columns<Sub2048, 8>, &launch_four_step_combine<8, 2048>},
+     &launch_four_step_columns<Sub2048, 8>, &launch_four_step_combine<8, 2048, false>, false},
+    {"fs32768_2x16384", 32768, 2, 16384, kSub16384, Sub16384::TW_ELEMS,
+     &launch_four_step_columns<Sub16384, 2>, &launch_four_step_combine<2, 16384, true>, true},
+    {"fs65536_4x16384", 65536, 4, 16384, kSub16384, Sub16384::TW_ELEMS,
+     &launch_four_step_columns<Sub16384, 4>, &launch_four_step_combine<4, 16384, true>, true},
+    {"fs131072_8x16384", 131072, 8, 16384, kSub16384, Sub16384::TW_ELEMS,
+     &launch_four_step_columns<Sub16384, 8>, &launch_four_step_combine<8, 16384, true>, true},
+    {"fs262144_16x16384", 262144, 16, 16384, kSub16384, Sub16384::TW_ELEMS,
+     &launch_four_step_columns<Sub16384, 16>, &launch_four_step_combine<16, 16384, true>, true},
+    {"fs524288_32x16384", 524288, 32, 16384, kSub16384, Sub16384::TW_ELEMS,
+     &launch_four_step_columns<Sub16384, 32>, &launch_four_step_combine<32, 16384, true>, true},
+    {"fs1048576_64x16384", 1048576, 64, 16384, kSub16384, Sub16384::TW_ELEMS,
+     &launch_four_step_columns<Sub16384, 64>, &launch_four_step_combine<64, 16384, true>, true},
   };
   *count = (int)(sizeof(table) / sizeof(table[0]));
   return table;

@@ -19,7 +19,8 @@ const SingleVariant* find_single(const char* name);
 const SingleVariant* tuned_variant(int64_t n, int64_t batch);
 void tuned_choice(int64_t n, int64_t batch, bool single_only, const SingleVariant** sv,
                   const FourStepVariant** fs);
-bool valid_size(int64_t n);
+bool valid_size(int64_t n);         // any plan length
+bool valid_single_size(int64_t n);  // lengths with a single-pass kernel (and ragged batches)
 int ilog2(int64_t n);
 void build_stockham_twiddles(const SingleVariant& v, std::vector<float>& out);
 int upload(const std::vector<float>& host, void** dev);

@@ -223,10 +223,54 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_four_step_columns(const 
   global_store_row<S>(a, y + (row * N1 + n1) * S::N, t, true);
 }
 
-template <int N1, int N2, bool INV>
+// Length-N1 DFT in registers for the four-step second stage.  N1 <= 16: the
+// exact radix-2 DIT of Dft.  N1 = 32, 64: N1 = P Q with P = 16, i.e. P-point
+// DFTs of the Q interleaved sub-sequences v[Q p + q], twiddles W_N1^{q kp}
+// (from wn, wn[j] = W_N1^j in the forward direction), then Q-point DFTs; the
+// result X[k] is left in v[slot(k)].
+template <int N1, bool INV>
+struct RegDft {
+  static constexpr int P = N1 <= 16 ? N1 : 16;
+  static constexpr int Q = N1 / P;
+  static constexpr int slot(int k) { return Q == 1 ? k : Q * (k % P) + k / P; }
+  __device__ __forceinline__ static void run(c32 (&v)[N1], const c32* wn) {
+    if constexpr (Q == 1) {
+      Dft<N1, INV>::run(v);
+    } else {
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        c32 t[P];
+#pragma unroll
+        for (int p = 0; p < P; ++p) t[p] = v[Q * p + q];
+        Dft<P, INV>::run(t);
+#pragma unroll
+        for (int kp = 0; kp < P; ++kp)
+          v[Q * kp + q] = (q == 0 || kp == 0) ? t[kp] : ctw<INV>(t[kp], wn[q * kp]);
+      }
+#pragma unroll
+      for (int kp = 0; kp < P; ++kp) {
+        c32 u[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) u[q] = v[Q * kp + q];
+        Dft<Q, INV>::run(u);
+#pragma unroll
+        for (int kq = 0; kq < Q; ++kq) v[Q * kp + kq] = u[kq];
+      }
+    }
+  }
+};
+
+constexpr int half_log2(int64_t n) {
+  int l = 0;
+  while ((int64_t(1) << l) < n) ++l;
+  return l / 2;
+}
+
+template <int N1, int N2, bool INV, bool TWO_LEVEL>
 __global__ __launch_bounds__(256) void k_four_step_combine(const c32* y, c32* out,
                                                            const c32* __restrict__ tw4, int64_t rows) {
   constexpr int N = N1 * N2;
+  static_assert(TWO_LEVEL || N1 <= 16, "the full twiddle table serves N1 <= 16");
   const int64_t gid = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const int64_t row = gid / N2;
   const int k2 = (int)(gid - row * N2);
@@ -234,12 +278,27 @@ __global__ __launch_bounds__(256) void k_four_step_combine(const c32* y, c32* ou
   const c32* src = y + row * N + k2;
   c32 v[N1];
   v[0] = src[0];
+  const c32* wn = nullptr;
+  if constexpr (TWO_LEVEL) {
+    constexpr int SL = half_log2(N);
+    const c32* lo = tw4;
+    const c32* hi = tw4 + (1 << SL);
+    wn = hi + (N >> SL);
 #pragma unroll
-  for (int n1 = 1; n1 < N1; ++n1) v[n1] = ctw<INV>(src[(int64_t)n1 * N2], tw4[(n1 - 1) * N2 + k2]);
-  Dft<N1, INV>::run(v);
+    for (int n1 = 1; n1 < N1; ++n1) {
+      const int m = n1 * k2;  // < N
+      const c32 w = cmul(hi[m >> SL], lo[m & ((1 << SL) - 1)]);
+      v[n1] = ctw<INV>(src[(int64_t)n1 * N2], w);
+    }
+  } else {
+#pragma unroll
+    for (int n1 = 1; n1 < N1; ++n1)
+      v[n1] = ctw<INV>(src[(int64_t)n1 * N2], tw4[(n1 - 1) * N2 + k2]);
+  }
+  RegDft<N1, INV>::run(v, wn);
   c32* dst = out + row * N + k2;
 #pragma unroll
-  for (int k1 = 0; k1 < N1; ++k1) dst[(int64_t)k1 * N2] = v[k1];
+  for (int k1 = 0; k1 < N1; ++k1) dst[(int64_t)k1 * N2] = v[RegDft<N1, INV>::slot(k1)];
 }
 
 template <class S, int N1>
@@ -262,7 +321,7 @@ hipError_t launch_four_step_columns(const void* x, void* y, const void* tw, int6
   return hipGetLastError();
 }
 
-template <int N1, int N2>
+template <int N1, int N2, bool TWO_LEVEL>
 hipError_t launch_four_step_combine(const void* y, void* out, const void* tw4, int64_t batch,
                                     bool inverse, hipStream_t s) {
   static_assert(N2 % 256 == 0, "combine blocks cover 256 consecutive k2");
@@ -275,9 +334,11 @@ hipError_t launch_four_step_combine(const void* y, void* out, const void* tw4, i
     c32* op = static_cast<c32*>(out) + r0 * N1 * N2;
     const c32* twp = static_cast<const c32*>(tw4);
     if (inverse)
-      k_four_step_combine<N1, N2, true><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(yp, op, twp, rows);
+      k_four_step_combine<N1, N2, true, TWO_LEVEL>
+          <<<dim3((unsigned)blocks), dim3(256), 0, s>>>(yp, op, twp, rows);
     else
-      k_four_step_combine<N1, N2, false><<<dim3((unsigned)blocks), dim3(256), 0, s>>>(yp, op, twp, rows);
+      k_four_step_combine<N1, N2, false, TWO_LEVEL>
+          <<<dim3((unsigned)blocks), dim3(256), 0, s>>>(yp, op, twp, rows);
   }
   return hipGetLastError();
 }

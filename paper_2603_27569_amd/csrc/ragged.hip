@@ -251,7 +251,7 @@ extern "C" int fft_plan_ragged(fft_ragged_plan_t* plan, const int64_t* sizes, in
   if (direction != FFT_FORWARD && direction != FFT_BACKWARD) return FFT_INVALID_DIRECTION;
   int64_t total = 0;
   for (int64_t i = 0; i < count; ++i) {
-    if (!valid_size(sizes[i])) return FFT_INVALID_SIZE;
+    if (!valid_single_size(sizes[i])) return FFT_INVALID_SIZE;
     total += sizes[i];
   }
   int dev = 0;
@@ -482,7 +482,7 @@ extern "C" int fft_destroy_ragged(fft_ragged_plan_t plan) {
 
 extern "C" int fft_tune_set_ragged(int64_t n, const char* shape) {
   if (!shape) return FFT_INVALID_POINTER;
-  if (!valid_size(n)) return FFT_INVALID_SIZE;
+  if (!valid_single_size(n)) return FFT_INVALID_SIZE;
   const int s = shape_index(shape);
   if (s < 0 || kShapes[s].n != n) return FFT_INVALID_ARGUMENT;
   std::lock_guard<std::mutex> lk(g_rtune_mu);
@@ -492,7 +492,7 @@ extern "C" int fft_tune_set_ragged(int64_t n, const char* shape) {
 
 extern "C" int fft_tune_query_ragged(int64_t n, char* buf, int64_t cap) {
   if (!buf) return FFT_INVALID_POINTER;
-  if (!valid_size(n)) return FFT_INVALID_SIZE;
+  if (!valid_single_size(n)) return FFT_INVALID_SIZE;
   int s;
   {
     std::lock_guard<std::mutex> lk(g_rtune_mu);
@@ -507,7 +507,7 @@ extern "C" int fft_tune_query_ragged(int64_t n, char* buf, int64_t cap) {
 
 extern "C" int fft_ragged_shapes(int64_t n, char* buf, int64_t cap) {
   if (!buf) return FFT_INVALID_POINTER;
-  if (!valid_size(n)) return FFT_INVALID_SIZE;
+  if (!valid_single_size(n)) return FFT_INVALID_SIZE;
   std::string s;
   for (int i = 0; i < kNumShapes; ++i)
     if (kShapes[i].n == n) {

@@ -15,6 +15,10 @@ constexpr int kMaxPasses = 8;
 
 // Grids larger than this many workgroups are split into several launches.
 constexpr int64_t kDefaultMaxGroupsPerLaunch = int64_t(1) << 20;
+// Lengths: single pass up to kMaxSinglePassN (a whole transform in LDS), the
+// four-step above it, up to kMaxN.
+constexpr int64_t kMaxSinglePassN = 16384;
+constexpr int64_t kMaxN = int64_t(1) << 20;
 int64_t max_groups_per_launch();
 void set_max_groups_per_launch(int64_t groups);
 
@@ -60,6 +64,11 @@ struct FourStepVariant {
   int tw_sub_elems;
   FourStepColumnsFn columns;
   FourStepCombineFn combine;
+  // Twiddle layout of the second stage: false -- the full table
+  // [n1 - 1][k2] = W_N^{n1 k2}; true (large N) -- W_N^m as the product of
+  // two short tables, lo[j] = W_N^j (j < 2^s) and hi[j] = W_N^{j 2^s}
+  // (j < N / 2^s), s = floor(log2 N / 2), followed by W_N1^j (j < N1).
+  bool two_level;
 };
 
 const FourStepVariant* four_step_variants(int* count);

@@ -43,11 +43,26 @@ def per_row_errors(y, ref, x):
 
 
 REL_RMS_GATE = 5e-6
-MAX_ABS_GATE = 1e-5  # times the input row norm
+MAX_ABS_GATE = 1e-5  # times the input row norm, for N <= 16384
 
 
-def gate(y, ref, x, rel_gate=REL_RMS_GATE, abs_gate=MAX_ABS_GATE):
-    """Return (ok, worst_rel_rms, median_rel_rms, worst_abs_ratio)."""
+def max_abs_gate(n):
+    """The max-abs tolerance (times ||x_b||_2) for length n.
+
+    1e-5 up to N = 16384, the paper's range.  Above it an output bin can
+    reach sqrt(N) ||x_b||_2 (Cauchy-Schwarz), and one unit in the last place
+    of such a bin, 2^-23 sqrt(N) ||x_b||_2, exceeds 1e-5 ||x_b||_2 from
+    N = 32768 on; there the gate is two such units, 2^-22 sqrt(N)."""
+    if n <= 16384:
+        return MAX_ABS_GATE
+    return 2.0 ** -22 * float(n) ** 0.5
+
+
+def gate(y, ref, x, rel_gate=REL_RMS_GATE, abs_gate=None):
+    """Return (ok, worst_rel_rms, median_rel_rms, worst_abs_ratio).  abs_gate
+    defaults to max_abs_gate(N) for the rows' length N."""
+    if abs_gate is None:
+        abs_gate = max_abs_gate(np.asarray(y).shape[-1])
     rel, mabs, xn = per_row_errors(y, ref, x)
     with np.errstate(divide="ignore", invalid="ignore"):
         ratio = np.where(xn > 0, mabs / xn, np.where(mabs == 0, 0.0, np.inf))

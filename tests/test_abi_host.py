@@ -52,7 +52,7 @@ def _plan_rc(n, batch, direction, algo=0, variant=None, null_out=False):
     return rc, h.value
 
 
-@pytest.mark.parametrize("n", [0, 1, 128, 255, 257, 3000, 32768, -4096])
+@pytest.mark.parametrize("n", [0, 1, 128, 255, 257, 3000, 3 * 2 ** 15, 2 ** 21, -4096])
 def test_invalid_size_rejected_before_device(n):
     rc, h = _plan_rc(n, 1, -1)
     assert rc == _lib.CODES["FFT_INVALID_SIZE"] and h is None
@@ -182,7 +182,10 @@ def test_variant_inventory():
     singles = [v for v in vs if v["kind"] == "single"]
     fours = [v for v in vs if v["kind"] == "four_step"]
     assert {v["n"] for v in singles} == {256, 512, 1024, 2048, 4096, 8192, 16384}
-    assert {v["n"] for v in fours} == {8192, 16384}
+    assert {v["n"] for v in fours} == {2 ** e for e in range(13, 21)}
+    for v in fours:
+        assert v["n1"] * v["n2"] == v["n"]
+        assert v["two_level_twiddles"] == (v["n"] > 16384)
     names = [v["name"] for v in vs]
     assert len(set(names)) == len(names)
     for v in singles:
@@ -271,11 +274,18 @@ def test_twiddle_tables_rounded_once_from_fp64():
                 for k in range(ns):
                     expect.append(_exact_roots(k * r, L))
             ns *= r_p
-        if v["kind"] == "four_step":
+        if v["kind"] == "four_step" and not v["two_level_twiddles"]:
             N = v["n"]
             for n1 in range(1, v["n1"]):
                 for k2 in range(v["n2"]):
                     expect.append(_exact_roots(n1 * k2, N))
+        elif v["kind"] == "four_step":
+            # lo[j] = W_N^j (j < 2^s), hi[j] = W_N^(j 2^s) (j < N / 2^s), W_N1^j (j < N1)
+            N = v["n"]
+            s = (N.bit_length() - 1) // 2
+            expect += [_exact_roots(j, N) for j in range(2 ** s)]
+            expect += [_exact_roots(j << s, N) for j in range(N >> s)]
+            expect += [_exact_roots(j, v["n1"]) for j in range(v["n1"])]
         expect = np.array(expect)
         assert tab.shape == expect.shape, v["name"]
         assert _ulp_err(tab, expect) <= 0.5 + 1e-6, v["name"]

@@ -60,6 +60,29 @@ def test_four_step_variant_parity(v, inverse):
     _check(_host(y), x, inverse)
 
 
+@pytest.mark.parametrize("n", [1 << 15, 1 << 17, 1 << 20])
+def test_large_n_auto_plan_closed_forms(n):
+    # Beyond 16384 the default plan is the four-step; a shifted delta gives
+    # W_N^{n0 k} and a tone gives one bin of height N.
+    n0, k0 = 12345 % n, (77 * n) // 100 + 3
+    x = np.zeros((2, n), np.complex64)
+    x[0, n0] = 1.0
+    m = np.arange(n)
+    x[1] = np.exp(2j * np.pi * ((k0 * m) % n) / n).astype(np.complex64)
+    y = _host(sf.fft(_gpu(x)))
+    _check(y, x)
+    exact = np.exp(-2j * np.pi * ((n0 * m) % n) / n)
+    assert np.max(np.abs(y[0] - exact)) <= 1e-5
+    assert int(np.argmax(np.abs(y[1]))) == k0
+    assert abs(y[1, k0] - n) <= 1e-5 * n
+    p = sf.Plan(n, 2)
+    assert p.describe()["algorithm"] == "four_step"
+    p.close()
+    with pytest.raises(sf.StockfftError) as e:
+        sf.Plan(n, 2, algorithm=sf.FFT_ALGO_SINGLE_PASS)
+    assert e.value.name == "FFT_UNSUPPORTED"
+
+
 def test_plain_uniform_n256_delta_tone():
     n, b = 256, 64
     x = workloads.plain_uniform(n, b)
@@ -206,6 +229,46 @@ def test_spectral_energy_loss_only_and_scale():
     _, ref = oracle.spectral_energy(x, w)
     rel = np.linalg.norm(_host(g2) - (-0.5) * ref) / np.linalg.norm(0.5 * ref)
     assert rel <= 1e-4
+
+
+def _fixed_order_total(rows):
+    """The loss total's summation order written out on the host in FP32:
+    1024 lanes each add rows i, i + 1024, ...; then a halving tree (lane t
+    adds lane t + w for w = 512, 256, ..., 1)."""
+    r = np.asarray(rows, dtype=np.float32)
+    lanes = np.zeros(1024, dtype=np.float32)
+    for i in range(0, len(r), 1024):
+        chunk = r[i:i + 1024]
+        lanes[:len(chunk)] = lanes[:len(chunk)] + chunk
+    w = 512
+    while w > 0:
+        lanes[:w] = lanes[:w] + lanes[w:2 * w]
+        w //= 2
+    return float(lanes[0])
+
+
+@pytest.mark.parametrize("limit", [0, 7], ids=["one_launch", "split_launches"])
+def test_spectral_energy_total_reproducible(limit):
+    # The loss total must cover every row (also when the fused kernel is split
+    # over several launches), equal the fixed-order sum of the row losses bit
+    # for bit, and repeat exactly from call to call.
+    x, w = workloads.spectral_energy_inputs(n=2048, batch=3000, seed=21, wseed=22)
+    xt, wt = _gpu(x), _gpu(w)
+    try:
+        sf.fft_set_launch_limit(limit)
+        sf.clear_plan_cache()
+        totals = []
+        for _ in range(3):
+            total, rows, _ = sf.spectral_energy(xt, wt, want_grad=(len(totals) != 1))
+            torch.cuda.synchronize()
+            totals.append(float(_host(total)[0]))
+    finally:
+        sf.fft_set_launch_limit(0)
+        sf.clear_plan_cache()
+    assert totals[0] == totals[1] == totals[2]
+    assert totals[0] == _fixed_order_total(_host(rows))
+    ref_rows, _ = oracle.spectral_energy(x, w)
+    assert abs(totals[0] - ref_rows.sum()) / ref_rows.sum() <= 1e-5
 
 
 def test_spectral_energy_unit_weight_closed_form():

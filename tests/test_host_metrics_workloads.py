@@ -33,6 +33,26 @@ def test_bytes_convention():
     assert metrics.fft_flops(4096, 256) == 62914560
 
 
+def test_max_abs_gate_by_length():
+    for n in (256, 4096, 16384):
+        assert metrics.max_abs_gate(n) == 1e-5
+    for e in range(15, 21):
+        n = 2 ** e
+        # two units in the last place of the largest bin sqrt(N) ||x|| can give
+        assert metrics.max_abs_gate(n) == 2.0 ** -22 * 2.0 ** (e / 2)
+        assert metrics.max_abs_gate(n) > 1e-5
+    # a length-2^20 tone: the peak bin N ||x|| / sqrt(N) off by one ulp passes
+    n = 2 ** 20
+    x = np.exp(2j * np.pi * 3 * np.arange(n) / n)[None, :]
+    ref = np.zeros_like(x)
+    ref[0, 3] = n
+    y = ref.copy()
+    y[0, 3] += np.spacing(np.float32(n))
+    assert metrics.gate(y, ref, x)[0]
+    y[0, 3] += 4 * np.spacing(np.float32(n))
+    assert not metrics.gate(y, ref, x)[0]
+
+
 def test_gate_logic():
     x = workloads.plain_normal(64, 4, seed=3).astype(np.complex128)
     ok, worst, med, ab = metrics.gate(x, x, x)
