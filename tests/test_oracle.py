@@ -28,7 +28,7 @@ def _close(a, b, tol):
 
 
 ALL_DIRECT = [1, 2, 3, 4, 5, 7, 8, 12, 16, 64, 100]
-ALL_FFT = [1, 2, 4, 8, 64, 128, 256, 1024, 4096]
+ALL_FFT = [1, 2, 4, 8, 64, 128, 256, 1024, 4096, 2 ** 17]
 
 
 def _roots(n, sign):
@@ -107,7 +107,7 @@ def test_recursive_equals_direct(n):
         assert rel <= 1e-12, (n, inv, rel)
 
 
-@pytest.mark.parametrize("n", [256, 512, 1024, 2048, 4096, 8192, 16384])
+@pytest.mark.parametrize("n", [256, 512, 1024, 2048, 4096, 8192, 16384, 2 ** 15, 2 ** 18, 2 ** 20])
 def test_numpy_cross_check(n):
     x = _rand(n, 2, seed=100 + n)
     f = oracle.fft(x)
@@ -118,7 +118,7 @@ def test_numpy_cross_check(n):
     assert np.linalg.norm(b - ref_b) / np.linalg.norm(ref_b) <= 1e-13
 
 
-@pytest.mark.parametrize("n", [16, 256, 4096])
+@pytest.mark.parametrize("n", [16, 256, 4096, 2 ** 20])
 def test_invariants(n):
     x = _rand(n, 1, seed=1)[0]
     y = _rand(n, 1, seed=2)[0]
