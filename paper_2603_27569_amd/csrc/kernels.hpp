@@ -280,14 +280,30 @@ __global__ __launch_bounds__(256) void k_four_step_combine(const c32* y, c32* ou
   v[0] = src[0];
   const c32* wn = nullptr;
   if constexpr (TWO_LEVEL) {
+    // W_N^{n1 k2} for n1 = RA j + i as W_N^{RA j k2} W_N^{i k2}: 2 (RA - 1 +
+    // N1 / RA - 1) table reads per lane instead of 2 (N1 - 1); each factor is
+    // hi[m >> SL] lo[m mod 2^SL] of two once-rounded entries.
     constexpr int SL = half_log2(N);
+    constexpr int RA = N1 >= 16 ? 8 : N1;
+    constexpr int RB = N1 / RA;
     const c32* lo = tw4;
     const c32* hi = tw4 + (1 << SL);
     wn = hi + (N >> SL);
+    c32 bi[RA], cj[RB];
+#pragma unroll
+    for (int i = 1; i < RA; ++i) {
+      const int m = i * k2;  // < N
+      bi[i] = cmul(hi[m >> SL], lo[m & ((1 << SL) - 1)]);
+    }
+#pragma unroll
+    for (int j = 1; j < RB; ++j) {
+      const int m = RA * j * k2;  // < N
+      cj[j] = cmul(hi[m >> SL], lo[m & ((1 << SL) - 1)]);
+    }
 #pragma unroll
     for (int n1 = 1; n1 < N1; ++n1) {
-      const int m = n1 * k2;  // < N
-      const c32 w = cmul(hi[m >> SL], lo[m & ((1 << SL) - 1)]);
+      const int i = n1 % RA, j = n1 / RA;
+      const c32 w = j == 0 ? bi[i] : i == 0 ? cj[j] : cmul(cj[j], bi[i]);
       v[n1] = ctw<INV>(src[(int64_t)n1 * N2], w);
     }
   } else {

@@ -20,6 +20,9 @@ parity tests check each one against the FP64 reference), so the search is
 on speed alone.
 
 Usage: python -m paper_2603_27569_amd.tune [--out tune_gfx950.json] [--quick]
+       python -m paper_2603_27569_amd.tune --run-variants N BATCH [--iters K]
+         (no search: runs every variant of length N, K launches each, so that
+         an external profiler can attribute counters to each variant)
 """
 import argparse
 import json
@@ -168,12 +171,38 @@ def run(out_path, quick=False, log=print):
     return doc
 
 
+def run_variants(n, batch, iters=10, log=print):
+    """Runs each compiled variant of length n (forward, batch rows) `iters`
+    times on one pair of buffers and synchronises; no timing, no choice."""
+    import torch
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    x = torch.randn(batch, n, dtype=torch.complex64, device=dev)
+    y = torch.empty_like(x)
+    for v in variants():
+        if v["n"] != n:
+            continue
+        algo = FFT_ALGO_SINGLE_PASS if v["kind"] == "single" else FFT_ALGO_FOUR_STEP
+        p = Plan(n, batch, FFT_FORWARD, algo, v["name"])
+        for _ in range(iters):
+            p.exec(x.data_ptr(), y.data_ptr(), stream.cuda_stream)
+        torch.cuda.synchronize()
+        p.close()
+        log(f"ran {v['name']} x{iters}")
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--out", default="tune_gfx950.json")
     ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--run-variants", nargs=2, type=int, metavar=("N", "BATCH"))
+    ap.add_argument("--iters", type=int, default=10)
     a = ap.parse_args(argv)
-    run(a.out, a.quick, log=lambda *x: print(*x, file=sys.stderr, flush=True))
+    log = lambda *x: print(*x, file=sys.stderr, flush=True)  # noqa: E731
+    if a.run_variants:
+        run_variants(a.run_variants[0], a.run_variants[1], a.iters, log=log)
+        return 0
+    run(a.out, a.quick, log=log)
     return 0
 
 
