@@ -634,9 +634,11 @@ static std::string describe_single(const SingleVariant& v) {
   std::snprintf(buf, sizeof buf,
                 "{\"kind\":\"single\",\"name\":\"%s\",\"n\":%d,\"values_per_lane\":%d,"
                 "\"lanes_per_transform\":%d,\"transforms_per_workgroup\":%d,\"pad_log2\":%d,"
+                "\"lds_layout\":\"%s\","
                 "\"passes\":%d,\"radices\":%s,\"exchange_rounds\":%d,\"threads\":%d,"
                 "\"lds_bytes\":%d,\"twiddle_entries\":%d,\"barriers\":%d}",
-                v.name, v.n, v.e, v.t, v.tpb, v.padlog, v.npass, radices_json(v).c_str(),
+                v.name, v.n, v.e, v.t, v.tpb, v.padlog,
+                v.padlog > 0 ? "pad" : v.padlog < 0 ? "xor" : "none", v.npass, radices_json(v).c_str(),
                 v.chunks, v.threads, v.lds_bytes, v.tw_elems, barriers_of(v));
   return buf;
 }

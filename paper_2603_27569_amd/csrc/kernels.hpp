@@ -34,7 +34,7 @@ __device__ __forceinline__ void global_store_row(const c32 (&a)[S::E], c32* dst,
 template <class S, bool INV>
 __global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham(const c32* in, c32* out,
                                                          const c32* tw, int64_t rows) {
-  __shared__ c32 lds_all[S::TPB * S::LDS_ELEMS];
+  __shared__ alignas(16) c32 lds_all[S::TPB * S::LDS_ELEMS];
   const int tid = threadIdx.x;
   const int slot = tid / S::T;
   const int t = tid - slot * S::T;
@@ -86,7 +86,7 @@ template <class S>
 __global__ __launch_bounds__(S::THREADS, S::WPE) void k_spectral_energy(
     const c32* x, const float* __restrict__ w, const float* __restrict__ scale, c32* grad,
     float* __restrict__ row_loss, const c32* tw, int64_t rows) {
-  __shared__ c32 lds_all[S::TPB * S::LDS_ELEMS];
+  __shared__ alignas(16) c32 lds_all[S::TPB * S::LDS_ELEMS];
   __shared__ float red[(S::THREADS + 63) / 64];
   const int tid = threadIdx.x;
   const int slot = tid / S::T;
@@ -152,7 +152,7 @@ template <class S>
 __global__ __launch_bounds__(S::THREADS, S::WPE) void k_matched_filter(const c32* x, const c32* __restrict__ h,
                                                                c32* out, const c32* tw,
                                                                int64_t rows) {
-  __shared__ c32 lds_all[S::TPB * S::LDS_ELEMS];
+  __shared__ alignas(16) c32 lds_all[S::TPB * S::LDS_ELEMS];
   const int tid = threadIdx.x;
   const int slot = tid / S::T;
   const int t = tid - slot * S::T;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_four_step_columns(const 
                                                                   const c32* tw,
                                                                   int64_t rows) {
   static_assert(S::TPB == 1, "four-step sub-transforms use one transform per workgroup");
-  __shared__ c32 lds[S::LDS_ELEMS];
+  __shared__ alignas(16) c32 lds[S::LDS_ELEMS];
   const int64_t i = blockIdx.x;
   const int64_t grp = i / (kXcds * N1);
   const int r = (int)(i - grp * kXcds * N1);

@@ -167,7 +167,7 @@ __device__ __forceinline__ void run_length_serial(int c, const int* r, const Rag
 
 template <bool INV>
 __global__ __launch_bounds__(kRaggedThreads, 4) void k_ragged(RaggedArgs A) {
-  __shared__ c32 lds_all[kLdsElems];
+  __shared__ alignas(16) c32 lds_all[kLdsElems];
   int r[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) r[i] = A.wg_cls[8 * blockIdx.x + i];

@@ -144,8 +144,9 @@ struct RadixList {
   static constexpr int r[P] = {Rs...};
 };
 
-// N points, E values per lane, TPB transforms per workgroup, LDS pad of one
-// element every 2^PADLOG (0 = no pad), radices of the passes in order.
+// N points, E values per lane, TPB transforms per workgroup, LDS layout
+// PADLOG (> 0: a pad element every 2^PADLOG; 0: none; -1: XOR swizzle, see
+// pidx), radices of the passes in order.
 //
 // C > 1 splits every exchange into C rounds through a buffer of N/C elements
 // (plus pad): the transform stays whole in registers and the LDS is only the
@@ -173,7 +174,7 @@ struct ShapeX {
   static constexpr int P = L::P;
   static constexpr int THREADS = T * TPB;
   static constexpr int CHUNK = N / C;
-  static constexpr int LDS_ELEMS = CHUNK + (PADLOG ? (CHUNK >> PADLOG) : 0);
+  static constexpr int LDS_ELEMS = CHUNK + (PADLOG > 0 ? (CHUNK >> PADLOG) : 0);
   static constexpr int radix(int p) { return L::r[p]; }
   static constexpr int ns(int p) {
     int s = 1;
@@ -204,8 +205,16 @@ struct ShapeX {
     return true;
   }
   static_assert(valid(), "inconsistent Stockham shape");
+  static_assert(PADLOG >= -1 && (PADLOG >= 0 || (CHUNK % 16 == 0 && radix(0) % 2 == 0)),
+                "unknown LDS layout");
+  // Physical LDS slot of exchange position i.  The XOR swizzle permutes the
+  // pairs of each 16-element row (one sweep of the LDS banks) by bits 4..6 of
+  // i: the stride-16 writes of a radix-16 pass then spread over the banks as
+  // with padding, while pairs (2k, 2k + 1) stay adjacent and in order, so
+  // they can still move as one 16-byte access, and no space is added.
   __device__ __forceinline__ static int pidx(int i) {
     if constexpr (PADLOG > 0) return i + (i >> PADLOG);
+    else if constexpr (PADLOG < 0) return i ^ (((i >> 4) & 7) << 1);
     else return i;
   }
 };
@@ -304,12 +313,30 @@ __device__ __forceinline__ void exchange(c32 (&a)[S::E], c32* lds, int t) {
     for (int b = h * BPC; b < (h + 1) * BPC; ++b) {
       const int j = t + b * S::T;
       const int base = (j / NS) * NS * R + (j & (NS - 1)) - h * S::CHUNK;
+      if constexpr (S::PADLOG < 0 && NS == 1) {
+        // The swizzle keeps the pairs of this butterfly's consecutive
+        // outputs adjacent and 16-byte aligned: one 16-byte store per pair.
 #pragma unroll
-      for (int k = 0; k < R; ++k) lds[S::pidx(base + k * NS)] = a[b + k * BPT];
+        for (int k = 0; k < R; k += 2) {
+          const c32 u = a[b + k * BPT], v = a[b + (k + 1) * BPT];
+          *reinterpret_cast<float4*>(lds + S::pidx(base + k)) = float4{u.x, u.y, v.x, v.y};
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < R; ++k) lds[S::pidx(base + k * NS)] = a[b + k * BPT];
+      }
     }
     __syncthreads();
+    if constexpr (S::PADLOG < 0 && S::T % 128 == 0 && S::CHUNK % 128 == 0) {
+      // The swizzle leaves bits 7 and up alone, so the read positions
+      // t + m T stay a constant stride apart after it.
+      const int base = S::pidx(t);
 #pragma unroll
-    for (int m = h * MPC; m < (h + 1) * MPC; ++m) nxt[m] = lds[S::pidx(t + m * S::T - h * S::CHUNK)];
+      for (int m = h * MPC; m < (h + 1) * MPC; ++m) nxt[m] = lds[base + m * S::T - h * S::CHUNK];
+    } else {
+#pragma unroll
+      for (int m = h * MPC; m < (h + 1) * MPC; ++m) nxt[m] = lds[S::pidx(t + m * S::T - h * S::CHUNK)];
+    }
   }
 #pragma unroll
   for (int m = 0; m < S::E; ++m) a[m] = nxt[m];

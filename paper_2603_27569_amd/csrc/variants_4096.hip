@@ -12,5 +12,6 @@ STOCKFFT_VARIANT_GROUP(variants_4096,
   make_variant<Shape<4096, 16, 1, 4, 16, 16, 16>>("n4096_e16_b1_p4_r16.16.16"),
   make_variant<Shape<4096, 16, 1, 0, 16, 16, 16>>("n4096_e16_b1_p0_r16.16.16"),
   make_variant<Shape<4096, 16, 1, 5, 16, 16, 16>>("n4096_e16_b1_p5_r16.16.16"),
+  make_variant<Shape<4096, 16, 1, -1, 16, 16, 16>>("n4096_e16_b1_px_r16.16.16"),
   make_variant<Shape<4096, 32, 1, 4, 16, 16, 16>>("n4096_e32_b1_p4_r16.16.16"),
   make_variant<Shape<4096, 32, 2, 4, 16, 16, 16>>("n4096_e32_b2_p4_r16.16.16"))

@@ -194,7 +194,8 @@ def test_variant_inventory():
         assert all(v["values_per_lane"] % r == 0 for r in v["radices"])
         assert v["threads"] == v["lanes_per_transform"] * v["transforms_per_workgroup"] <= 1024
         chunk = v["n"] // v["exchange_rounds"]
-        pad = (chunk >> v["pad_log2"]) if v["pad_log2"] else 0
+        pad = (chunk >> v["pad_log2"]) if v["pad_log2"] > 0 else 0
+        assert v["lds_layout"] == ("pad" if v["pad_log2"] > 0 else "xor" if v["pad_log2"] < 0 else "none")
         assert v["lds_bytes"] == v["transforms_per_workgroup"] * (chunk + pad) * 8
         assert v["lds_bytes"] <= 160 * 1024  # gfx950 LDS per workgroup
         c = v["exchange_rounds"]
