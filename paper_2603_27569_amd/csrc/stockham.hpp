@@ -156,15 +156,17 @@ struct RadixList {
 // from chunk floor(m C / E), both known at compile time, provided C divides
 // BPT_p = E / R_p and Ns_{p+1} <= N / C (checked below).
 //
-// PF = true loads each pass's twiddles one pass ahead (latency hidden behind a
-// pass, registers spent); PF = false loads them at the start of their pass
-// (for shapes that need the registers for occupancy).  WPE is the minimum
+// PF = 1 loads each pass's twiddles one pass ahead (latency hidden behind a
+// pass, registers spent); PF = 2 loads every pass's twiddles together with the
+// input (for one workgroup per CU, where registers are plentiful and a pass
+// is too short to hide an L2 round trip); PF = 0 loads them at the start of
+// their pass (for shapes that need the registers for occupancy).  WPE is the minimum
 // number of waves per SIMD the compiler must allow for (1 = no constraint).
-template <int C_, bool PF_, int WPE_, int N_, int E_, int TPB_, int PADLOG_, int... Rs>
+template <int C_, int PF_, int WPE_, int N_, int E_, int TPB_, int PADLOG_, int... Rs>
 struct ShapeX {
   using L = RadixList<Rs...>;
   static constexpr int C = C_;
-  static constexpr bool PF = PF_;
+  static constexpr int PF = PF_;
   static constexpr int WPE = WPE_;
   static constexpr int N = N_;
   static constexpr int E = E_;
@@ -190,9 +192,18 @@ struct ShapeX {
   static constexpr int TW_ELEMS = tw_off(P);
   // Twiddles one lane applies in pass p: E/R_p butterflies x (R_p - 1) legs.
   static constexpr int tw_per_lane(int p) { return p == 0 ? 0 : (E / L::r[p]) * (L::r[p] - 1); }
+  // Where pass p's twiddles sit in a lane's twiddle registers: one set reused
+  // per pass, or (PF = 2) every pass's in turn.
+  static constexpr int tw_lane_off(int p) {
+    int o = 0;
+    if (PF == 2)
+      for (int i = 1; i < p; ++i) o += tw_per_lane(i);
+    return o;
+  }
   static constexpr int TW_REGS = [] {
     int m = 1;
     for (int i = 1; i < P; ++i) m = tw_per_lane(i) > m ? tw_per_lane(i) : m;
+    if (PF == 2 && tw_lane_off(P) > 1) m = tw_lane_off(P);
     return m;
   }();
   static constexpr bool valid() {
@@ -205,6 +216,7 @@ struct ShapeX {
     return true;
   }
   static_assert(valid(), "inconsistent Stockham shape");
+  static_assert(PF >= 0 && PF <= 2, "unknown twiddle schedule");
   static_assert(PADLOG >= -1 && (PADLOG >= 0 || (CHUNK % 16 == 0 && radix(0) % 2 == 0)),
                 "unknown LDS layout");
   // Physical LDS slot of exchange position i.  The XOR swizzle permutes the
@@ -239,7 +251,7 @@ __device__ __forceinline__ void load_twiddles(c32 (&w)[S::TW_REGS], const c32* t
     for (int b = 0; b < BPT; ++b) {
       const int k = (t + b * S::T) & (NS - 1);
 #pragma unroll
-      for (int r = 1; r < R; ++r) w[b * (R - 1) + (r - 1)] = twp[(r - 1) * NS + k];
+      for (int r = 1; r < R; ++r) w[S::tw_lane_off(p) + b * (R - 1) + (r - 1)] = twp[(r - 1) * NS + k];
     }
     // Keep prefetched loads here: the scheduler would otherwise sink them to
     // their use, past the exchange barriers, and expose their latency.
@@ -280,9 +292,10 @@ __device__ __forceinline__ void pass_compute(c32 (&a)[S::E], c32 (&w)[S::TW_REGS
 #pragma unroll
     for (int b = 0; b < BPT; ++b)
 #pragma unroll
-      for (int r = 1; r < R; ++r) a[b + r * BPT] = ctw<INV>(a[b + r * BPT], w[b * (R - 1) + (r - 1)]);
+      for (int r = 1; r < R; ++r)
+        a[b + r * BPT] = ctw<INV>(a[b + r * BPT], w[S::tw_lane_off(p) + b * (R - 1) + (r - 1)]);
   }
-  if constexpr (S::PF) load_twiddles<S, p + 1>(w, tw, t);
+  if constexpr (S::PF == 1) load_twiddles<S, p + 1>(w, tw, t);
 #pragma unroll
   for (int b = 0; b < BPT; ++b) {
     c32 v[R];
@@ -359,10 +372,19 @@ __device__ __forceinline__ void run_passes_from(c32 (&a)[S::E], c32 (&w)[S::TW_R
 
 // All passes of one transform.  Called right after the lane's input loads
 // were issued, so the first twiddle loads queue behind them.
+template <class S, int p>
+__device__ __forceinline__ void load_all_twiddles(c32 (&w)[S::TW_REGS], const c32* tw, int t) {
+  if constexpr (p < S::P) {
+    load_twiddles<S, p>(w, tw, t);
+    load_all_twiddles<S, p + 1>(w, tw, t);
+  }
+}
+
 template <class S, bool INV>
 __device__ __forceinline__ void run_passes(c32 (&a)[S::E], c32* lds, const c32* tw,
                                            int t) {
   c32 w[S::TW_REGS];
+  if constexpr (S::PF == 2) load_all_twiddles<S, 1>(w, tw, t);
   run_passes_from<S, 0, INV>(a, w, lds, tw, t);
 }
 
