@@ -83,6 +83,30 @@ def test_large_n_auto_plan_closed_forms(n):
     assert e.value.name == "FFT_UNSUPPORTED"
 
 
+@pytest.mark.parametrize("n", list(workloads.SIZES) + [1 << 15])
+def test_single_row_auto_plan(n):
+    # batch 1: the tuned choice for the smallest bucket (a four-step split at
+    # 8192 and 16384, fewer workgroups than CUs everywhere)
+    x = workloads.plain_normal(n, 1, seed=n + 3)
+    _check(_host(sf.fft(_gpu(x))), x)
+    _check(_host(sf.fft(_gpu(x), inverse=True)), x, inverse=True)
+
+
+@pytest.mark.parametrize("n,batch", [(16384, 8192), (256, 1 << 20)])
+def test_large_batch_sampled_rows(n, batch):
+    # A 1-2 GiB batch generated on the device; rows sampled across it (first,
+    # last, and strided) are checked against the oracle one by one.
+    g = torch.Generator(device=DEV)
+    g.manual_seed(n + batch)
+    x = torch.randn(batch, n, dtype=torch.complex64, device=DEV, generator=g)
+    y = sf.fft(x)
+    rows = sorted({0, 1, batch // 3, batch // 2 + 7, batch - 2, batch - 1})
+    xs = _host(x[rows])
+    _check(_host(y[rows]), xs)
+    del x, y
+    torch.cuda.empty_cache()
+
+
 def test_plain_uniform_n256_delta_tone():
     n, b = 256, 64
     x = workloads.plain_uniform(n, b)
