@@ -136,7 +136,9 @@ int fft_exec_spectral_energy(fft_plan_t plan, const void *x, const float *w,
  * fft_exec_matched_filter -- fused range compression (the paper's future
  * work on SAR pipeline fusion, Section VIII): out_b = F^{-1}(conj(h) .* F x_b)
  * with F^{-1} = backward / N, in one kernel.
- *   plan   a forward, single-pass plan.
+ *   plan   a forward, single-pass plan; the kernel's shape is the plan's
+ *          variant when one was named, else fft_tune_query_filter's choice
+ *          (its twiddles are built with the plan).
  *   x      device, batch * n complex64;  h  device, n complex64 filter spectrum;
  *   out    device, batch * n complex64 (may equal x).
  * Errors: as fft_exec_spectral_energy.
@@ -232,6 +234,16 @@ int fft_tune_clear(void);
  * FFT_INVALID_ARGUMENT (buffer too small).
  */
 int fft_tune_query(int64_t n, int64_t batch, char *buf, int64_t cap);
+
+/*
+ * fft_tune_query_filter -- the single-pass variant whose fused kernel
+ * fft_exec_matched_filter would use for a forward plan of (n, batch) made
+ * without an explicit variant (the matched filter is tuned on its own: it
+ * runs two transforms per load and may prefer another shape).  The tune
+ * file's "filter_entries" take precedence over the built-in table.  Host
+ * only.  Errors: as fft_tune_query (n must be at most 16384).
+ */
+int fft_tune_query_filter(int64_t n, int64_t batch, char *buf, int64_t cap);
 
 /*
  * fft_set_launch_limit -- largest grid (in workgroups) one kernel launch may

@@ -198,6 +198,10 @@ struct TuneEntry {
 };
 
 std::mutex g_tune_mu;
+// Matched-filter kernel choice per (n, batch range): the fused forward ->
+// multiply -> inverse kernel can prefer another shape than the plain
+// transform.  Tune-file entries ("filter_entries") take precedence.
+std::vector<TuneEntry> g_tune_filter;
 std::vector<TuneEntry> g_tune;
 bool g_env_tune_done = false;
 
@@ -209,27 +213,46 @@ struct BuiltinEntry {
   const char* name;
 };
 const BuiltinEntry kBuiltin[] = {
-    {256, 1, 64, "n256_e16_b4_p4_r16.16"},
-    {256, 65, 512, "n256_e16_b16_p4_r16.16"},
-    {256, 513, 4096, "n256_e16_b4_p4_r16.16"},
+    {256, 1, 4096, "n256_e16_b4_p4_r16.16"},
     {256, 4097, INT64_MAX, "n256_e8_b8_p4_r8.8.4"},
-    {512, 1, 64, "n512_e16_b2_p4_r16.16.2"},
-    {512, 65, 512, "n512_e8_b4_p4_r8.8.8"},
+    {512, 1, 512, "n512_e8_b4_p4_r8.8.8"},
     {512, 513, 4096, "n512_e16_b2_p4_r16.16.2"},
     {512, 4097, INT64_MAX, "n512_e8_b4_p4_r8.8.8"},
-    {1024, 1, 512, "n1024_e8_b2_p4_r8.8.8.2"},
-    {1024, 513, INT64_MAX, "n1024_e16_b1_p4_r16.16.4"},
+    {1024, 1, 64, "n1024_e8_b2_p4_r8.8.8.2"},
+    {1024, 65, INT64_MAX, "n1024_e16_b1_p4_r16.16.4"},
     {2048, 1, 512, "n2048_e8_b1_p4_r8.8.8.4"},
     {2048, 513, INT64_MAX, "n2048_e16_b1_p4_r16.16.8"},
-    {4096, 1, 512, "n4096_e16_b1_p5_r16.16.16"},
-    {4096, 513, 4096, "n4096_e16_b1_px_r16.16.16"},
+    {4096, 1, 64, "n4096_e16_b1_p5_r16.16.16"},
+    {4096, 65, 4096, "n4096_e16_b1_px_r16.16.16"},
     {4096, 4097, INT64_MAX, "n4096_e32_b1_p4_r16.16.16"},
-    {8192, 1, 64, "n8192_e16_b1_p4_r16.16.16.2"},
+    {8192, 1, 64, "fs8192_2x4096"},
     {8192, 65, 512, "n8192_e32_b1_p4_r16.16.16.2"},
     {8192, 513, INT64_MAX, "n8192_e32_c2_b1_p4_r16.16.16.2"},
     {16384, 1, 64, "fs16384_8x2048"},
     {16384, 65, 512, "n16384_e16_b1_p4_r16.16.16.4"},
     {16384, 513, INT64_MAX, "n16384_e32_c2_b1_p4_r16.16.16.4"},
+};
+
+// Built-in matched-filter choices: the autotuner's result on MI355X (the
+// "filter_entries" of the package's tune_gfx950.json).
+const BuiltinEntry kBuiltinFilter[] = {
+    {256, 1, 64, "n256_e8_b8_p4_r8.8.4"},
+    {256, 65, 512, "n256_e16_b4_p4_r16.16"},
+    {256, 513, 4096, "n256_e8_b8_p4_r8.8.4"},
+    {256, 4097, INT64_MAX, "n256_e16_b4_p4_r16.16"},
+    {512, 1, 4096, "n512_e8_b4_p4_r8.8.8"},
+    {512, 4097, INT64_MAX, "n512_e16_b2_p4_r16.16.2"},
+    {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4"},
+    {1024, 65, 512, "n1024_e8_b2_p4_r8.8.8.2"},
+    {1024, 513, INT64_MAX, "n1024_e16_b1_p4_r16.16.4"},
+    {2048, 1, 512, "n2048_e8_b1_p4_r8.8.8.4"},
+    {2048, 513, INT64_MAX, "n2048_e16_b1_p4_r16.16.8"},
+    {4096, 1, 512, "n4096_e8_b1_p4_r8.8.8.8"},
+    {4096, 513, 4096, "n4096_e16_b1_px_r16.16.16"},
+    {4096, 4097, INT64_MAX, "n4096_e32_b1_p4_r16.16.16"},
+    {8192, 1, 512, "n8192_e8_b1_p4_r8.8.8.8.2"},
+    {8192, 513, INT64_MAX, "n8192_e32_b1_p4_r16.16.16.2"},
+    {16384, 1, INT64_MAX, "n16384_e32_b1_p4_r16.16.16.4"},
 };
 
 // Single-pass fallback when a four-step choice is not wanted.
@@ -272,6 +295,21 @@ void tuned_choice(int64_t n, int64_t batch, bool single_only, const SingleVarian
   if (!*sv && !*fs && !single_only && n > kMaxSinglePassN)
     for (int i = 0; i < num_four_step() && !*fs; ++i)
       if (four_step_at(i).n == n) *fs = &four_step_at(i);
+}
+
+// The matched-filter variant for (n, batch): the last matching filter entry
+// (tune file, then built-in), else the plain transform's single-pass choice.
+const SingleVariant* tuned_filter_variant(int64_t n, int64_t batch) {
+  const SingleVariant* sv = nullptr;
+  const FourStepVariant* fs = nullptr;
+  tuned_choice(n, batch, true, &sv, &fs);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const SingleVariant* chosen = nullptr;
+  for (const BuiltinEntry& b : kBuiltinFilter)
+    if (b.n == n && batch >= b.bmin && batch <= b.bmax) chosen = find_single(b.name);
+  for (const TuneEntry& e : g_tune_filter)
+    if (e.n == n && batch >= e.bmin && batch <= e.bmax && e.v) chosen = e.v;
+  return chosen && chosen->filter ? chosen : sv;
 }
 
 const SingleVariant* tuned_variant(int64_t n, int64_t batch) {
@@ -343,6 +381,19 @@ int load_tune_file_locked(const char* path) {
       add.push_back({n, num(e, "batch_min", 1), num(e, "batch_max", INT64_MAX), v, fs});
     }
   }
+  std::vector<TuneEntry> add_filter;
+  if (const json::Value* es = doc.get("filter_entries"); es && es->kind == json::Value::Array) {
+    for (const json::Value& e : es->arr) {
+      const std::string* name = str(e, "variant");
+      const int64_t n = num(e, "n", 0);
+      const SingleVariant* v = name && valid_single_size(n) ? find_single(name->c_str()) : nullptr;
+      if (!v || v->n != n) {
+        ++skipped;
+        continue;
+      }
+      add_filter.push_back({n, num(e, "batch_min", 1), num(e, "batch_max", INT64_MAX), v, nullptr});
+    }
+  }
   if (const json::Value* rs = doc.get("ragged"); rs && rs->kind == json::Value::Array) {
     for (const json::Value& e : rs->arr) {
       const std::string* shape = str(e, "shape");
@@ -353,6 +404,7 @@ int load_tune_file_locked(const char* path) {
     std::fprintf(stderr, "stockfft: %d tune entries in %s are not usable here; skipped\n",
                  skipped, path);
   g_tune.insert(g_tune.end(), add.begin(), add.end());
+  g_tune_filter.insert(g_tune_filter.end(), add_filter.begin(), add_filter.end());
   return FFT_SUCCESS;
 }
 
@@ -398,6 +450,8 @@ struct stockfft_plan_s {
   void* d_tw4 = nullptr;
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
+  const SingleVariant* sv_filter = nullptr;  // matched-filter kernel shape (forward plans)
+  void* d_tw_filter = nullptr;               // its twiddles when it differs from sv
 };
 
 static void free_plan(stockfft_plan_s* p) {
@@ -405,6 +459,7 @@ static void free_plan(stockfft_plan_s* p) {
   if (p->d_tw) (void)hipFree(p->d_tw);
   if (p->d_tw4) (void)hipFree(p->d_tw4);
   if (p->d_ws) (void)hipFree(p->d_ws);
+  if (p->d_tw_filter) (void)hipFree(p->d_tw_filter);
   delete p;
 }
 
@@ -475,6 +530,15 @@ extern "C" int fft_plan_config(fft_plan_t* plan, int64_t n, int64_t batch, int d
   std::vector<float> host;
   build_stockham_twiddles(*sv, host);
   rc = upload(host, &p->d_tw);
+  if (!rc && !fs && direction == FFT_FORWARD) {
+    // The matched filter's kernel: the named variant, else its own tuned choice.
+    p->sv_filter = variant ? sv : tuned_filter_variant(n, batch);
+    if (p->sv_filter != sv) {
+      std::vector<float> ftw;
+      build_stockham_twiddles(*p->sv_filter, ftw);
+      rc = upload(ftw, &p->d_tw_filter);
+    }
+  }
   if (!rc && fs) {
     build_four_step_twiddles(*fs, host);
     rc = upload(host, &p->d_tw4);
@@ -550,15 +614,17 @@ extern "C" int fft_exec_spectral_energy(fft_plan_t plan, const void* x, const fl
 extern "C" int fft_exec_matched_filter(fft_plan_t plan, const void* x, const void* h, void* out,
                                        void* stream) {
   if (!plan || !live_handle(plan)) return FFT_INVALID_PLAN;
-  if (plan->direction != FFT_FORWARD || plan->algorithm != FFT_ALGO_SINGLE_PASS ||
-      !plan->sv->filter)
+  const SingleVariant* fv = plan->sv_filter;
+  if (plan->direction != FFT_FORWARD || plan->algorithm != FFT_ALGO_SINGLE_PASS || !fv ||
+      !fv->filter)
     return FFT_UNSUPPORTED;
   if (!x || !h || !out) return FFT_INVALID_POINTER;
   if (!aligned8(x) || !aligned8(h) || !aligned8(out)) return FFT_MISALIGNED;
   const size_t bytes = (size_t)plan->n * (size_t)plan->batch * 8;
   if (ranges_partially_overlap(x, out, bytes)) return FFT_OVERLAP;
   DeviceGuard g(plan->device);
-  hipError_t e = plan->sv->filter(x, h, out, plan->d_tw, plan->batch, (hipStream_t)stream);
+  const void* tw = fv == plan->sv ? plan->d_tw : plan->d_tw_filter;
+  hipError_t e = fv->filter(x, h, out, tw, plan->batch, (hipStream_t)stream);
   return e == hipSuccess ? FFT_SUCCESS : hip_fail(e);
 }
 
@@ -603,6 +669,15 @@ extern "C" int fft_tune_query(int64_t n, int64_t batch, char* buf, int64_t cap) 
   return put_text(v->name, buf, cap);
 }
 
+extern "C" int fft_tune_query_filter(int64_t n, int64_t batch, char* buf, int64_t cap) {
+  if (!buf) return FFT_INVALID_POINTER;
+  if (!valid_single_size(n)) return FFT_INVALID_SIZE;
+  if (batch < 1) return FFT_INVALID_BATCH;
+  const SingleVariant* v = tuned_filter_variant(n, batch);
+  if (!v) return FFT_INVALID_SIZE;
+  return put_text(v->name, buf, cap);
+}
+
 extern "C" int fft_set_launch_limit(int64_t max_groups) {
   set_max_groups_per_launch(max_groups > 0 ? max_groups : kDefaultMaxGroupsPerLaunch);
   return FFT_SUCCESS;
@@ -612,6 +687,7 @@ extern "C" int fft_tune_clear(void) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_env_tune_done = true;
   g_tune.clear();
+  g_tune_filter.clear();
   return FFT_SUCCESS;
 }
 
@@ -706,7 +782,10 @@ extern "C" int fft_plan_describe(fft_plan_t plan, char* buf, int64_t cap) {
                   (plan->algorithm == FFT_ALGO_FOUR_STEP ? "four_step" : "single_pass") + "\"" +
                   ",\"workspace_bytes\":" + std::to_string(plan->ws_bytes) +
                   ",\"variant\":" + describe_single(*plan->sv) +
-                  (plan->fs ? ",\"four_step\":" + describe_four_step(*plan->fs) : "") + "}";
+                  (plan->fs ? ",\"four_step\":" + describe_four_step(*plan->fs) : "") +
+                  (plan->sv_filter ? ",\"filter_variant\":\"" + std::string(plan->sv_filter->name) + "\""
+                                   : "") +
+                  "}";
   return put_text(s, buf, cap);
 }
 

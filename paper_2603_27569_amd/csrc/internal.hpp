@@ -17,6 +17,7 @@ int hip_fail(hipError_t e);
 
 const SingleVariant* find_single(const char* name);
 const SingleVariant* tuned_variant(int64_t n, int64_t batch);
+const SingleVariant* tuned_filter_variant(int64_t n, int64_t batch);
 void tuned_choice(int64_t n, int64_t batch, bool single_only, const SingleVariant** sv,
                   const FourStepVariant** fs);
 bool valid_size(int64_t n);         // any plan length

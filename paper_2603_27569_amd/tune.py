@@ -3,9 +3,10 @@
 For every transform length and batch bucket it times each compiled kernel
 variant -- values per lane (hence the radix and lanes per transform),
 transforms per workgroup, LDS padding, and for N >= 8192 the four-step
-splits -- through the C ABI, and keeps the fastest.  For the ragged
-persistent kernel it picks one compiled shape per length by coordinate
-descent on a mixed ragged batch.  The result is a JSON file that
+splits -- through the C ABI, and keeps the fastest.  The fused matched
+filter is tuned the same way on its own.  For the ragged persistent kernel
+it picks one compiled shape per length by coordinate descent on a mixed
+ragged batch.  The result is a JSON file that
 ``fft_tune_load`` (or the STOCKFFT_TUNE_CACHE environment variable) applies:
 
   {"arch": "gfx950", "cus": 256, "hip_runtime": ..., "entries": [
@@ -31,7 +32,8 @@ import statistics
 import sys
 
 from . import (FFT_ALGO_FOUR_STEP, FFT_ALGO_SINGLE_PASS, FFT_FORWARD, Plan, RaggedPlan,
-               fft_ragged_shapes, fft_tune_clear_ragged, fft_tune_set_ragged, variants)
+               fft_exec_matched_filter, fft_ragged_shapes, fft_tune_clear_ragged,
+               fft_tune_set_ragged, variants)
 
 SIZES = (256, 512, 1024, 2048, 4096, 8192, 16384)
 # Batch buckets: (batch_min, batch_max, representative batch timed).
@@ -102,6 +104,38 @@ def tune_plain(torch, dev, stream, sizes=SIZES, buckets=BUCKETS, iters=30, log=p
     return entries
 
 
+def tune_filter(torch, dev, stream, sizes=SIZES, buckets=BUCKETS, iters=30, log=print):
+    """The fused matched filter (forward, multiply by conj(h), inverse in one
+    kernel) per length and batch bucket, over the single-pass variants."""
+    entries = []
+    for n in sizes:
+        h = torch.randn(n, dtype=torch.complex64, device=dev)
+        for bmin, bmax, b in buckets:
+            while n * b * 8 > MAX_BYTES and b > 1:
+                b //= 2
+            xs, ys = _ring(torch, dev, n, b)
+            k = len(xs)
+            times = {}
+            cs = stream.cuda_stream
+            for name, algo in candidates(n):
+                if algo != FFT_ALGO_SINGLE_PASS:
+                    continue
+                p = Plan(n, b, FFT_FORWARD, algo, name)
+                times[name] = _time(torch, stream,
+                                    lambda i: fft_exec_matched_filter(p.handle, xs[i % k].data_ptr(),
+                                                                      h.data_ptr(), ys[i % k].data_ptr(),
+                                                                      cs),
+                                    iters)
+                p.close()
+            best = min(times, key=times.get)
+            log(f"tune filter n={n} batch={b} -> {best} {times[best]:.2f} us")
+            entries.append({"n": n, "batch_min": bmin, "batch_max": bmax, "variant": best,
+                            "timed_batch": b, "us": round(times[best], 3),
+                            "candidates": {k2: round(v, 3) for k2, v in times.items()}})
+            del xs, ys
+    return entries
+
+
 def tune_ragged(torch, dev, stream, sizes=None, iters=20, sweeps=2, log=print):
     """Choose the ragged kernel's shape per length on a mixed ragged batch.
 
@@ -162,10 +196,12 @@ def run(out_path, quick=False, log=print):
     props = torch.cuda.get_device_properties(dev)
     buckets = BUCKETS if not quick else ((1, 2 ** 62, 1024),)
     entries = tune_plain(torch, dev, stream, buckets=buckets, iters=10 if quick else 30, log=log)
+    filters = tune_filter(torch, dev, stream, buckets=buckets, iters=10 if quick else 30, log=log)
     ragged = tune_ragged(torch, dev, stream, iters=5 if quick else 20, sweeps=1 if quick else 2,
                          log=log)
     doc = {"arch": props.gcnArchName.split(":")[0], "cus": props.multi_processor_count,
-           "hip_runtime": getattr(torch.version, "hip", None), "entries": entries, "ragged": ragged}
+           "hip_runtime": getattr(torch.version, "hip", None), "entries": entries,
+           "filter_entries": filters, "ragged": ragged}
     with open(out_path, "w") as f:
         json.dump(doc, f, indent=1)
     return doc

@@ -138,6 +138,9 @@ def test_builtin_table_is_the_shipped_tuner_output():
             assert sf.fft_tune_query(e["n"], b) == e["variant"], (e["n"], b)
     for r in doc["ragged"]:
         assert sf.fft_tune_query_ragged(r["n"]) == r["shape"]
+    for e in doc.get("filter_entries", []):
+        for b in (e["batch_min"], e["timed_batch"], min(e["batch_max"], 10 ** 9)):
+            assert sf.fft_tune_query_filter(e["n"], b) == e["variant"], (e["n"], b)
 
 
 def test_ragged_shape_tuning_api():
@@ -295,18 +298,25 @@ def test_twiddle_tables_rounded_once_from_fp64():
 def test_tune_table_set_query_load(tmp_path):
     sf.fft_tune_clear()
     try:
-        assert sf.fft_tune_query(4096, 256) == "n4096_e16_b1_p5_r16.16.16"
+        base = sf.fft_tune_query(4096, 256)
+        assert base.startswith("n4096_")
         sf.fft_tune_set(4096, 1, 100, "n4096_e8_b1_p4_r8.8.8.8")
         assert sf.fft_tune_query(4096, 50) == "n4096_e8_b1_p4_r8.8.8.8"
-        assert sf.fft_tune_query(4096, 256) == "n4096_e16_b1_p5_r16.16.16"
+        assert sf.fft_tune_query(4096, 256) == base
         with pytest.raises(sf.StockfftError):
             sf.fft_tune_set(4096, 1, 10, "n256_e16_b16_p4_r16.16")
         p = tmp_path / "tune.json"
         p.write_text(json.dumps({"arch": "gfx950", "entries": [
             {"n": 2048, "batch_min": 1, "batch_max": 10 ** 9, "variant": "n2048_e8_b1_p4_r8.8.8.4"},
-            {"n": 2048, "batch_min": 1, "batch_max": 10, "variant": "bogus"}]}))
+            {"n": 2048, "batch_min": 1, "batch_max": 10, "variant": "bogus"}],
+            "filter_entries": [
+            {"n": 1024, "batch_min": 1, "batch_max": 10 ** 9, "variant": "n1024_e4_b1_p4_r4.4.4.4.4"},
+            {"n": 1024, "batch_min": 1, "batch_max": 10, "variant": "n2048_e8_b1_p4_r8.8.8.4"}]}))
         sf.fft_tune_load(str(p))
         assert sf.fft_tune_query(2048, 5) == "n2048_e8_b1_p4_r8.8.8.4"
+        assert sf.fft_tune_query_filter(1024, 5) == "n1024_e4_b1_p4_r4.4.4.4.4"
+        with pytest.raises(sf.StockfftError):
+            sf.fft_tune_query_filter(32768, 5)  # no single-pass kernel at that length
         with pytest.raises(sf.StockfftError):
             sf.fft_tune_load(str(tmp_path / "missing.json"))
         bad = tmp_path / "bad.json"

@@ -324,6 +324,31 @@ def test_autograd_functions():
     assert rel2 <= 1e-4, rel2
 
 
+@pytest.mark.parametrize("n", [1024, 4096, 16384])
+def test_matched_filter_every_variant_and_tuned_choice(n):
+    # The filter kernel is tuned separately from the plain transform: the
+    # plan's own choice (with its own twiddle table) and every variant named
+    # explicitly must all match the oracle.
+    b = 9
+    x = workloads.plain_normal(n, b, seed=n + 1)
+    h = workloads.complex_normal((n,), seed=n + 2)
+    ref = oracle.matched_filter(x, h)
+    xt, ht = _gpu(x), _gpu(h)
+    names = [None] + [v["name"] for v in SINGLE if v["n"] == n]
+    for name in names:
+        p = sf.Plan(n, b, sf.FFT_FORWARD, sf.FFT_ALGO_SINGLE_PASS, name)
+        d = p.describe()
+        want = name if name else sf.fft_tune_query_filter(n, b)
+        assert d["filter_variant"] == want
+        y = torch.empty_like(xt)
+        sf.fft_exec_matched_filter(p.handle, xt.data_ptr(), ht.data_ptr(), y.data_ptr(),
+                                   torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        _, worst, _, _ = metrics.gate(_host(y), ref, x)
+        assert worst <= 5e-6, (name, worst)
+        p.close()
+
+
 def test_matched_filter_matches_oracle():
     n, b = 4096, 33
     x = workloads.plain_normal(n, b, seed=12)
