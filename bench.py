@@ -479,6 +479,8 @@ def compare_ragged(args, torch, np, sf, metrics, workloads, T, dev, cs, iters, w
         gx.append(ins)
         gy.append(outs)
     t_r = T.run(lambda i: plan.exec(xs[i % K].data_ptr(), ys[i % K].data_ptr(), cs), iters, warm) / iters
+    t_rd = T.run(lambda i: plan.exec_direct(xs[i % K].data_ptr(), ys[i % K].data_ptr(), cs),
+                 iters, warm) / iters
 
     def plain(i):
         j = i % K
@@ -518,7 +520,10 @@ def compare_ragged(args, torch, np, sf, metrics, workloads, T, dev, cs, iters, w
         worst = max(worst, w_)
     flops = sum(metrics.fft_flops(int(s)) for s in sizes)
     return {"transforms": int(len(sizes)), "elements": total,
-            "persistent_graph_us": round(t_r * 1e6, 3), "per_size_plain_us": round(t_p * 1e6, 3),
+            "persistent_graph_us": round(t_r * 1e6, 3),
+            "persistent_direct_launch_us": round(t_rd * 1e6, 3),
+            "speedup_direct_launch": round(t_p / t_rd, 3),
+            "per_size_plain_us": round(t_p * 1e6, 3),
             "per_size_plain_graph_us": round(t_pg * 1e6, 3),
             "plain_graph_matches_eager": bool(graph_matches_eager),
             "speedup": round(t_p / t_r, 3), "speedup_vs_plain_graph": round(t_pg / t_r, 3), "persistent_GBs_algorithmic": round(16 * total / t_r / 1e9, 1),
