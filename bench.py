@@ -17,7 +17,8 @@ kernel, the FP64 oracle timed on the host cores (a baseline, not a target),
 and the comparisons the paper's method implies (fused forward+adjoint vs
 the plain chain, fused range compression vs its unfused chain, ragged
 persistent launch vs per-size plain launches, four-step vs single-pass at
-8192/16384, the four-step at 2^16 and 2^20, a same-footprint copy kernel).  The accuracy figures reported
+8192/16384, the four-step at 2^16 and 2^20, 16-bit storage against FP32
+storage, a same-footprint copy kernel).  The accuracy figures reported
 here are against numpy's FP64 FFT (an independent library routine); the
 parity tests against the oracle are the test suite's job.
 
@@ -373,6 +374,11 @@ def compare(args, torch, np, sf, metrics, workloads, T, dev, cs):
         log(f"n{n}", rec)
         del xs, ys
 
+    # 16-bit storage (binary16 / bfloat16 pairs, FP32 arithmetic): half the
+    # bytes of the FP32 path at the same transform.
+    comps["storage_16bit"] = compare_lowp(torch, np, sf, metrics, workloads, T, dev, cs, iters, warm)
+    log("storage_16bit", comps["storage_16bit"])
+
     # Lengths beyond one LDS-resident transform: the four-step only (two
     # passes over HBM, so at most half the algorithmic rate of the peak).
     for n, b in ((1 << 16, 256), (1 << 20, 16)):
@@ -403,6 +409,51 @@ def compare(args, torch, np, sf, metrics, workloads, T, dev, cs):
     except sf.StockfftError as e:
         comps["ragged_2000"] = {"error": str(e)}
     return comps
+
+
+def compare_lowp(torch, np, sf, metrics, workloads, T, dev, cs, iters, warm):
+    out = {}
+    n = 4096
+    for b in (256, 16384):
+        x_h = workloads.complex_normal((b, n), seed=1007 + b)
+        rec = {}
+        K = ring_count(2 * n * b * 8)
+        xs = [torch.from_numpy(x_h).to(dev)] + [torch.randn(b, n, dtype=torch.complex64, device=dev)
+                                                for _ in range(K - 1)]
+        ys = [torch.empty_like(xs[0]) for _ in range(K)]
+        p = sf.Plan(n, b, sf.FFT_FORWARD, sf.FFT_ALGO_SINGLE_PASS)
+        t32 = T.run(lambda i: p.exec(xs[i % K].data_ptr(), ys[i % K].data_ptr(), cs), iters, warm) / iters
+        rec["fp32_us"] = round(t32 * 1e6, 3)
+        del xs, ys
+        for fmt, io, dt in (("f16", sf.FFT_IO_C16, torch.float16), ("bf16", sf.FFT_IO_BC16, torch.bfloat16)):
+            stored, xv = workloads.to_storage(x_h, fmt)
+            t0 = torch.from_numpy(np.ascontiguousarray(stored))
+            if fmt == "bf16":
+                t0 = t0.view(torch.int16).view(torch.bfloat16)
+            K2 = ring_count(2 * n * b * 4)
+            xs = [t0.to(dev)] + [torch.randn(b, n, 2, device=dev).to(dt) for _ in range(K2 - 1)]
+            ys = [torch.empty_like(xs[0]) for _ in range(K2)]
+            t = T.run(lambda i: sf.fft_exec_io(p.handle, xs[i % K2].data_ptr(), ys[i % K2].data_ptr(), io, cs),
+                      iters, warm) / iters
+            sf.fft_exec_io(p.handle, xs[0].data_ptr(), ys[0].data_ptr(), io, cs)
+            torch.cuda.synchronize()
+            rows = min(b, 32)
+            yh = ys[0][:rows].cpu()
+            if fmt == "bf16":
+                yv = workloads.bf16_value(yh.view(torch.int16).numpy().view(np.uint16)).astype(np.float64)
+            else:
+                yv = yh.numpy().astype(np.float64)
+            ok, worst, med, _ = metrics.gate_storage(yv[..., 0] + 1j * yv[..., 1], ref_fft(np, xv[:rows]),
+                                                     xv[:rows], fmt)
+            rec[fmt] = {"us": round(t * 1e6, 3), "speedup_vs_fp32": round(t32 / t, 3),
+                        "GBs_moved_algorithmic": round(8 * n * b / t / 1e9, 1),
+                        "pct_hbm_peak": round(100 * 8 * n * b / t / 1e9 / HBM_PEAK_GBS, 2),
+                        "worst_rel_rms": worst, "median_rel_rms": med,
+                        "unit_roundoff": metrics.STORAGE_UNIT_ROUNDOFF[fmt], "gates_pass": bool(ok)}
+            del xs, ys
+        p.close()
+        out[f"n{n}_b{b}"] = rec
+    return out
 
 
 def compare_matched(torch, np, sf, metrics, workloads, T, dev, cs, iters, warm):

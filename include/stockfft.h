@@ -59,6 +59,11 @@ enum fft_status {
 #define FFT_ALGO_SINGLE_PASS 1 /* one dispatch, all passes on chip (Section IV-D rule 1) */
 #define FFT_ALGO_FOUR_STEP 2   /* two dispatches through device memory (Section IV-B eq. (3)) */
 
+/* Storage formats of fft_exec_io's buffers (arithmetic is FP32 in all). */
+#define FFT_IO_C64 0   /* complex64: two float32 per value (fft_exec's format) */
+#define FFT_IO_C16 1   /* two IEEE binary16 per value, real part first */
+#define FFT_IO_BC16 2  /* two bfloat16 per value, real part first */
+
 /*
  * fft_plan -- create a plan for `batch` transforms of length `n`.
  * Section II-A (definition), Section IV-D (synthesis rules).
@@ -102,6 +107,25 @@ int fft_plan_config(fft_plan_t *plan, int64_t n, int64_t batch, int direction, i
  * FFT_OVERLAP, FFT_HIP_ERROR.
  */
 int fft_exec(fft_plan_t plan, const void *in, void *out, void *stream);
+
+/*
+ * fft_exec_io -- fft_exec with 16-bit storage in HBM: in and out hold
+ * batch * n complex values of `io` (FFT_IO_C16 or FFT_IO_BC16, 4 bytes per
+ * value; FFT_IO_C64 is fft_exec itself).  Values are widened exactly on
+ * load, every pass runs in FP32 with the plan's FP32 twiddles, and each
+ * output is rounded once to the storage format (nearest even).  This halves
+ * the bytes of a bandwidth-bound transform (the paper's future-work item on
+ * half-precision storage, Section VIII); the error is then that of one
+ * rounding of the output, about 2^-11 (binary16) or 2^-8 (bfloat16) relative.
+ * binary16 overflows to infinity above 65504: a bin can reach sqrt(n) times
+ * the input row's 2-norm, so inputs must be scaled for that; bfloat16 has
+ * float32's range.  Single-pass plans only (n <= 16384).  Asynchronous; does
+ * not allocate.  in == out allowed.
+ * Errors: FFT_INVALID_PLAN, FFT_INVALID_ARGUMENT (unknown io),
+ * FFT_UNSUPPORTED (four-step plan), FFT_INVALID_POINTER, FFT_MISALIGNED (not
+ * 4-byte aligned), FFT_OVERLAP, FFT_HIP_ERROR.
+ */
+int fft_exec_io(fft_plan_t plan, const void *in, void *out, int io, void *stream);
 
 /*
  * fft_destroy -- free the plan's device memory.  The caller must ensure no

@@ -20,14 +20,17 @@ import ctypes
 import json
 import threading
 
-from ._lib import (CODES, FFT_ALGO_AUTO, FFT_ALGO_FOUR_STEP, FFT_ALGO_SINGLE_PASS,
-                   FFT_BACKWARD, FFT_FORWARD, STATUS, StockfftError, check, lib)
+from ._lib import (CODES, FFT_ALGO_AUTO, FFT_ALGO_FOUR_STEP, FFT_ALGO_SINGLE_PASS, FFT_BACKWARD,
+                   FFT_FORWARD, FFT_IO_BC16, FFT_IO_C16, FFT_IO_C64, STATUS, StockfftError, check,
+                   lib)
 
 __all__ = [
     "FFT_FORWARD", "FFT_BACKWARD", "FFT_ALGO_AUTO", "FFT_ALGO_SINGLE_PASS",
-    "FFT_ALGO_FOUR_STEP", "StockfftError", "STATUS", "CODES",
+    "FFT_ALGO_FOUR_STEP", "FFT_IO_C64", "FFT_IO_C16", "FFT_IO_BC16", "StockfftError", "STATUS",
+    "CODES",
     "fft_plan", "fft_plan_config", "fft_exec", "fft_destroy",
     "fft_exec_spectral_energy", "fft_exec_matched_filter",
+    "fft_exec_io", "fft_lowp",
     "fft_plan_ragged", "fft_exec_ragged", "fft_exec_ragged_direct", "fft_exec_ragged_plain",
     "fft_destroy_ragged",
     "fft_ragged_shapes", "fft_tune_set_ragged", "fft_tune_query_ragged", "fft_tune_clear_ragged",
@@ -84,6 +87,11 @@ def fft_plan_ragged(sizes, direction):
     h = ctypes.c_void_p()
     check("fft_plan_ragged", lib().fft_plan_ragged(ctypes.byref(h), arr, len(sizes), int(direction)))
     return h.value
+
+
+def fft_exec_io(plan, in_ptr, out_ptr, io, stream=0):
+    return check("fft_exec_io", lib().fft_exec_io(_vp(plan), _vp(in_ptr), _vp(out_ptr), int(io),
+                                                  _vp(stream)))
 
 
 def fft_exec_ragged(plan, in_ptr, out_ptr, stream=0):
@@ -318,6 +326,31 @@ def fft(x, inverse=False, out=None, algorithm=FFT_ALGO_AUTO, variant=None):
     inverse=True gives the backward transform exp(+2 pi i n k / N), also
     unscaled (backward(forward(x)) = N x)."""
     return _transform(x, FFT_BACKWARD if inverse else FFT_FORWARD, out, algorithm, variant)
+
+
+def fft_lowp(x, inverse=False, out=None):
+    """The transform with 16-bit storage: x is a contiguous float16 or
+    bfloat16 tensor of shape [..., N, 2] (real, imaginary); the result has
+    the same dtype and shape.  Arithmetic is FP32; the output is rounded once
+    to x's format.  Single-pass lengths only (N <= 16384)."""
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda or not x.is_contiguous():
+        raise ValueError("x must be a contiguous CUDA tensor")
+    if x.dtype not in (torch.float16, torch.bfloat16) or x.dim() < 2 or x.shape[-1] != 2:
+        raise ValueError("x must be float16 or bfloat16 with a trailing dimension of 2")
+    io = FFT_IO_C16 if x.dtype == torch.float16 else FFT_IO_BC16
+    n = x.shape[-2]
+    batch = x.numel() // (2 * n) if n else 0
+    if out is None:
+        out = torch.empty_like(x)
+    elif out.shape != x.shape or out.dtype != x.dtype or not out.is_contiguous():
+        raise ValueError("out must match x")
+    if batch == 0:
+        return out
+    p = cached_plan(n, batch, FFT_BACKWARD if inverse else FFT_FORWARD, x.device.index,
+                    FFT_ALGO_SINGLE_PASS)
+    fft_exec_io(p.handle, x.data_ptr(), out.data_ptr(), io, _stream(x.device))
+    return out
 
 
 def ifft_unnormalized(x, out=None):

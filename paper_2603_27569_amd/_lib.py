@@ -16,6 +16,9 @@ FFT_BACKWARD = 1
 FFT_ALGO_AUTO = 0
 FFT_ALGO_SINGLE_PASS = 1
 FFT_ALGO_FOUR_STEP = 2
+FFT_IO_C64 = 0
+FFT_IO_C16 = 1
+FFT_IO_BC16 = 2
 
 STATUS = {
     0: "FFT_SUCCESS", 1: "FFT_INVALID_SIZE", 2: "FFT_INVALID_BATCH",
@@ -40,6 +43,7 @@ SIGNATURES = {
     "fft_exec_matched_filter": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "fft_plan_ragged": (_int, [_pvp, ctypes.POINTER(_i64), _i64, _int]),
     "fft_exec_ragged": (_int, [_vp, _vp, _vp, _vp]),
+    "fft_exec_io": (_int, [_vp, _vp, _vp, ctypes.c_int, _vp]),
     "fft_exec_ragged_direct": (_int, [_vp, _vp, _vp, _vp]),
     "fft_exec_ragged_plain": (_int, [_vp, _pvp, _pvp, _vp]),
     "fft_destroy_ragged": (_int, [_vp]),

@@ -3,6 +3,9 @@
 // splits very large batches into several grids.
 #pragma once
 
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+
 #include "stockham.hpp"
 #include "variants.hpp"
 
@@ -31,6 +34,79 @@ __device__ __forceinline__ void global_store_row(const c32 (&a)[S::E], c32* dst,
 // ------------------------------------------------------------ single pass
 // One dispatch per batch (the paper's synthesis rule 1, Section IV-D): each
 // workgroup owns TPB whole transforms; every pass stays on chip.
+// 16-bit storage formats: one complex value in 4 bytes (real in the low
+// half).  Loads widen exactly to FP32; stores round to nearest even.
+struct IoF16 {
+  __device__ __forceinline__ static c32 load(uint32_t v) {
+    const float2 f = __half22float2(*reinterpret_cast<const __half2*>(&v));
+    return c32{f.x, f.y};
+  }
+  __device__ __forceinline__ static uint32_t store(c32 a) {
+    const __half2 h = __floats2half2_rn(a.x, a.y);
+    return *reinterpret_cast<const uint32_t*>(&h);
+  }
+};
+
+struct IoBF16 {
+  __device__ __forceinline__ static c32 load(uint32_t v) {
+    return c32{__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u)};
+  }
+  // gfx950 converts a pair in one instruction, rounding to nearest even.
+  __device__ __forceinline__ static uint32_t store(c32 a) {
+    const __hip_bfloat162 h = __float22bfloat162_rn(float2{a.x, a.y});
+    return *reinterpret_cast<const uint32_t*>(&h);
+  }
+};
+
+// The single-pass transform with 16-bit storage: the rows are widened on
+// load, every pass runs in FP32, and the result is rounded once on store.
+template <class S, bool INV, class IO>
+__global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham_io(const uint32_t* in,
+                                                                    uint32_t* out, const c32* tw,
+                                                                    int64_t rows) {
+  __shared__ alignas(16) c32 lds_all[S::TPB * S::LDS_ELEMS];
+  const int tid = threadIdx.x;
+  const int slot = tid / S::T;
+  const int t = tid - slot * S::T;
+  const int64_t row = (int64_t)blockIdx.x * S::TPB + slot;
+  const bool live = row < rows;
+  c32* lds = lds_all + slot * S::LDS_ELEMS;
+  c32 a[S::E];
+  if (live) {
+    const uint32_t* src = in + row * S::N;
+#pragma unroll
+    for (int m = 0; m < S::E; ++m) a[m] = IO::load(src[t + m * S::T]);
+  } else {
+#pragma unroll
+    for (int m = 0; m < S::E; ++m) a[m] = c32{0.f, 0.f};
+  }
+  run_passes<S, INV>(a, lds, tw, t);
+  if (live) {
+    uint32_t* dst = out + row * S::N;
+#pragma unroll
+    for (int m = 0; m < S::E; ++m) dst[t + m * S::T] = IO::store(a[m]);
+  }
+}
+
+template <class S, class IO>
+hipError_t launch_single_io(const void* in, void* out, const void* tw, int64_t batch,
+                            bool inverse, hipStream_t s) {
+  const int64_t groups = (batch + S::TPB - 1) / S::TPB;
+  const int64_t cap = max_groups_per_launch();
+  for (int64_t g0 = 0; g0 < groups; g0 += cap) {
+    const int64_t g = groups - g0 < cap ? groups - g0 : cap;
+    const int64_t r0 = g0 * S::TPB;
+    const uint32_t* ip = static_cast<const uint32_t*>(in) + r0 * S::N;
+    uint32_t* op = static_cast<uint32_t*>(out) + r0 * S::N;
+    const c32* twp = static_cast<const c32*>(tw);
+    if (inverse)
+      k_stockham_io<S, true, IO><<<dim3((unsigned)g), dim3(S::THREADS), 0, s>>>(ip, op, twp, batch - r0);
+    else
+      k_stockham_io<S, false, IO><<<dim3((unsigned)g), dim3(S::THREADS), 0, s>>>(ip, op, twp, batch - r0);
+  }
+  return hipGetLastError();
+}
+
 template <class S, bool INV>
 __global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham(const c32* in, c32* out,
                                                          const c32* tw, int64_t rows) {

@@ -23,6 +23,8 @@ SingleVariant make_variant(const char* name) {
   v.launch = &launch_single<S>;
   v.fused = &launch_spectral_energy<S>;
   v.filter = &launch_matched_filter<S>;
+  v.launch_f16 = &launch_single_io<S, IoF16>;
+  v.launch_bf16 = &launch_single_io<S, IoBF16>;
   return v;
 }
 

@@ -45,6 +45,10 @@ struct SingleVariant {
   LaunchFn launch;
   FusedFn fused;     // null when not compiled for this variant
   FilterFn filter;   // null when not compiled for this variant
+  // The same transform with 16-bit storage (FP32 arithmetic): complex values
+  // in HBM as IEEE half pairs (launch_f16) or bfloat16 pairs (launch_bf16).
+  LaunchFn launch_f16;
+  LaunchFn launch_bf16;
 };
 
 extern const SingleVariant kSingleVariants[];

@@ -69,3 +69,26 @@ def gate(y, ref, x, rel_gate=REL_RMS_GATE, abs_gate=None):
     ok = bool(np.all(rel <= rel_gate) and np.all(ratio <= abs_gate))
     return ok, float(rel.max(initial=0.0)), float(np.median(rel) if rel.size else 0.0), \
         float(ratio.max(initial=0.0))
+
+
+# 16-bit storage: unit roundoff of one rounding to the format.
+STORAGE_UNIT_ROUNDOFF = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+
+
+def gate_storage(y, ref, x, fmt):
+    """Gate for results stored in a 16-bit format (`ref` is the exact DFT of
+    the values actually stored as input).  One rounding of the output to a
+    format with unit roundoff u leaves a relative error of at most u per bin
+    and about u / sqrt(3) in RMS, so: rel-RMS <= u, and per bin
+    |y - X| <= u |X|max + 1e-5 ||x_b||_2 (the FP32 arithmetic's own share, as
+    in the FP32 gate).  Returns (ok, worst_rel_rms, median_rel_rms,
+    worst_abs_ratio) with the abs ratio taken against that bound."""
+    u = STORAGE_UNIT_ROUNDOFF[fmt]
+    rel, mabs, xn = per_row_errors(y, ref, x)
+    r = np.asarray(ref).reshape(rel.shape[0], -1)
+    bound = u * np.max(np.abs(r), axis=1) + 1e-5 * xn
+    with np.errstate(divide="ignore", invalid="ignore"):
+        ratio = np.where(bound > 0, mabs / bound, np.where(mabs == 0, 0.0, np.inf))
+    ok = bool(np.all(rel <= u) and np.all(ratio <= 1.0))
+    return ok, float(rel.max(initial=0.0)), float(np.median(rel) if rel.size else 0.0), \
+        float(ratio.max(initial=0.0))

@@ -18,6 +18,9 @@ for it:
                   the chirp support                                   (seed 1003)
   spectral_energy N=4096, batch 512, x ~ N(0, 1); W ~ U[0, 1) float32  (1004/1104)
   ragged          2000 transforms, sizes 2^U{8..14}, N(0, 1) values   (seed 1005)
+  to_storage      any of these rounded to a 16-bit storage format (IEEE
+                  binary16 or bfloat16 pairs, nearest even) for the
+                  half-storage path
   range_compression  N=4096, 256 lines: chirp_noise rows and a matched
                   filter given directly in frequency: unit-modulus quadratic
                   phase over the swept band, zero outside        (seed 1006)
@@ -154,3 +157,37 @@ def range_compression_inputs(n=4096, batch=256, seed=1006, beta=0.5):
     re = np.where(inband, np.cos(ph), 0.0)
     im = np.where(inband, np.sin(ph), 0.0)
     return x, _to_c64(re, im)
+
+
+def bf16_bits(a):
+    """float32 -> bfloat16 bit patterns (uint16), rounding to nearest even."""
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    nan = np.isnan(np.asarray(a, dtype=np.float32))
+    r[nan] = ((u[nan] >> 16) | 0x40).astype(np.uint16)
+    return r
+
+
+def bf16_value(bits):
+    """bfloat16 bit patterns -> float32 values (exact)."""
+    return (np.asarray(bits, dtype=np.uint16).astype(np.uint32) << 16).view(np.float32)
+
+
+def to_storage(x, fmt):
+    """Round complex values to a 16-bit storage format.
+
+    Returns (stored, values): `stored` is an array of shape x.shape + (2,)
+    holding (real, imaginary) as float16 (fmt "f16") or as bfloat16 bit
+    patterns in uint16 (fmt "bf16"); `values` is complex128, the exact values
+    those hold (what the transform is then applied to)."""
+    x = np.asarray(x)
+    pair = np.stack([x.real, x.imag], axis=-1).astype(np.float32)
+    if fmt == "f16":
+        stored = pair.astype(np.float16)
+        back = stored.astype(np.float64)
+    elif fmt == "bf16":
+        stored = bf16_bits(pair)
+        back = bf16_value(stored).astype(np.float64)
+    else:
+        raise ValueError("fmt must be 'f16' or 'bf16'")
+    return stored, back[..., 0] + 1j * back[..., 1]

@@ -1,0 +1,109 @@
+"""16-bit storage (binary16 / bfloat16 pairs in HBM, FP32 arithmetic)
+against the FP64 oracle applied to the stored input values."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_2603_27569_amd as sf
+from paper_2603_27569_amd import metrics, workloads
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+SINGLE = [v for v in sf.variants() if v["kind"] == "single"]
+
+
+def _device(stored, fmt):
+    t = torch.from_numpy(np.ascontiguousarray(stored))
+    if fmt == "bf16":
+        t = t.view(torch.int16).view(torch.bfloat16)
+    return t.to(DEV)
+
+
+def _host(t, fmt):
+    a = t.cpu()
+    if fmt == "bf16":
+        v = workloads.bf16_value(a.view(torch.int16).numpy().view(np.uint16)).astype(np.float64)
+    else:
+        v = a.numpy().astype(np.float64)
+    return v[..., 0] + 1j * v[..., 1]
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+@pytest.mark.parametrize("v", SINGLE, ids=[v["name"] for v in SINGLE])
+def test_every_variant_with_16bit_storage(v, fmt):
+    n = v["n"]
+    batch = 2 * v["transforms_per_workgroup"] + 1
+    x = workloads.plain_normal(n, batch, seed=n + 77)
+    stored, xv = workloads.to_storage(x, fmt)
+    for inverse in (False, True):
+        p = sf.Plan(n, batch, sf.FFT_BACKWARD if inverse else sf.FFT_FORWARD,
+                    sf.FFT_ALGO_SINGLE_PASS, v["name"])
+        xt = _device(stored, fmt)
+        yt = torch.empty_like(xt)
+        sf.fft_exec_io(p.handle, xt.data_ptr(), yt.data_ptr(),
+                       sf.FFT_IO_C16 if fmt == "f16" else sf.FFT_IO_BC16,
+                       torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        p.close()
+        ok, worst, _, ab = metrics.gate_storage(_host(yt, fmt), oracle.fft(xv, inverse=inverse), xv, fmt)
+        assert ok, (inverse, worst, ab)
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_lowp_auto_plan_in_place_and_repeatable(fmt):
+    n, b = 4096, 64
+    x = workloads.plain_normal(n, b, seed=5)
+    stored, xv = workloads.to_storage(x, fmt)
+    xt = _device(stored, fmt)
+    y1 = sf.fft_lowp(xt)
+    y2 = sf.fft_lowp(xt)
+    z = xt.clone()
+    sf.fft_lowp(z, out=z)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2) and torch.equal(y1, z)
+    ok, worst, med, _ = metrics.gate_storage(_host(y1, fmt), oracle.fft(xv), xv, fmt)
+    u = metrics.STORAGE_UNIT_ROUNDOFF[fmt]
+    assert ok and med > 0.2 * u  # the error is the output rounding, not zero
+    print(f"lowp {fmt}: worst rel-RMS {worst:.3e} (u = {u:.3e})", flush=True)
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_lowp_output_is_the_fp32_result_rounded_once(fmt):
+    # The same plan in FP32 on the widened input gives the values before the
+    # final rounding; the 16-bit result must be those, rounded to nearest
+    # (within one unit in the last place where the two kernels' FP32
+    # arithmetic differs in its last bit).
+    n, b = 1024, 32
+    x = workloads.plain_normal(n, b, seed=11)
+    stored, xv = workloads.to_storage(x, fmt)
+    xt = _device(stored, fmt)
+    y16 = _host(sf.fft_lowp(xt), fmt)
+    y32 = sf.fft(torch.from_numpy(xv.astype(np.complex64)).to(DEV), algorithm=sf.FFT_ALGO_SINGLE_PASS)
+    _, r32 = workloads.to_storage(y32.cpu().numpy(), fmt)
+    torch.cuda.synchronize()
+    same = np.mean(y16 == r32)
+    assert same > 0.99, same
+    u = metrics.STORAGE_UNIT_ROUNDOFF[fmt]
+    rowmax = np.max(np.abs(r32), axis=1, keepdims=True)
+    assert np.all(np.abs(y16 - r32) <= 4 * u * (np.abs(r32) + 1e-3 * rowmax))
+
+
+def test_lowp_errors():
+    L = sf._lib.lib()
+    vp = ctypes.c_void_p
+    buf = torch.zeros(4096 * 8, dtype=torch.float16, device=DEV)
+    base = buf.data_ptr()
+    p = sf.Plan(1024, 4)
+    assert L.fft_exec_io(vp(p.handle), vp(base + 2), vp(base + 8192), 1, None) == sf.CODES["FFT_MISALIGNED"]
+    assert L.fft_exec_io(vp(p.handle), vp(base), vp(base + 4), 1, None) == sf.CODES["FFT_OVERLAP"]
+    assert L.fft_exec_io(vp(p.handle), vp(base), vp(base), 7, None) == sf.CODES["FFT_INVALID_ARGUMENT"]
+    q = sf.Plan(8192, 1, algorithm=sf.FFT_ALGO_FOUR_STEP)
+    assert L.fft_exec_io(vp(q.handle), vp(base), vp(base), 2, None) == sf.CODES["FFT_UNSUPPORTED"]
+    q.close()
+    h = p.handle
+    p.close()
+    assert L.fft_exec_io(vp(h), vp(base), vp(base), 1, None) == sf.CODES["FFT_INVALID_PLAN"]
+    torch.cuda.synchronize()

@@ -131,3 +131,30 @@ def test_ragged_recipe():
     # log-uniform exponents: each class near 2000/7
     counts = np.array([np.sum(sizes == s) for s in workloads.SIZES])
     assert np.all(np.abs(counts - 2000 / 7) < 60)
+
+
+def test_bf16_rounding_is_nearest_even():
+    # halfway cases round to the even neighbour; others to the nearest
+    one = np.float32(1.0)
+    step = np.float32(2.0 ** -7)  # bfloat16 spacing at 1.0
+    vals = np.array([one, one + step / 2, one + 3 * step / 2, one + step / 4, -(one + step / 2),
+                     np.float32(np.inf), np.float32(-0.0)], dtype=np.float32)
+    got = workloads.bf16_value(workloads.bf16_bits(vals))
+    want = np.array([1.0, 1.0, 1.0 + 2 * step, 1.0, -1.0, np.inf, -0.0], dtype=np.float32)
+    assert np.array_equal(got, want)
+    assert np.isnan(workloads.bf16_value(workloads.bf16_bits(np.array([np.nan], np.float32))))[0]
+
+
+def test_storage_gate():
+    x = workloads.plain_normal(256, 4, seed=3)
+    for fmt, u in (("f16", 2.0 ** -11), ("bf16", 2.0 ** -8)):
+        stored, v = workloads.to_storage(x, fmt)
+        assert stored.shape == x.shape + (2,)
+        ref = np.fft.fft(v)
+        # the reference rounded once to the format passes ...
+        _, r = workloads.to_storage(ref.astype(np.complex64), fmt)
+        ok, worst, _, _ = metrics.gate_storage(r, ref, v, fmt)
+        assert ok and worst <= u
+        # ... ten roundings' worth of error does not
+        bad = ref * (1 + 10 * u)
+        assert not metrics.gate_storage(bad, ref, v, fmt)[0]
