@@ -1,5 +1,5 @@
-// Kernels of the plain, fused and four-step paths, templated on a Stockham
-// Shape (stockham.hpp).  Each kernel is launched by a small host wrapper that
+// Kernels of the plain, 16-bit storage, fused and four-step paths, templated
+// on a Stockham Shape (stockham.hpp).  Each kernel is launched by a small host wrapper that
 // splits very large batches into several grids.
 #pragma once
 
@@ -34,6 +34,42 @@ __device__ __forceinline__ void global_store_row(const c32 (&a)[S::E], c32* dst,
 // ------------------------------------------------------------ single pass
 // One dispatch per batch (the paper's synthesis rule 1, Section IV-D): each
 // workgroup owns TPB whole transforms; every pass stays on chip.
+template <class S, bool INV>
+__global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham(const c32* in, c32* out,
+                                                         const c32* tw, int64_t rows) {
+  __shared__ alignas(16) c32 lds_all[S::TPB * S::LDS_ELEMS];
+  const int tid = threadIdx.x;
+  const int slot = tid / S::T;
+  const int t = tid - slot * S::T;
+  const int64_t row = (int64_t)blockIdx.x * S::TPB + slot;
+  const bool live = row < rows;
+  c32* lds = lds_all + slot * S::LDS_ELEMS;
+  c32 a[S::E];
+  global_load_row<S>(a, in + row * S::N, t, live);
+  run_passes<S, INV>(a, lds, tw, t);
+  global_store_row<S>(a, out + row * S::N, t, live);
+}
+
+template <class S>
+hipError_t launch_single(const void* in, void* out, const void* tw, int64_t batch, bool inverse,
+                         hipStream_t s) {
+  const int64_t groups = (batch + S::TPB - 1) / S::TPB;
+  const int64_t cap = max_groups_per_launch();
+  for (int64_t g0 = 0; g0 < groups; g0 += cap) {
+    const int64_t g = groups - g0 < cap ? groups - g0 : cap;
+    const int64_t r0 = g0 * S::TPB;
+    const c32* ip = static_cast<const c32*>(in) + r0 * S::N;
+    c32* op = static_cast<c32*>(out) + r0 * S::N;
+    const c32* twp = static_cast<const c32*>(tw);
+    if (inverse)
+      k_stockham<S, true><<<dim3((unsigned)g), dim3(S::THREADS), 0, s>>>(ip, op, twp, batch - r0);
+    else
+      k_stockham<S, false><<<dim3((unsigned)g), dim3(S::THREADS), 0, s>>>(ip, op, twp, batch - r0);
+  }
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ 16-bit storage
 // 16-bit storage formats: one complex value in 4 bytes (real in the low
 // half).  Loads widen exactly to FP32; stores round to nearest even.
 struct IoF16 {
@@ -103,41 +139,6 @@ hipError_t launch_single_io(const void* in, void* out, const void* tw, int64_t b
       k_stockham_io<S, true, IO><<<dim3((unsigned)g), dim3(S::THREADS), 0, s>>>(ip, op, twp, batch - r0);
     else
       k_stockham_io<S, false, IO><<<dim3((unsigned)g), dim3(S::THREADS), 0, s>>>(ip, op, twp, batch - r0);
-  }
-  return hipGetLastError();
-}
-
-template <class S, bool INV>
-__global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham(const c32* in, c32* out,
-                                                         const c32* tw, int64_t rows) {
-  __shared__ alignas(16) c32 lds_all[S::TPB * S::LDS_ELEMS];
-  const int tid = threadIdx.x;
-  const int slot = tid / S::T;
-  const int t = tid - slot * S::T;
-  const int64_t row = (int64_t)blockIdx.x * S::TPB + slot;
-  const bool live = row < rows;
-  c32* lds = lds_all + slot * S::LDS_ELEMS;
-  c32 a[S::E];
-  global_load_row<S>(a, in + row * S::N, t, live);
-  run_passes<S, INV>(a, lds, tw, t);
-  global_store_row<S>(a, out + row * S::N, t, live);
-}
-
-template <class S>
-hipError_t launch_single(const void* in, void* out, const void* tw, int64_t batch, bool inverse,
-                         hipStream_t s) {
-  const int64_t groups = (batch + S::TPB - 1) / S::TPB;
-  const int64_t cap = max_groups_per_launch();
-  for (int64_t g0 = 0; g0 < groups; g0 += cap) {
-    const int64_t g = groups - g0 < cap ? groups - g0 : cap;
-    const int64_t r0 = g0 * S::TPB;
-    const c32* ip = static_cast<const c32*>(in) + r0 * S::N;
-    c32* op = static_cast<c32*>(out) + r0 * S::N;
-    const c32* twp = static_cast<const c32*>(tw);
-    if (inverse)
-      k_stockham<S, true><<<dim3((unsigned)g), dim3(S::THREADS), 0, s>>>(ip, op, twp, batch - r0);
-    else
-      k_stockham<S, false><<<dim3((unsigned)g), dim3(S::THREADS), 0, s>>>(ip, op, twp, batch - r0);
   }
   return hipGetLastError();
 }
