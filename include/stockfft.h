@@ -147,7 +147,10 @@ int fft_destroy(fft_plan_t plan);
  *               or NULL to compute the loss only (forward passes only).
  *   row_loss    device, batch float32: the per-row sums.  Required.
  *   loss_total  device, one float32 receiving sum_b row_loss[b] (a fixed-order
- *               tree, bitwise reproducible), or NULL.
+ *               tree, bitwise reproducible), or NULL.  The kernel's last
+ *               workgroup writes it, counting arrivals on counters the plan
+ *               owns: calls on one plan must not run concurrently (different
+ *               streams without ordering between them race).
  * Errors: FFT_INVALID_PLAN, FFT_INVALID_POINTER, FFT_MISALIGNED,
  * FFT_OVERLAP (grad_x partially overlapping x), FFT_UNSUPPORTED (backward or
  * four-step plan), FFT_HIP_ERROR.

@@ -24,7 +24,6 @@ namespace stockfft {
 const SingleVariant* variants_small(int* count);
 const SingleVariant* variants_4096(int* count);
 const SingleVariant* variants_large(int* count);
-hipError_t launch_sum_rows(const float* rows, float* total, int64_t count, hipStream_t s);
 }  // namespace stockfft
 
 using namespace stockfft;
@@ -450,6 +449,7 @@ struct stockfft_plan_s {
   void* d_tw4 = nullptr;
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
+  unsigned* d_counters = nullptr;            // fused loss total (kept zeroed)
   const SingleVariant* sv_filter = nullptr;  // matched-filter kernel shape (forward plans)
   void* d_tw_filter = nullptr;               // its twiddles when it differs from sv
 };
@@ -460,6 +460,7 @@ static void free_plan(stockfft_plan_s* p) {
   if (p->d_tw4) (void)hipFree(p->d_tw4);
   if (p->d_ws) (void)hipFree(p->d_ws);
   if (p->d_tw_filter) (void)hipFree(p->d_tw_filter);
+  if (p->d_counters) (void)hipFree(p->d_counters);
   delete p;
 }
 
@@ -530,6 +531,16 @@ extern "C" int fft_plan_config(fft_plan_t* plan, int64_t n, int64_t batch, int d
   std::vector<float> host;
   build_stockham_twiddles(*sv, host);
   rc = upload(host, &p->d_tw);
+  if (!rc && !fs && direction == FFT_FORWARD && sv->fused) {
+    const size_t bytes = (kTotalGroups * 64 + 1) * sizeof(unsigned);
+    hipError_t e = hipMalloc((void**)&p->d_counters, bytes);
+    if (e == hipSuccess) e = hipMemset(p->d_counters, 0, bytes);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      p->d_counters = nullptr;
+      rc = hip_fail(e);
+    }
+  }
   if (!rc && !fs && direction == FFT_FORWARD) {
     // The matched filter's kernel: the named variant, else its own tuned choice.
     p->sv_filter = variant ? sv : tuned_filter_variant(n, batch);
@@ -623,8 +634,8 @@ extern "C" int fft_exec_spectral_energy(fft_plan_t plan, const void* x, const fl
   if (grad_x && ranges_partially_overlap(x, grad_x, bytes)) return FFT_OVERLAP;
   DeviceGuard g(plan->device);
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = plan->sv->fused(x, w, grad_scale, grad_x, row_loss, plan->d_tw, plan->batch, s);
-  if (e == hipSuccess && loss_total) e = launch_sum_rows(row_loss, loss_total, plan->batch, s);
+  const hipError_t e = plan->sv->fused(x, w, grad_scale, grad_x, row_loss, loss_total,
+                                       plan->d_counters, plan->d_tw, plan->batch, s);
   return e == hipSuccess ? FFT_SUCCESS : hip_fail(e);
 }
 

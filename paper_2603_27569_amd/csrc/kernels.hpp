@@ -159,12 +159,18 @@ __device__ __forceinline__ float wave_group_sum(float v) {
 // x -> y = F x -> (row loss sum w^2 |y|^2, g = 2 w^2 y * scale) -> F^H g.
 // Reads x once and writes the gradient once: 16 N bytes per row against the
 // 48 N of three separate launches.
+// Loss total: workgroups count themselves on kTotalGroups counters (by global
+// index mod kTotalGroups, each on its own 256-byte line), and each group's
+// last one on a second-level counter, so no single address takes every
+// workgroup's atomic.  counters: kTotalGroups * 64 + 1 zeroed words, left zeroed.
 template <class S>
 __global__ __launch_bounds__(S::THREADS, S::WPE) void k_spectral_energy(
     const c32* x, const float* __restrict__ w, const float* __restrict__ scale, c32* grad,
-    float* __restrict__ row_loss, const c32* tw, int64_t rows) {
+    float* row_loss, const c32* tw, int64_t rows, float* total_out, unsigned* counters,
+    float* row_loss_all, int64_t rows_all, unsigned groups_all, unsigned gbase) {
   __shared__ alignas(16) c32 lds_all[S::TPB * S::LDS_ELEMS];
   __shared__ float red[(S::THREADS + 63) / 64];
+  __shared__ int is_last;
   const int tid = threadIdx.x;
   const int slot = tid / S::T;
   const int t = tid - slot * S::T;
@@ -199,16 +205,80 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_spectral_energy(
 #pragma unroll
       for (int i = 0; i < S::T / 64; ++i) total += red[w0 + i];
     }
-    row_loss[row] = total;
+    if (total_out != nullptr)
+      atomicExch(&row_loss[row], total);  // published where every XCD sees it
+    else
+      row_loss[row] = total;
   }
-  if (grad == nullptr) return;  // uniform across the workgroup
-  run_passes<S, true>(a, lds, tw, t);
-  global_store_row<S>(a, grad + row * S::N, t, live);
+  if (grad != nullptr) {  // uniform across the launch
+    run_passes<S, true>(a, lds, tw, t);
+    global_store_row<S>(a, grad + row * S::N, t, live);
+  }
+  if (total_out != nullptr) {  // uniform across the launch
+    // The loss total: the last workgroup to finish adds all rows in a fixed
+    // order (bitwise reproducible), reading them with device-scope atomic
+    // loads as they were published, so no cache write-back is needed.
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this lane's publication has completed
+    __syncthreads();  // ... for every lane; and the LDS is free
+    if (tid == 0) {
+      const unsigned gi = gbase + blockIdx.x;
+      const unsigned grp = gi % kTotalGroups;
+      const unsigned in_grp = groups_all / kTotalGroups + (grp < groups_all % kTotalGroups ? 1u : 0u);
+      const unsigned ngrp = groups_all < kTotalGroups ? groups_all : kTotalGroups;
+      unsigned* c1 = counters + grp * 64;
+      unsigned* c2 = counters + kTotalGroups * 64;
+      int last = 0;
+      if (atomicAdd(c1, 1u) == in_grp - 1u) {
+        atomicExch(c1, 0u);
+        if (atomicAdd(c2, 1u) == ngrp - 1u) {
+          atomicExch(c2, 0u);
+          last = 1;
+        }
+      }
+      is_last = last;
+    }
+    __syncthreads();
+    if (is_last) {
+      // Summation order, whatever the workgroup size: 1024 lanes, lane v adds
+      // rows v, v + 1024, ... in turn, then a halving tree (lane v adds lane
+      // v + h for h = 512, 256, ..., 1).  Thread tid plays lanes tid + j THREADS.
+      static_assert(1024 % S::THREADS == 0 && S::THREADS % 64 == 0, "lane mapping");
+      static_assert(S::TPB * S::LDS_ELEMS * sizeof(c32) >= S::THREADS * sizeof(float), "tree");
+      constexpr int V = 1024 / S::THREADS;
+      float v[V];
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        v[j] = 0.f;
+        for (int64_t i = tid + j * S::THREADS; i < rows_all; i += 1024)
+          v[j] += __hip_atomic_load(row_loss_all + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+#pragma unroll
+      for (int h = V / 2; h > 0; h >>= 1)  // tree steps h * THREADS, inside a thread
+#pragma unroll
+        for (int j = 0; j < h; ++j) v[j] += v[j + h];
+      float part = v[0];
+      if constexpr (S::THREADS > 64) {  // tree steps THREADS / 2 .. 64, across waves
+        float* f = reinterpret_cast<float*>(lds_all);
+        f[tid] = part;
+        __syncthreads();
+#pragma unroll
+        for (int h = S::THREADS / 2; h >= 64; h >>= 1) {
+          if (tid < h) f[tid] += f[tid + h];
+          __syncthreads();
+        }
+        part = f[tid & 63];
+      }
+#pragma unroll
+      for (int h = 32; h > 0; h >>= 1) part += __shfl_xor(part, h, 64);  // steps 32 .. 1
+      if (tid == 0) total_out[0] = part;
+    }
+  }
 }
 
 template <class S>
 hipError_t launch_spectral_energy(const void* x, const float* w, const float* scale, void* grad,
-                                  float* row_loss, const void* tw, int64_t batch, hipStream_t s) {
+                                  float* row_loss, float* total, unsigned* counters, const void* tw,
+                                  int64_t batch, hipStream_t s) {
   const int64_t groups = (batch + S::TPB - 1) / S::TPB;
   const int64_t cap = max_groups_per_launch();
   for (int64_t g0 = 0; g0 < groups; g0 += cap) {
@@ -217,7 +287,8 @@ hipError_t launch_spectral_energy(const void* x, const float* w, const float* sc
     k_spectral_energy<S><<<dim3((unsigned)g), dim3(S::THREADS), 0, s>>>(
         static_cast<const c32*>(x) + r0 * S::N, w, scale,
         grad ? static_cast<c32*>(grad) + r0 * S::N : nullptr, row_loss + r0,
-        static_cast<const c32*>(tw), batch - r0);
+        static_cast<const c32*>(tw), batch - r0, total, counters, row_loss, batch,
+        (unsigned)groups, (unsigned)g0);
   }
   return hipGetLastError();
 }

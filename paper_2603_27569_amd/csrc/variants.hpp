@@ -27,8 +27,13 @@ using LaunchFn = hipError_t (*)(const void* in, void* out, const void* tw, int64
 
 // Fused forward -> weight -> adjoint: grad = scale * F^H(2 w^2 .* F x) and
 // row_loss[b] = sum_k w_k^2 |(F x_b)[k]|^2.  grad may be null (loss only).
+// With total non-null the last workgroup to finish also writes sum_b
+// row_loss[b] there; counters is plan-owned zeroed device memory of
+// kTotalGroups * 64 + 1 words, left zeroed.
+constexpr unsigned kTotalGroups = 16;  // first-level counters of the fused loss total
 using FusedFn = hipError_t (*)(const void* x, const float* w, const float* scale, void* grad,
-                               float* row_loss, const void* tw, int64_t batch, hipStream_t s);
+                               float* row_loss, float* total, unsigned* counters, const void* tw,
+                               int64_t batch, hipStream_t s);
 
 // Fused matched filter: out = (1/N) F^H(conj(h) .* F x).
 using FilterFn = hipError_t (*)(const void* x, const void* h, void* out, const void* tw,

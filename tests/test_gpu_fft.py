@@ -295,6 +295,23 @@ def test_spectral_energy_total_reproducible(limit):
     assert abs(totals[0] - ref_rows.sum()) / ref_rows.sum() <= 1e-5
 
 
+@pytest.mark.parametrize("n,batch", [(256, 5), (4096, 17), (16384, 40)])
+def test_spectral_energy_total_few_workgroups(n, batch):
+    # Fewer workgroups than the total's first-level counters, and several rows
+    # per workgroup: the total still covers every row exactly once, in the
+    # fixed order, on repeated calls (the counters must come back to zero).
+    x, w = workloads.spectral_energy_inputs(n=n, batch=batch, seed=31, wseed=32)
+    xt, wt = _gpu(x), _gpu(w)
+    totals = []
+    for want in (True, False, True):
+        total, rows, _ = sf.spectral_energy(xt, wt, want_grad=want)
+        totals.append(float(_host(total)[0]))
+    assert totals[0] == totals[1] == totals[2]
+    assert totals[0] == _fixed_order_total(_host(rows))
+    ref_rows, _ = oracle.spectral_energy(x, w)
+    assert abs(totals[0] - ref_rows.sum()) / ref_rows.sum() <= 1e-5
+
+
 def test_spectral_energy_unit_weight_closed_form():
     n = 4096
     x = workloads.plain_normal(n, 8, seed=9)
