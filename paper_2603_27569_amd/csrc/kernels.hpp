@@ -11,23 +11,44 @@
 
 namespace stockfft {
 
+// Streaming (nontemporal) global accesses for the transform data: every input
+// element is read once and every output element written once, so the hint
+// keeps them from displacing the shared twiddle tables and lets the output
+// drain to memory while the kernel still runs instead of at its end.  The
+// four-step keeps ordinary accesses: its strided column loads share cache
+// lines between workgroups (the hint there cost up to 1.5x at N = 2^20), and
+// its workspace is read back by the second stage.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ c32 load_stream(const c32* p) {
+  const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p));
+  return c32{v.x, v.y};
+}
+__device__ __forceinline__ void store_stream(c32* p, c32 a) {
+  const f32x2 v = {a.x, a.y};
+  __builtin_nontemporal_store(v, reinterpret_cast<f32x2*>(p));
+}
 
 template <class S>
 __device__ __forceinline__ void global_load_row(c32 (&a)[S::E], const c32* src, int t, bool live) {
   if (live) {
 #pragma unroll
-    for (int m = 0; m < S::E; ++m) a[m] = src[t + m * S::T];
+    for (int m = 0; m < S::E; ++m) a[m] = load_stream(src + t + m * S::T);
   } else {
 #pragma unroll
     for (int m = 0; m < S::E; ++m) a[m] = c32{0.f, 0.f};
   }
 }
 
-template <class S>
+template <class S, bool STREAM = true>
 __device__ __forceinline__ void global_store_row(const c32 (&a)[S::E], c32* dst, int t, bool live) {
   if (live) {
 #pragma unroll
-    for (int m = 0; m < S::E; ++m) dst[t + m * S::T] = a[m];
+    for (int m = 0; m < S::E; ++m) {
+      if constexpr (STREAM)
+        store_stream(dst + t + m * S::T, a[m]);
+      else
+        dst[t + m * S::T] = a[m];
+    }
   }
 }
 
@@ -111,7 +132,7 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham_io(const uint32
   if (live) {
     const uint32_t* src = in + row * S::N;
 #pragma unroll
-    for (int m = 0; m < S::E; ++m) a[m] = IO::load(src[t + m * S::T]);
+    for (int m = 0; m < S::E; ++m) a[m] = IO::load(__builtin_nontemporal_load(src + t + m * S::T));
   } else {
 #pragma unroll
     for (int m = 0; m < S::E; ++m) a[m] = c32{0.f, 0.f};
@@ -120,7 +141,7 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham_io(const uint32
   if (live) {
     uint32_t* dst = out + row * S::N;
 #pragma unroll
-    for (int m = 0; m < S::E; ++m) dst[t + m * S::T] = IO::store(a[m]);
+    for (int m = 0; m < S::E; ++m) __builtin_nontemporal_store(IO::store(a[m]), dst + t + m * S::T);
   }
 }
 
@@ -368,7 +389,7 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_four_step_columns(const 
 #pragma unroll
   for (int m = 0; m < S::E; ++m) a[m] = src[(int64_t)(t + m * S::T) * N1];
   run_passes<S, INV>(a, lds, tw, t);
-  global_store_row<S>(a, y + (row * N1 + n1) * S::N, t, true);
+  global_store_row<S, false>(a, y + (row * N1 + n1) * S::N, t, true);
 }
 
 // Length-N1 DFT in registers for the four-step second stage.  N1 <= 16: the
