@@ -18,7 +18,8 @@ and the comparisons the paper's method implies (fused forward+adjoint vs
 the plain chain, fused range compression vs its unfused chain, ragged
 persistent launch vs per-size plain launches, four-step vs single-pass at
 8192/16384, the four-step at 2^16 and 2^20, 16-bit storage against FP32
-storage, a same-footprint copy kernel).  The accuracy figures reported
+storage with vector-ALU and with matrix-core DFTs, a same-footprint copy
+kernel).  The accuracy figures reported
 here are against numpy's FP64 FFT (an independent library routine); the
 parity tests against the oracle are the test suite's job.
 
@@ -427,7 +428,11 @@ def compare_lowp(torch, np, sf, metrics, workloads, T, dev, cs, iters, warm):
         t32 = T.run(lambda i: p.exec(xs[i % K].data_ptr(), ys[i % K].data_ptr(), cs), iters, warm) / iters
         rec["fp32_us"] = round(t32 * 1e6, 3)
         del xs, ys
-        for fmt, io, dt in (("f16", sf.FFT_IO_C16, torch.float16), ("bf16", sf.FFT_IO_BC16, torch.bfloat16)):
+        for key, fmt, io, dt in (("f16", "f16", sf.FFT_IO_C16, torch.float16),
+                                 ("bf16", "bf16", sf.FFT_IO_BC16, torch.bfloat16),
+                                 ("f16_matrix_cores", "f16", sf.FFT_IO_C16_MMA, torch.float16),
+                                 ("bf16_matrix_cores", "bf16", sf.FFT_IO_BC16_MMA, torch.bfloat16)):
+            mma = key.endswith("matrix_cores")
             stored, xv = workloads.to_storage(x_h, fmt)
             t0 = torch.from_numpy(np.ascontiguousarray(stored))
             if fmt == "bf16":
@@ -446,12 +451,14 @@ def compare_lowp(torch, np, sf, metrics, workloads, T, dev, cs, iters, warm):
             else:
                 yv = yh.numpy().astype(np.float64)
             ok, worst, med, _ = metrics.gate_storage(yv[..., 0] + 1j * yv[..., 1], ref_fft(np, xv[:rows]),
-                                                     xv[:rows], fmt)
-            rec[fmt] = {"us": round(t * 1e6, 3), "speedup_vs_fp32": round(t32 / t, 3),
+                                                     xv[:rows], fmt, mma=mma)
+            rec[key] = {"us": round(t * 1e6, 3), "speedup_vs_fp32": round(t32 / t, 3),
                         "GBs_moved_algorithmic": round(8 * n * b / t / 1e9, 1),
                         "pct_hbm_peak": round(100 * 8 * n * b / t / 1e9 / HBM_PEAK_GBS, 2),
                         "worst_rel_rms": worst, "median_rel_rms": med,
                         "unit_roundoff": metrics.STORAGE_UNIT_ROUNDOFF[fmt], "gates_pass": bool(ok)}
+            if mma:
+                rec[key]["gate_factor_u"] = round(metrics.mma_gate_factor(fmt), 3)
             del xs, ys
         p.close()
         out[f"n{n}_b{b}"] = rec

@@ -63,6 +63,10 @@ enum fft_status {
 #define FFT_IO_C64 0   /* complex64: two float32 per value (fft_exec's format) */
 #define FFT_IO_C16 1   /* two IEEE binary16 per value, real part first */
 #define FFT_IO_BC16 2  /* two bfloat16 per value, real part first */
+/* The same storage formats with the 16-point DFTs on the matrix cores (see
+ * fft_exec_io). */
+#define FFT_IO_C16_MMA 3
+#define FFT_IO_BC16_MMA 4
 
 /*
  * fft_plan -- create a plan for `batch` transforms of length `n`.
@@ -121,9 +125,17 @@ int fft_exec(fft_plan_t plan, const void *in, void *out, void *stream);
  * the input row's 2-norm, so inputs must be scaled for that; bfloat16 has
  * float32's range.  Single-pass plans only (n <= 16384).  Asynchronous; does
  * not allocate.  in == out allowed.
+ * FFT_IO_C16_MMA / FFT_IO_BC16_MMA: the same storage, n = 4096 only (plans
+ * whose kernel uses three radix-16 passes), with every 16-point DFT computed
+ * on the matrix cores (the paper's matrix-multiply DFT, Section VI, with its
+ * half-precision future-work item, Section VIII): twiddles are applied in
+ * FP32, then each pass's operands and the DFT matrix are rounded to the
+ * storage format and multiplied with FP32 sums, so the error is that of
+ * about 2 log16(n) + 1 roundings of the format instead of one.
  * Errors: FFT_INVALID_PLAN, FFT_INVALID_ARGUMENT (unknown io),
- * FFT_UNSUPPORTED (four-step plan), FFT_INVALID_POINTER, FFT_MISALIGNED (not
- * 4-byte aligned), FFT_OVERLAP, FFT_HIP_ERROR.
+ * FFT_UNSUPPORTED (four-step plan; for the MMA formats also another length or
+ * radix plan), FFT_INVALID_POINTER, FFT_MISALIGNED (not 4-byte aligned),
+ * FFT_OVERLAP, FFT_HIP_ERROR.
  */
 int fft_exec_io(fft_plan_t plan, const void *in, void *out, int io, void *stream);
 

@@ -21,12 +21,14 @@ import json
 import threading
 
 from ._lib import (CODES, FFT_ALGO_AUTO, FFT_ALGO_FOUR_STEP, FFT_ALGO_SINGLE_PASS, FFT_BACKWARD,
-                   FFT_FORWARD, FFT_IO_BC16, FFT_IO_C16, FFT_IO_C64, STATUS, StockfftError, check,
+                   FFT_FORWARD, FFT_IO_BC16, FFT_IO_BC16_MMA, FFT_IO_C16, FFT_IO_C16_MMA,
+                   FFT_IO_C64, STATUS, StockfftError, check,
                    lib)
 
 __all__ = [
     "FFT_FORWARD", "FFT_BACKWARD", "FFT_ALGO_AUTO", "FFT_ALGO_SINGLE_PASS",
-    "FFT_ALGO_FOUR_STEP", "FFT_IO_C64", "FFT_IO_C16", "FFT_IO_BC16", "StockfftError", "STATUS",
+    "FFT_ALGO_FOUR_STEP", "FFT_IO_C64", "FFT_IO_C16", "FFT_IO_BC16", "FFT_IO_C16_MMA",
+    "FFT_IO_BC16_MMA", "StockfftError", "STATUS",
     "CODES",
     "fft_plan", "fft_plan_config", "fft_exec", "fft_destroy",
     "fft_exec_spectral_energy", "fft_exec_matched_filter",
@@ -328,17 +330,22 @@ def fft(x, inverse=False, out=None, algorithm=FFT_ALGO_AUTO, variant=None):
     return _transform(x, FFT_BACKWARD if inverse else FFT_FORWARD, out, algorithm, variant)
 
 
-def fft_lowp(x, inverse=False, out=None):
+def fft_lowp(x, inverse=False, out=None, mma=False):
     """The transform with 16-bit storage: x is a contiguous float16 or
     bfloat16 tensor of shape [..., N, 2] (real, imaginary); the result has
     the same dtype and shape.  Arithmetic is FP32; the output is rounded once
-    to x's format.  Single-pass lengths only (N <= 16384)."""
+    to x's format.  Single-pass lengths only (N <= 16384).  mma=True (N = 4096
+    only) runs the 16-point DFTs on the matrix cores with operands in x's
+    format and FP32 sums."""
     import torch
     if not isinstance(x, torch.Tensor) or not x.is_cuda or not x.is_contiguous():
         raise ValueError("x must be a contiguous CUDA tensor")
     if x.dtype not in (torch.float16, torch.bfloat16) or x.dim() < 2 or x.shape[-1] != 2:
         raise ValueError("x must be float16 or bfloat16 with a trailing dimension of 2")
-    io = FFT_IO_C16 if x.dtype == torch.float16 else FFT_IO_BC16
+    if mma:
+        io = FFT_IO_C16_MMA if x.dtype == torch.float16 else FFT_IO_BC16_MMA
+    else:
+        io = FFT_IO_C16 if x.dtype == torch.float16 else FFT_IO_BC16
     n = x.shape[-2]
     batch = x.numel() // (2 * n) if n else 0
     if out is None:

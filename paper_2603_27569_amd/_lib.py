@@ -19,6 +19,8 @@ FFT_ALGO_FOUR_STEP = 2
 FFT_IO_C64 = 0
 FFT_IO_C16 = 1
 FFT_IO_BC16 = 2
+FFT_IO_C16_MMA = 3
+FFT_IO_BC16_MMA = 4
 
 STATUS = {
     0: "FFT_SUCCESS", 1: "FFT_INVALID_SIZE", 2: "FFT_INVALID_BATCH",

@@ -597,13 +597,17 @@ extern "C" int fft_exec(fft_plan_t plan, const void* in, void* out, void* stream
 extern "C" int fft_exec_io(fft_plan_t plan, const void* in, void* out, int io, void* stream) {
   if (io == FFT_IO_C64) return fft_exec(plan, in, out, stream);
   if (!plan || !live_handle(plan)) return FFT_INVALID_PLAN;
-  if (io != FFT_IO_C16 && io != FFT_IO_BC16) return FFT_INVALID_ARGUMENT;
+  const bool mma = io == FFT_IO_C16_MMA || io == FFT_IO_BC16_MMA;
+  if (io != FFT_IO_C16 && io != FFT_IO_BC16 && !mma) return FFT_INVALID_ARGUMENT;
   if (plan->algorithm != FFT_ALGO_SINGLE_PASS) return FFT_UNSUPPORTED;
+  if (mma && !mma_supported(*plan->sv)) return FFT_UNSUPPORTED;
   if (!in || !out) return FFT_INVALID_POINTER;
   if (((uintptr_t)in & 3u) || ((uintptr_t)out & 3u)) return FFT_MISALIGNED;
   const size_t bytes = (size_t)plan->n * (size_t)plan->batch * 4;
   if (ranges_partially_overlap(in, out, bytes)) return FFT_OVERLAP;
-  const LaunchFn fn = io == FFT_IO_C16 ? plan->sv->launch_f16 : plan->sv->launch_bf16;
+  LaunchFn fn = io == FFT_IO_C16 ? plan->sv->launch_f16 : plan->sv->launch_bf16;
+  if (io == FFT_IO_C16_MMA) fn = &launch_mma_f16;
+  if (io == FFT_IO_BC16_MMA) fn = &launch_mma_bf16;
   if (!fn) return FFT_UNSUPPORTED;
   DeviceGuard g(plan->device);
   const hipError_t e = fn(in, out, plan->d_tw, plan->batch, plan->direction == FFT_BACKWARD,

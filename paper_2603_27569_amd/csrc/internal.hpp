@@ -24,6 +24,13 @@ bool valid_size(int64_t n);         // any plan length
 bool valid_single_size(int64_t n);  // lengths with a single-pass kernel (and ragged batches)
 int ilog2(int64_t n);
 void build_stockham_twiddles(const SingleVariant& v, std::vector<float>& out);
+// Matrix-core DFT stages with 16-bit storage (mma.hip): lengths whose plan
+// table is the radix-16 one of N = 4096.
+bool mma_supported(const SingleVariant& v);
+hipError_t launch_mma_f16(const void* in, void* out, const void* tw, int64_t batch, bool inverse,
+                          hipStream_t s);
+hipError_t launch_mma_bf16(const void* in, void* out, const void* tw, int64_t batch,
+                           bool inverse, hipStream_t s);
 int upload(const std::vector<float>& host, void** dev);
 int check_device(int* dev);
 bool ranges_partially_overlap(const void* a, const void* b, size_t bytes);

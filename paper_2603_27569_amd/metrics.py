@@ -75,20 +75,51 @@ def gate(y, ref, x, rel_gate=REL_RMS_GATE, abs_gate=None):
 STORAGE_UNIT_ROUNDOFF = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
 
 
-def gate_storage(y, ref, x, fmt):
+def dft16_matrix_error(fmt):
+    """||M_fmt - M||_2 / 4 for the real 32 x 32 form M = [[C, S], [-S, C]] of
+    the 16-point DFT (C, S: cos and sin of 2 pi k r / 16) rounded entrywise to
+    the 16-bit format: the relative error one pass of matrix-core DFTs takes
+    from its rounded matrix (M / 4 is orthogonal)."""
+    k = np.arange(16)
+    ang = 2.0 * np.pi * np.outer(k, k) / 16.0
+    c, s = np.cos(ang), np.sin(ang)
+    m = np.block([[c, s], [-s, c]])
+    if fmt == "f16":
+        mr = m.astype(np.float16).astype(np.float64)
+    else:
+        from .workloads import bf16_bits, bf16_value
+        mr = bf16_value(bf16_bits(m.astype(np.float32))).astype(np.float64)
+    return float(np.linalg.norm(mr - m, 2) / 4.0)
+
+
+def mma_gate_factor(fmt, passes=3):
+    """Error factor g (in units of u) for the matrix-core 16-bit path: the
+    operands of each of the `passes` radix-16 passes and the output are each
+    rounded once (relative RMS <= u / sqrt(3) each, independent, so
+    sqrt(passes + 1) u / sqrt(3) together), and every pass adds the rounded
+    matrix's error (linearly, as it is systematic)."""
+    u = STORAGE_UNIT_ROUNDOFF[fmt]
+    return float(np.sqrt((passes + 1) / 3.0) + passes * dft16_matrix_error(fmt) / u)
+
+
+def gate_storage(y, ref, x, fmt, mma=False):
     """Gate for results stored in a 16-bit format (`ref` is the exact DFT of
     the values actually stored as input).  One rounding of the output to a
     format with unit roundoff u leaves a relative error of at most u per bin
     and about u / sqrt(3) in RMS, so: rel-RMS <= u, and per bin
     |y - X| <= u |X|max + 1e-5 ||x_b||_2 (the FP32 arithmetic's own share, as
-    in the FP32 gate).  Returns (ok, worst_rel_rms, median_rel_rms,
+    in the FP32 gate).  With mma=True (16-point DFTs on the matrix cores,
+    mma_gate_factor) the RMS bound is g u and the per-bin one 2 g u |X|max +
+    1e-5 ||x_b||_2 (a bin's error is the largest of n samples where the RMS
+    averages them).  Returns (ok, worst_rel_rms, median_rel_rms,
     worst_abs_ratio) with the abs ratio taken against that bound."""
     u = STORAGE_UNIT_ROUNDOFF[fmt]
+    g = mma_gate_factor(fmt) if mma else 1.0
     rel, mabs, xn = per_row_errors(y, ref, x)
     r = np.asarray(ref).reshape(rel.shape[0], -1)
-    bound = u * np.max(np.abs(r), axis=1) + 1e-5 * xn
+    bound = (2.0 * g if mma else 1.0) * u * np.max(np.abs(r), axis=1) + 1e-5 * xn
     with np.errstate(divide="ignore", invalid="ignore"):
         ratio = np.where(bound > 0, mabs / bound, np.where(mabs == 0, 0.0, np.inf))
-    ok = bool(np.all(rel <= u) and np.all(ratio <= 1.0))
+    ok = bool(np.all(rel <= g * u) and np.all(ratio <= 1.0))
     return ok, float(rel.max(initial=0.0)), float(np.median(rel) if rel.size else 0.0), \
         float(ratio.max(initial=0.0))

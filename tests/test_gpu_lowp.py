@@ -107,3 +107,103 @@ def test_lowp_errors():
     p.close()
     assert L.fft_exec_io(vp(h), vp(base), vp(base), 1, None) == sf.CODES["FFT_INVALID_PLAN"]
     torch.cuda.synchronize()
+
+
+# ---------------------------------------------------------------- matrix cores
+# FFT_IO_C16_MMA / FFT_IO_BC16_MMA: N = 4096, the 16-point DFTs of the three
+# radix-16 passes as matrix-core products with 16-bit operands and FP32 sums,
+# gated by metrics.gate_storage(..., mma=True).
+
+MMA_IO = {"f16": sf.FFT_IO_C16_MMA, "bf16": sf.FFT_IO_BC16_MMA}
+
+
+def _run_io(plan, xt, io, out=None):
+    yt = torch.empty_like(xt) if out is None else out
+    sf.fft_exec_io(plan.handle, xt.data_ptr(), yt.data_ptr(), io,
+                   torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return yt
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+@pytest.mark.parametrize("inverse", [False, True], ids=["forward", "backward"])
+@pytest.mark.parametrize("batch", [1, 9])
+def test_mma_matches_oracle(fmt, inverse, batch):
+    n = 4096
+    x = workloads.plain_normal(n, batch, seed=40 + batch)
+    stored, xv = workloads.to_storage(x, fmt)
+    p = sf.Plan(n, batch, sf.FFT_BACKWARD if inverse else sf.FFT_FORWARD, sf.FFT_ALGO_SINGLE_PASS)
+    y = _host(_run_io(p, _device(stored, fmt), MMA_IO[fmt]), fmt)
+    p.close()
+    ok, worst, med, ab = metrics.gate_storage(y, oracle.fft(xv, inverse=inverse), xv, fmt, mma=True)
+    u = metrics.STORAGE_UNIT_ROUNDOFF[fmt]
+    print(f"mma {fmt} inverse={inverse} b={batch}: worst rel-RMS {worst / u:.3f} u, "
+          f"gate {metrics.mma_gate_factor(fmt):.3f} u, bin ratio {ab:.3f}", flush=True)
+    assert ok, (worst / u, ab)
+    assert med > 0.2 * u  # the path rounds; an exact result would mean it did not run
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+def test_mma_every_radix16_variant_and_closed_forms(fmt):
+    # The kernel takes the plan's twiddle table; every N = 4096 variant with
+    # three radix-16 passes builds the same one.  Closed forms: a delta row
+    # gives all ones, a tone e^{2 pi i k0 n / N} gives N at bin k0 (within
+    # the gate).
+    n = 4096
+    rows = np.zeros((3, n), dtype=np.complex128)
+    rows[0, 0] = 1.0
+    rows[1] = np.exp(2j * np.pi * 37 * np.arange(n) / n) / 64.0  # N / 64 = 64 at bin 37
+    rows[2] = workloads.plain_normal(n, 1, seed=2)[0]
+    stored, xv = workloads.to_storage(rows, fmt)
+    ref = oracle.fft(xv)
+    for v in SINGLE:
+        if v["n"] != n or v["radices"] != [16, 16, 16]:
+            continue
+        p = sf.Plan(n, 3, sf.FFT_FORWARD, sf.FFT_ALGO_SINGLE_PASS, v["name"])
+        y = _host(_run_io(p, _device(stored, fmt), MMA_IO[fmt]), fmt)
+        p.close()
+        ok, worst, _, ab = metrics.gate_storage(y, ref, xv, fmt, mma=True)
+        assert ok, (v["name"], worst, ab)
+        assert np.all(y[0] == 1.0), v["name"]  # pass 0 of a delta is exact, later passes see ones
+
+
+def test_mma_large_batch_split_in_place_and_repeatable():
+    n, b = 4096, 20000
+    gen = np.random.default_rng(8)
+    xt = torch.from_numpy(gen.standard_normal((b, n, 2)).astype(np.float16)).to(DEV)
+    p = sf.Plan(n, b, sf.FFT_FORWARD, sf.FFT_ALGO_SINGLE_PASS)
+    y1 = _run_io(p, xt, sf.FFT_IO_C16_MMA)
+    y2 = _run_io(p, xt, sf.FFT_IO_C16_MMA)
+    try:
+        sf.fft_set_launch_limit(4097)  # several grids per call
+        y3 = _run_io(p, xt, sf.FFT_IO_C16_MMA)
+    finally:
+        sf.fft_set_launch_limit(0)
+    z = xt.clone()
+    _run_io(p, z, sf.FFT_IO_C16_MMA, out=z)
+    yv = _run_io(p, xt, sf.FFT_IO_C16)
+    p.close()
+    assert torch.equal(y1, y2) and torch.equal(y1, y3) and torch.equal(y1, z)
+    assert not torch.equal(y1, yv)  # a different kernel from the FP32-arithmetic one
+    rows = [0, 1, 4095, 4096, 12345, b - 1]
+    xs = xt[rows].cpu().numpy().astype(np.float64)
+    xv = xs[..., 0] + 1j * xs[..., 1]
+    ok, worst, _, ab = metrics.gate_storage(_host(y1[rows], "f16"), oracle.fft(xv), xv, "f16", mma=True)
+    assert ok, (worst, ab)
+
+
+def test_mma_unsupported_plans():
+    L = sf._lib.lib()
+    vp = ctypes.c_void_p
+    buf = torch.zeros(8192 * 4, dtype=torch.float16, device=DEV)
+    base = buf.data_ptr()
+    radix8 = [v["name"] for v in SINGLE if v["n"] == 4096 and v["radices"] != [16, 16, 16]][0]
+    for args in ((2048, 2, sf.FFT_FORWARD, sf.FFT_ALGO_SINGLE_PASS),
+                 (4096, 1, sf.FFT_FORWARD, sf.FFT_ALGO_SINGLE_PASS, radix8),
+                 (8192, 1, sf.FFT_FORWARD, sf.FFT_ALGO_FOUR_STEP)):
+        p = sf.Plan(*args)
+        for io in (sf.FFT_IO_C16_MMA, sf.FFT_IO_BC16_MMA):
+            assert L.fft_exec_io(vp(p.handle), vp(base), vp(base), io, None) == \
+                sf.CODES["FFT_UNSUPPORTED"], args
+        p.close()
+    torch.cuda.synchronize()

@@ -158,3 +158,40 @@ def test_storage_gate():
         # ... ten roundings' worth of error does not
         bad = ref * (1 + 10 * u)
         assert not metrics.gate_storage(bad, ref, v, fmt)[0]
+
+
+def test_dft16_real_matrix_form():
+    # The 32 x 32 real form [[C, S], [-S, C]] acting on (Re x, Im x) is the
+    # 16-point forward DFT (checked against numpy's FFT, an independent
+    # routine); M / 4 is orthogonal, which is what lets one pass's relative
+    # error be ||M_fmt - M||_2 / 4.
+    k = np.arange(16)
+    ang = 2.0 * np.pi * np.outer(k, k) / 16.0
+    m = np.block([[np.cos(ang), np.sin(ang)], [-np.sin(ang), np.cos(ang)]])
+    x = np.random.default_rng(4).standard_normal(16) + 1j * np.random.default_rng(5).standard_normal(16)
+    y = m @ np.concatenate([x.real, x.imag])
+    assert np.allclose(y[:16] + 1j * y[16:], np.fft.fft(x), rtol=0, atol=1e-12)
+    assert np.allclose((m / 4) @ (m / 4).T, np.eye(32), atol=1e-14)
+
+
+def test_mma_gate_factor():
+    for fmt in ("f16", "bf16"):
+        u = metrics.STORAGE_UNIT_ROUNDOFF[fmt]
+        e = metrics.dft16_matrix_error(fmt)
+        # the rounded matrix is off by less than one unit roundoff per pass, not 0
+        assert 0 < e < u
+        g = metrics.mma_gate_factor(fmt)
+        assert g == pytest.approx(np.sqrt(4 / 3) + 3 * e / u)
+    # binary16: cos(pi / 8), cos(pi / 4), cos(3 pi / 8) round by 5.6e-5, 1.1e-4
+    # and 3.0e-4 relative, giving 0.258 u per pass
+    assert metrics.dft16_matrix_error("f16") / 2.0 ** -11 == pytest.approx(0.2581, abs=1e-3)
+    x = workloads.plain_normal(256, 4, seed=3)
+    stored, v = workloads.to_storage(x, "f16")
+    ref = np.fft.fft(v)
+    u = 2.0 ** -11
+    g = metrics.mma_gate_factor("f16")
+    # a relative error of 0.9 g u (every bin scaled) passes the matrix-core gate
+    # and fails the single-rounding one; 1.1 g u fails both
+    assert metrics.gate_storage(ref * (1 + 0.9 * g * u), ref, v, "f16", mma=True)[0]
+    assert not metrics.gate_storage(ref * (1 + 0.9 * g * u), ref, v, "f16")[0]
+    assert not metrics.gate_storage(ref * (1 + 1.1 * g * u), ref, v, "f16", mma=True)[0]
