@@ -587,7 +587,8 @@ extern "C" int fft_exec(fft_plan_t plan, const void* in, void* out, void* stream
   hipError_t e;
   if (plan->algorithm == FFT_ALGO_FOUR_STEP) {
     e = plan->fs->columns(in, plan->d_ws, plan->d_tw, plan->batch, inv, s);
-    if (e == hipSuccess) e = plan->fs->combine(plan->d_ws, out, plan->d_tw4, plan->batch, inv, s);
+    if (e == hipSuccess) e = plan->fs->combine(plan->d_ws, out, plan->d_tw, plan->d_tw4, plan->batch, inv,
+                                              s);
   } else {
     e = plan->sv->launch(in, out, plan->d_tw, plan->batch, inv, s);
   }

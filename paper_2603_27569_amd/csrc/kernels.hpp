@@ -507,8 +507,8 @@ hipError_t launch_four_step_columns(const void* x, void* y, const void* tw, int6
 }
 
 template <int N1, int N2, bool TWO_LEVEL>
-hipError_t launch_four_step_combine(const void* y, void* out, const void* tw4, int64_t batch,
-                                    bool inverse, hipStream_t s) {
+hipError_t launch_four_step_combine(const void* y, void* out, const void* /*tw*/, const void* tw4,
+                                    int64_t batch, bool inverse, hipStream_t s) {
   static_assert(N2 % 256 == 0, "combine blocks cover 256 consecutive k2");
   const int64_t per = max_groups_per_launch() * 256 / N2;
   const int64_t rows_per_launch = per > 0 ? per : 1;

@@ -60,8 +60,10 @@ extern const SingleVariant kSingleVariants[];
 extern const int kNumSingleVariants;
 
 // Four-step second stage: Z[b][k2 + N2 k1] = sum_{n1} W_N1^{n1 k1} W_N^{n1 k2} Y[b][n1][k2]
-using FourStepCombineFn = hipError_t (*)(const void* y, void* out, const void* tw4, int64_t batch,
-                                         bool inverse, hipStream_t s);
+// (tw: the sub-transform table, used by second stages that run it too; tw4:
+// the stage's own table).
+using FourStepCombineFn = hipError_t (*)(const void* y, void* out, const void* tw, const void* tw4,
+                                         int64_t batch, bool inverse, hipStream_t s);
 // Four-step first stage: Y[b][n1][.] = FFT_N2(x[b][n1 + N1 m], m = 0..N2-1)
 using FourStepColumnsFn = hipError_t (*)(const void* x, void* y, const void* tw, int64_t batch,
                                          bool inverse, hipStream_t s);
