@@ -139,6 +139,11 @@ void build_four_step_twiddles(const FourStepVariant& f, std::vector<float>& out)
   for (int64_t j = 0; j < (int64_t(1) << s); ++j) put(j, N);
   for (int64_t j = 0; j < (N >> s); ++j) put(j << s, N);
   for (int j = 0; j < f.n1; ++j) put(j, f.n1);
+  if (f.sub2_name) {
+    std::vector<float> sub2;
+    build_stockham_twiddles(*find_single(f.sub2_name), sub2);
+    out.insert(out.end(), sub2.begin(), sub2.end());
+  }
 }
 
 int upload(const std::vector<float>& host, void** dev) {
@@ -760,15 +765,18 @@ static int64_t four_step_table_entries(const FourStepVariant& f) {
   if (!f.two_level) return (int64_t)(f.n1 - 1) * f.n2;
   const int64_t N = (int64_t)f.n1 * f.n2;
   const int s = ilog2(N) / 2;
-  return (int64_t(1) << s) + (N >> s) + f.n1;
+  const SingleVariant* sub2 = f.sub2_name ? find_single(f.sub2_name) : nullptr;
+  return (int64_t(1) << s) + (N >> s) + f.n1 + (sub2 ? sub2->tw_elems : 0);
 }
 
 static std::string describe_four_step(const FourStepVariant& f) {
   char buf[384];
   std::snprintf(buf, sizeof buf,
                 "{\"kind\":\"four_step\",\"name\":\"%s\",\"n\":%d,\"n1\":%d,\"n2\":%d,"
-                "\"sub_variant\":\"%s\",\"two_level_twiddles\":%s,\"twiddle_entries\":%lld}",
-                f.name, f.n, f.n1, f.n2, f.sub_name, f.two_level ? "true" : "false",
+                "\"sub_variant\":\"%s\",\"sub2_variant\":\"%s\",\"two_level_twiddles\":%s,"
+                "\"twiddle_entries\":%lld}",
+                f.name, f.n, f.n1, f.n2, f.sub_name, f.sub2_name ? f.sub2_name : "",
+                f.two_level ? "true" : "false",
                 (long long)(f.tw_sub_elems + four_step_table_entries(f)));
   return buf;
 }

@@ -1,18 +1,17 @@
-// Tiled four-step for N = L x L (L = 256, 512, 1024): both stages read and
-// write whole cache-line segments.
+// Tiled four-step for N = N1 x N2 with N1, N2 in {256, 512, 1024}: both
+// stages read and write whole cache-line segments.
 //
-// The decomposition is that of eq. (3) with N1 = N2 = L, n = n1 + L n2 and
-// k = k2 + L k1:
-//   stage 1: Y[k2][n1] = sum_{n2} x[n1 + L n2] W_L^{n2 k2}   (L-point DFTs over n2)
-//   stage 2: X[k2 + L k1] = sum_{n1} W_L^{n1 k1} W_N^{n1 k2} Y[k2][n1].
+// The decomposition is that of eq. (3), n = n1 + N1 n2 and k = k2 + N2 k1:
+//   stage 1: Y[k2][n1] = sum_{n2} x[n1 + N1 n2] W_N2^{n2 k2}   (N2-point DFTs over n2)
+//   stage 2: X[k2 + N2 k1] = sum_{n1} W_N1^{n1 k1} W_N^{n1 k2} Y[k2][n1].
 // A workgroup runs TILE transforms side by side.  In stage 1 they are TILE
 // adjacent n1, so for every n2 the workgroup reads TILE consecutive elements
 // of x (one 128-byte segment for TILE = 16) and writes Y[k2][n1 .. n1 +
 // TILE - 1] the same way; the workspace holds Y row by row in k2.  In stage 2
 // they are TILE adjacent k2: each reads its contiguous workspace row, applies
 // W_N^{n1 k2} (two-level table, as for the N1 x 16384 split) and runs the
-// L-point DFT; the results go through LDS once more so that the stores of
-// X[k2 .. k2 + TILE - 1 + L k1] are again whole segments.  Each transform
+// N1-point DFT; the results go through LDS once more so that the stores of
+// X[k2 .. k2 + TILE - 1 + N2 k1] are again whole segments.  Each transform
 // uses the single-pass body (run_passes) on its own slice of LDS; the slices
 // are an odd number of 8-byte slots apart so that the TILE transforms'
 // accesses to the same position fall on different banks.  TILE = 8 halves
@@ -41,13 +40,14 @@ __device__ __forceinline__ int64_t tile_of_block(int64_t b) {
   return G * (kXcds * (q / G) + x) + q % G;
 }
 
-template <class S, int TILE, bool INV>
-__global__ __launch_bounds__(TILE * S::T, S::WPE) void k_tile_columns(const c32* x, c32* y, const c32* tw,
-                                                              int64_t rows) {
-  static_assert(S::TPB == 1 && S::N % (16 * kXcds) == 0 && 16 % TILE == 0, "tile shape");
-  constexpr int L = S::N;
-  constexpr int64_t N = (int64_t)L * L;
-  constexpr int tiles = L / TILE;
+// Stage 1: S is the N2-point shape.
+template <class S, int N1, int TILE, bool INV>
+__global__ __launch_bounds__(TILE * S::T, S::WPE) void k_tile_columns(const c32* x, c32* y,
+                                                                     const c32* tw, int64_t rows) {
+  static_assert(S::TPB == 1 && N1 % 16 == 0 && 16 % TILE == 0, "tile shape");
+  constexpr int L = N1;
+  constexpr int64_t N = (int64_t)N1 * S::N;
+  constexpr int tiles = N1 / TILE;
   __shared__ alignas(16) c32 lds[TILE * tile_stride<S>()];
   const int64_t g = tile_of_block<TILE>(blockIdx.x);
   const int64_t row = g / tiles;
@@ -71,15 +71,17 @@ __global__ __launch_bounds__(TILE * S::T, S::WPE) void k_tile_columns(const c32*
   for (int m = 0; m < S::E; ++m) dst[(int64_t)m * S::T * L] = a[m];  // Y[k2][n1], k2 = t + m T
 }
 
-template <class S, int TILE, bool INV>
-__global__ __launch_bounds__(TILE * S::T, S::WPE) void k_tile_rows(const c32* y, c32* out, const c32* tw,
-                                                           const c32* __restrict__ tw4,
-                                                           int64_t rows) {
-  constexpr int L = S::N;
-  constexpr int64_t N = (int64_t)L * L;
-  constexpr int tiles = L / TILE;
-  constexpr int SL = half_log2(N);  // = log2 L
-  static_assert((1 << SL) == L, "square split");
+// Stage 2: S is the N1-point shape; tw its table, tw4 the two-level W_N table.
+template <class S, int N2, int TILE, bool INV>
+__global__ __launch_bounds__(TILE * S::T, S::WPE) void k_tile_rows(const c32* y, c32* out,
+                                                                  const c32* tw,
+                                                                  const c32* __restrict__ tw4,
+                                                                  int64_t rows) {
+  constexpr int L = S::N;  // N1: the length of a workspace row
+  constexpr int64_t N = (int64_t)L * N2;
+  constexpr int tiles = N2 / TILE;
+  constexpr int SL = half_log2(N);
+  static_assert(N2 % 16 == 0 && 16 % TILE == 0, "tile shape");
   static_assert(S::C == 1, "the closing transpose holds whole transforms in LDS");
   __shared__ alignas(16) c32 lds[TILE * tile_stride<S>()];
   const int64_t g = tile_of_block<TILE>(blockIdx.x);
@@ -92,19 +94,19 @@ __global__ __launch_bounds__(TILE * S::T, S::WPE) void k_tile_rows(const c32* y,
   const int k2 = tile * TILE + s;
   const c32* src = y + row * N + (int64_t)k2 * L;
   const c32* lo = tw4;
-  const c32* hi = tw4 + L;
+  const c32* hi = tw4 + (1 << SL);
   c32 a[S::E];
 #pragma unroll
   for (int m = 0; m < S::E; ++m) {
     const int n1 = t + m * S::T;
     const int e = n1 * k2;  // < N
-    a[m] = ctw<INV>(src[n1], cmul(hi[e >> SL], lo[e & (L - 1)]));
+    a[m] = ctw<INV>(src[n1], cmul(hi[e >> SL], lo[e & ((1 << SL) - 1)]));
   }
   c32* mine = lds + s * tile_stride<S>();
   run_passes<S, INV>(a, mine, tw, t);
   __syncthreads();  // every wave is past its last exchange reads
 #pragma unroll
-  for (int m = 0; m < S::E; ++m) mine[t + m * S::T] = a[m];  // X[k2 + L k1], k1 = t + m T
+  for (int m = 0; m < S::E; ++m) mine[t + m * S::T] = a[m];  // X[k2 + N2 k1], k1 = t + m T
   __syncthreads();
   const int s2 = tid % TILE;  // adjacent lanes: adjacent k2
   const int t2 = tid / TILE;
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(TILE * S::T, S::WPE) void k_tile_rows(const c32* y,
 #pragma unroll
   for (int m = 0; m < S::E; ++m) {
     const int k1 = t2 + m * S::T;
-    dst[(int64_t)k1 * L] = col[k1];
+    dst[(int64_t)k1 * N2] = col[k1];
   }
 }
 
@@ -124,18 +126,18 @@ inline int64_t tile_grid(int64_t rows, int tiles) {
   return (rows * tiles + q - 1) / q * q;
 }
 
-template <int L, int TILE>
+template <int TILES>
 inline int64_t tile_rows_per_launch() {
-  const int64_t per = max_groups_per_launch() / (L / TILE);
+  const int64_t per = max_groups_per_launch() / TILES;
   return per > 0 ? per : 1;
 }
 
-template <class S, int TILE>
+template <class S, int N1, int TILE>
 hipError_t launch_tile_columns(const void* x, void* y, const void* tw, int64_t batch, bool inverse,
                                hipStream_t s) {
-  constexpr int tiles = S::N / TILE;
-  constexpr int64_t N = (int64_t)S::N * S::N;
-  const int64_t rows_per_launch = tile_rows_per_launch<S::N, TILE>();
+  constexpr int tiles = N1 / TILE;
+  constexpr int64_t N = (int64_t)N1 * S::N;
+  const int64_t rows_per_launch = tile_rows_per_launch<tiles>();
   for (int64_t r0 = 0; r0 < batch; r0 += rows_per_launch) {
     const int64_t rows = batch - r0 < rows_per_launch ? batch - r0 : rows_per_launch;
     const c32* xp = static_cast<const c32*>(x) + r0 * N;
@@ -143,30 +145,34 @@ hipError_t launch_tile_columns(const void* x, void* y, const void* tw, int64_t b
     const c32* twp = static_cast<const c32*>(tw);
     const dim3 grid((unsigned)tile_grid<TILE>(rows, tiles)), block(TILE * S::T);
     if (inverse)
-      k_tile_columns<S, TILE, true><<<grid, block, 0, s>>>(xp, yp, twp, rows);
+      k_tile_columns<S, N1, TILE, true><<<grid, block, 0, s>>>(xp, yp, twp, rows);
     else
-      k_tile_columns<S, TILE, false><<<grid, block, 0, s>>>(xp, yp, twp, rows);
+      k_tile_columns<S, N1, TILE, false><<<grid, block, 0, s>>>(xp, yp, twp, rows);
   }
   return hipGetLastError();
 }
 
-template <class S, int TILE>
+// tw is the stage-1 (N2-point) table; when N1 != N2 the N1-point table follows
+// the two-level table and W_N1 in tw4.
+template <class S, int N2, int TILE>
 hipError_t launch_tile_rows(const void* y, void* out, const void* tw, const void* tw4,
                             int64_t batch, bool inverse, hipStream_t s) {
-  constexpr int tiles = S::N / TILE;
-  constexpr int64_t N = (int64_t)S::N * S::N;
-  const int64_t rows_per_launch = tile_rows_per_launch<S::N, TILE>();
+  constexpr int tiles = N2 / TILE;
+  constexpr int64_t N = (int64_t)S::N * N2;
+  constexpr int SL = half_log2(N);
+  constexpr int64_t own_off = S::N == N2 ? -1 : (int64_t(1) << SL) + (N >> SL) + S::N;
+  const int64_t rows_per_launch = tile_rows_per_launch<tiles>();
   for (int64_t r0 = 0; r0 < batch; r0 += rows_per_launch) {
     const int64_t rows = batch - r0 < rows_per_launch ? batch - r0 : rows_per_launch;
     const c32* yp = static_cast<const c32*>(y) + r0 * N;
     c32* op = static_cast<c32*>(out) + r0 * N;
-    const c32* twp = static_cast<const c32*>(tw);
     const c32* tw4p = static_cast<const c32*>(tw4);
+    const c32* twp = own_off < 0 ? static_cast<const c32*>(tw) : tw4p + own_off;
     const dim3 grid((unsigned)tile_grid<TILE>(rows, tiles)), block(TILE * S::T);
     if (inverse)
-      k_tile_rows<S, TILE, true><<<grid, block, 0, s>>>(yp, op, twp, tw4p, rows);
+      k_tile_rows<S, N2, TILE, true><<<grid, block, 0, s>>>(yp, op, twp, tw4p, rows);
     else
-      k_tile_rows<S, TILE, false><<<grid, block, 0, s>>>(yp, op, twp, tw4p, rows);
+      k_tile_rows<S, N2, TILE, false><<<grid, block, 0, s>>>(yp, op, twp, tw4p, rows);
   }
   return hipGetLastError();
 }

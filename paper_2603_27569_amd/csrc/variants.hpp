@@ -80,6 +80,9 @@ struct FourStepVariant {
   // two short tables, lo[j] = W_N^j (j < 2^s) and hi[j] = W_N^{j 2^s}
   // (j < N / 2^s), s = floor(log2 N / 2), followed by W_N1^j (j < N1).
   bool two_level;
+  // Tiled splits with N1 != N2: the N1-point single-pass shape whose table
+  // the second stage runs on, appended to the stage table (else null).
+  const char* sub2_name;
 };
 
 const FourStepVariant* four_step_variants(int* count);

@@ -290,6 +290,15 @@ def test_twiddle_tables_rounded_once_from_fp64():
             expect += [_exact_roots(j, N) for j in range(2 ** s)]
             expect += [_exact_roots(j << s, N) for j in range(N >> s)]
             expect += [_exact_roots(j, v["n1"]) for j in range(v["n1"])]
+            if v["sub2_variant"]:  # the second stage's own N1-point table
+                sub2 = next(s for s in vs if s["name"] == v["sub2_variant"])
+                assert sub2["n"] == v["n1"]
+                r2 = sub2["radices"]
+                ns = r2[0]
+                for r_p in r2[1:]:
+                    for r in range(1, r_p):
+                        expect += [_exact_roots(k * r, ns * r_p) for k in range(ns)]
+                    ns *= r_p
         expect = np.array(expect)
         assert tab.shape == expect.shape, v["name"]
         assert _ulp_err(tab, expect) <= 0.5 + 1e-6, v["name"]
