@@ -11,8 +11,11 @@
 // as the 32 columns of a 32 x 32 operand and forms M times it with two
 // v_mfma_f32_32x32x16 products (K = 32 split in two halves of 16): the
 // operands are rounded to the 16-bit format, products are exact and the
-// sums are FP32.  Twiddles are applied in FP32 on the vector ALUs before the
-// rounding, and the exchange between passes keeps FP32 values in LDS.
+// sums are FP32.  Each pass's outputs get the next pass's twiddles in FP32 on
+// the vector ALUs and are rounded once to the 16-bit format as they go into
+// LDS, so the exchange moves 16-bit pairs and the next pass reads its
+// operands without converting (the first pass reads them from HBM as
+// stored).
 //
 // Lane layouts of the 32x32x16 products (checked on gfx950): lane l holds
 // A[l % 32][8 (l / 32) + e] and B[8 (l / 32) + e][l % 32] for e < 8, and the
@@ -37,7 +40,7 @@ constexpr int kN = 4096;
 constexpr int kNB = kN / 16;              // butterflies per pass
 constexpr int kThreads = 256;             // four waves per transform
 constexpr int kBlocks = kNB / 32 / (kThreads / 64);  // 32-butterfly blocks per wave
-constexpr int kLds = kN + kN / 16;        // one pad element per 16 against bank conflicts
+constexpr int kLds = kN + kN / 16;        // one pad slot per 16 against bank conflicts
 
 __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
 
@@ -96,11 +99,23 @@ struct MmaOps<IoBF16> {
 // Bin of the butterfly held in output slot q (q < 8) by half h of the wave.
 __device__ __forceinline__ int out_bin(int q, int h) { return 4 * h + q + (q & 4); }
 
+// The 8 real parts (lo) or imaginary parts (hi) of 8 stored 16-bit pairs as
+// one operand: dword i of the operand is half 0 or 1 of pairs 2i and 2i + 1.
+template <class V>
+__device__ __forceinline__ V gather_halves(const uint32_t (&d)[8], bool hi) {
+  const unsigned sel = hi ? 0x07060302u : 0x05040100u;
+  uint32_t w[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w[i] = __builtin_amdgcn_perm(d[2 * i + 1], d[2 * i], sel);
+  return __builtin_bit_cast(V, w);
+}
+
 template <bool INV, class IO>
 __global__ __launch_bounds__(kThreads) void k_stockham_mma(const uint32_t* in, uint32_t* out,
                                                            const c32* tw, int64_t rows) {
   using Ops = MmaOps<IO>;
-  __shared__ alignas(16) c32 lds[kLds];
+  using V = typename Ops::V;
+  __shared__ alignas(16) uint32_t lds[kLds];  // 16-bit pairs, one pad per 16
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int jl = lane & 31;
@@ -110,7 +125,7 @@ __global__ __launch_bounds__(kThreads) void k_stockham_mma(const uint32_t* in, u
 
   // The DFT matrix as the A operand: row jl, columns 8h + e (first product,
   // real legs) and 16 + 8h + e (second product, imaginary legs).
-  typename Ops::V a_re, a_im;
+  V a_re, a_im;
   {
     float re[8], im[8];
 #pragma unroll
@@ -126,84 +141,74 @@ __global__ __launch_bounds__(kThreads) void k_stockham_mma(const uint32_t* in, u
 #pragma unroll
   for (int b = 0; b < kBlocks; ++b) j[b] = 32 * ((tid >> 6) * kBlocks + b) + jl;
 
-  // Legs 8h + e of each butterfly, and every twiddle up front (passes 1, 2:
-  // W_{16 Ns}^{r (j mod Ns)} for leg r, table entry (r - 1) Ns + j mod Ns).
-  c32 d[kBlocks][8];
-  c32 w1[kBlocks][8], w2[kBlocks][8];
+  // Legs 8h + e of each butterfly as stored pairs: the first pass takes its
+  // operands straight from HBM, the later ones from LDS, where the writer has
+  // already applied their twiddles and rounded.
+  uint32_t d[kBlocks][8];
   const uint32_t* src = in + row * kN;
 #pragma unroll
   for (int b = 0; b < kBlocks; ++b)
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int r = 8 * h + e;
-      d[b][e] = IO::load(__builtin_nontemporal_load(src + j[b] + r * kNB));
-      const int r1 = r > 0 ? r - 1 : 0;
-      w1[b][e] = tw[r1 * 16 + (j[b] & 15)];
-      w2[b][e] = tw[15 * 16 + r1 * 256 + j[b]];
-      if (r == 0) w1[b][e] = w2[b][e] = c32{1.f, 0.f};
-    }
+    for (int e = 0; e < 8; ++e) d[b][e] = __builtin_nontemporal_load(src + j[b] + (8 * h + e) * kNB);
 
-  c32 o[kBlocks][8];
 #pragma unroll
   for (int p = 0; p < 3; ++p) {
-    // Operands of every block first, then the products block after block, so
-    // that one block's products run while the next block's are issued.
-    typename Ops::V b_re[kBlocks], b_im[kBlocks];
+    // Bin k of butterfly j goes to x = (j / Ns) Ns 16 + j mod Ns + k Ns, which
+    // the next pass reads as leg r' = x / 256 = j / 16 of butterfly j' = x mod
+    // 256; its twiddle there is W_{16 Ns'}^{r' (j' mod Ns')} (Ns' = 16 Ns):
+    // table entry (r' - 1) 16 + k after the first pass, 240 + (r' - 1) 256 +
+    // j mod 16 + 16 k after the second.  Loaded before the products.
+    c32 wn[kBlocks][8];
+    if (p < 2) {
 #pragma unroll
-    for (int b = 0; b < kBlocks; ++b) {
-      float re[8], im[8];
+      for (int b = 0; b < kBlocks; ++b) {
+        const int r = j[b] >> 4;
+        const int r1 = r > 0 ? r - 1 : 0;
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        c32 v = d[b][e];
-        if (p == 1) v = ctw<INV>(v, w1[b][e]);
-        if (p == 2) v = ctw<INV>(v, w2[b][e]);
-        re[e] = v.x;
-        im[e] = v.y;
+        for (int q = 0; q < 8; ++q) {
+          const int k = out_bin(q, h);
+          const int idx = p == 0 ? r1 * 16 + k : 240 + r1 * 256 + (j[b] & 15) + 16 * k;
+          wn[b][q] = r > 0 ? tw[idx] : c32{1.f, 0.f};
+        }
       }
-      b_re[b] = Ops::pack(re);
-      b_im[b] = Ops::pack(im);
     }
     f32x16 acc[kBlocks];
 #pragma unroll
-    for (int b = 0; b < kBlocks; ++b) acc[b] = Ops::mma(a_re, b_re[b], f32x16{});
+    for (int b = 0; b < kBlocks; ++b) acc[b] = Ops::mma(a_re, gather_halves<V>(d[b], false), f32x16{});
 #pragma unroll
-    for (int b = 0; b < kBlocks; ++b) acc[b] = Ops::mma(a_im, b_im[b], acc[b]);
-#pragma unroll
-    for (int b = 0; b < kBlocks; ++b)
-#pragma unroll
-      for (int q = 0; q < 8; ++q) o[b][q] = c32{acc[b][q], acc[b][8 + q]};
+    for (int b = 0; b < kBlocks; ++b) acc[b] = Ops::mma(a_im, gather_halves<V>(d[b], true), acc[b]);
     if (p < 2) {
-      // Bin k of butterfly j goes to x = (j / Ns) Ns 16 + j mod Ns + k Ns; the
-      // next pass reads leg r of butterfly j at j + r N / 16.  With one pad
-      // element per 16 the padded slots are affine in k and r: pidx(x) =
-      // pidx(x at k = 0) + k for Ns = 1 (x = 16 j + k) and + 17 k for Ns = 16,
-      // and pidx(j + 256 r) = pidx(j) + 272 r, so every access is a base
-      // address plus a constant.
+      // With one pad element per 16 the padded slots are affine in k and r:
+      // pidx(x) = pidx(x at k = 0) + k for Ns = 1 (x = 16 j + k) and + 17 k
+      // for Ns = 16, and pidx(j + 256 r) = pidx(j) + 272 r.
       const int ns = p == 0 ? 1 : 16;
       const int step = p == 0 ? 1 : 17;
 #pragma unroll
       for (int b = 0; b < kBlocks; ++b) {
-        c32* wr = lds + pidx((j[b] / ns) * ns * 16 + (j[b] & (ns - 1))) + step * 4 * h;
+        uint32_t* wr = lds + pidx((j[b] / ns) * ns * 16 + (j[b] & (ns - 1))) + step * 4 * h;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) wr[step * (q + (q & 4))] = o[b][q];
+        for (int q = 0; q < 8; ++q)
+          wr[step * (q + (q & 4))] = IO::store(ctw<INV>(c32{acc[b][q], acc[b][8 + q]}, wn[b][q]));
       }
       __syncthreads();
 #pragma unroll
       for (int b = 0; b < kBlocks; ++b) {
-        const c32* rd = lds + pidx(j[b]) + 272 * 8 * h;
+        const uint32_t* rd = lds + pidx(j[b]) + 272 * 8 * h;
 #pragma unroll
         for (int e = 0; e < 8; ++e) d[b][e] = rd[272 * e];
       }
       __syncthreads();
+    } else {
+      // Last pass (Ns = 256): bin k of butterfly j is element j + 256 k.
+      uint32_t* dst = out + row * kN;
+#pragma unroll
+      for (int b = 0; b < kBlocks; ++b)
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          __builtin_nontemporal_store(IO::store(c32{acc[b][q], acc[b][8 + q]}),
+                                      dst + j[b] + out_bin(q, h) * kNB);
     }
   }
-  // Last pass (Ns = 256): bin k of butterfly j is element j + 256 k.
-  uint32_t* dst = out + row * kN;
-#pragma unroll
-  for (int b = 0; b < kBlocks; ++b)
-#pragma unroll
-    for (int q = 0; q < 8; ++q)
-      __builtin_nontemporal_store(IO::store(o[b][q]), dst + j[b] + out_bin(q, h) * kNB);
 }
 
 template <class IO>
