@@ -204,7 +204,10 @@ def test_plan_describe_and_alloc_failure(monkeypatch):
 def test_launch_splitting_matches_single_grid():
     try:
         sf.fft_set_launch_limit(3)
-        for n, algo, b in [(256, sf.FFT_ALGO_SINGLE_PASS, 200), (8192, sf.FFT_ALGO_FOUR_STEP, 21)]:
+        # (the tiled splits at 2^17 and 2^20: one row per launch, grids rounded
+        # up to whole XCD groups)
+        for n, algo, b in [(256, sf.FFT_ALGO_SINGLE_PASS, 200), (8192, sf.FFT_ALGO_FOUR_STEP, 21),
+                           (1 << 17, sf.FFT_ALGO_FOUR_STEP, 3), (1 << 20, sf.FFT_ALGO_FOUR_STEP, 2)]:
             x = workloads.plain_normal(n, b, seed=5)
             sf.clear_plan_cache()
             y = _host(sf.fft(_gpu(x), algorithm=algo))
