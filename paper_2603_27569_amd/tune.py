@@ -3,7 +3,8 @@
 For every transform length and batch bucket it times each compiled kernel
 variant -- values per lane (hence the radix and lanes per transform),
 transforms per workgroup, LDS padding, and for N >= 8192 the four-step
-splits -- through the C ABI, and keeps the fastest.  The fused matched
+splits (for N > 16384 the only kind) -- through the C ABI, and keeps the
+fastest.  The fused matched
 filter is tuned the same way on its own.  For the ragged persistent kernel
 it picks one compiled shape per length by coordinate descent on a mixed
 ragged batch.  The result is a JSON file that
@@ -36,6 +37,9 @@ from . import (FFT_ALGO_FOUR_STEP, FFT_ALGO_SINGLE_PASS, FFT_FORWARD, Plan, Ragg
                fft_tune_set_ragged, variants)
 
 SIZES = (256, 512, 1024, 2048, 4096, 8192, 16384)
+# Lengths with four-step splits only (plain transform; the fused kernels are
+# single-pass); the timed batch is capped by MAX_BYTES per buffer.
+SIZES_LARGE = tuple(1 << e for e in range(15, 21))
 # Batch buckets: (batch_min, batch_max, representative batch timed).
 BUCKETS = ((1, 64, 32), (65, 512, 256), (513, 4096, 2048), (4097, 2 ** 62, 16384))
 RING_BYTES = 1 << 30
@@ -195,7 +199,8 @@ def run(out_path, quick=False, log=print):
     stream = torch.cuda.Stream()
     props = torch.cuda.get_device_properties(dev)
     buckets = BUCKETS if not quick else ((1, 2 ** 62, 1024),)
-    entries = tune_plain(torch, dev, stream, buckets=buckets, iters=10 if quick else 30, log=log)
+    entries = tune_plain(torch, dev, stream, sizes=SIZES + SIZES_LARGE, buckets=buckets,
+                         iters=10 if quick else 30, log=log)
     filters = tune_filter(torch, dev, stream, buckets=buckets, iters=10 if quick else 30, log=log)
     ragged = tune_ragged(torch, dev, stream, iters=5 if quick else 20, sweeps=1 if quick else 2,
                          log=log)
