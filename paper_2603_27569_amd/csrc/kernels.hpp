@@ -15,9 +15,10 @@ namespace stockfft {
 // element is read once and every output element written once, so the hint
 // keeps them from displacing the shared twiddle tables and lets the output
 // drain to memory while the kernel still runs instead of at its end.  The
-// four-step keeps ordinary accesses: its strided column loads share cache
-// lines between workgroups (the hint there cost up to 1.5x at N = 2^20), and
-// its workspace is read back by the second stage.
+// four-step's stride-N1 column loads keep ordinary accesses (their cache
+// lines are shared between workgroups; the hint there cost up to 1.5x at
+// N = 2^20), and so does its workspace, which the second stage reads back;
+// its final stores stream.
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ c32 load_stream(const c32* p) {
   const f32x2 v = __builtin_nontemporal_load(reinterpret_cast<const f32x2*>(p));
@@ -483,7 +484,7 @@ __global__ __launch_bounds__(256) void k_four_step_combine(const c32* y, c32* ou
   RegDft<N1, INV>::run(v, wn);
   c32* dst = out + row * N + k2;
 #pragma unroll
-  for (int k1 = 0; k1 < N1; ++k1) dst[(int64_t)k1 * N2] = v[RegDft<N1, INV>::slot(k1)];
+  for (int k1 = 0; k1 < N1; ++k1) store_stream(dst + (int64_t)k1 * N2, v[RegDft<N1, INV>::slot(k1)]);
 }
 
 template <class S, int N1>

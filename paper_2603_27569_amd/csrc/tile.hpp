@@ -14,7 +14,9 @@
 // X[k2 .. k2 + TILE - 1 + N2 k1] are again whole segments.  Each transform
 // uses the single-pass body (run_passes) on its own slice of LDS; the slices
 // are an odd number of 8-byte slots apart so that the TILE transforms'
-// accesses to the same position fall on different banks.  TILE = 8 halves
+// accesses to the same position fall on different banks.  Input loads and
+// output stores carry the streaming hint (each segment is touched by one
+// workgroup once); the workspace keeps ordinary accesses.  TILE = 8 halves
 // the LDS (two workgroups per CU at L = 1024); the two tiles that share each
 // 128-byte segment are then put on the same XCD (same L2).
 #pragma once
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(TILE * S::T, S::WPE) void k_tile_columns(const c32*
   const c32* src = x + row * N + n1;
   c32 a[S::E];
 #pragma unroll
-  for (int m = 0; m < S::E; ++m) a[m] = src[(int64_t)(t + m * S::T) * L];
+  for (int m = 0; m < S::E; ++m) a[m] = load_stream(src + (int64_t)(t + m * S::T) * L);
   run_passes<S, INV>(a, lds + s * tile_stride<S>(), tw, t);
   // The store addresses are formed only now (an opaque copy of the lane
   // index), not held in registers through the passes.
@@ -115,7 +117,7 @@ __global__ __launch_bounds__(TILE * S::T, S::WPE) void k_tile_rows(const c32* y,
 #pragma unroll
   for (int m = 0; m < S::E; ++m) {
     const int k1 = t2 + m * S::T;
-    dst[(int64_t)k1 * N2] = col[k1];
+    store_stream(dst + (int64_t)k1 * N2, col[k1]);
   }
 }
 
