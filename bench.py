@@ -417,7 +417,7 @@ def compare(args, torch, np, sf, metrics, workloads, T, dev, cs):
 def compare_lowp(torch, np, sf, metrics, workloads, T, dev, cs, iters, warm):
     out = {}
     n = 4096
-    for b in (256, 16384):
+    for b in (256, 2048, 16384):
         x_h = workloads.complex_normal((b, n), seed=1007 + b)
         rec = {}
         K = ring_count(2 * n * b * 8)

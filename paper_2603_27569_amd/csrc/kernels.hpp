@@ -109,10 +109,12 @@ struct IoBF16 {
   __device__ __forceinline__ static c32 load(uint32_t v) {
     return c32{__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u)};
   }
-  // gfx950 converts a pair in one instruction, rounding to nearest even.
+  // gfx950 converts a pair in one instruction (v_cvt_pk_bf16_f32), rounding
+  // to nearest even.
   __device__ __forceinline__ static uint32_t store(c32 a) {
-    const __hip_bfloat162 h = __float22bfloat162_rn(float2{a.x, a.y});
-    return *reinterpret_cast<const uint32_t*>(&h);
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f2{a.x, a.y}, b2));
   }
 };
 

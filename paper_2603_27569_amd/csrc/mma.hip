@@ -26,6 +26,8 @@
 // parts in accumulators 0 .. 7 and imaginary parts in 8 .. 15.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.hpp"
 #include "kernels.hpp"
 
@@ -38,8 +40,6 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int kN = 4096;
 constexpr int kNB = kN / 16;              // butterflies per pass
-constexpr int kThreads = 256;             // four waves per transform
-constexpr int kBlocks = kNB / 32 / (kThreads / 64);  // 32-butterfly blocks per wave
 constexpr int kLds = kN + kN / 16;        // one pad slot per 16 against bank conflicts
 
 __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
@@ -110,9 +110,15 @@ __device__ __forceinline__ V gather_halves(const uint32_t (&d)[8], bool hi) {
   return __builtin_bit_cast(V, w);
 }
 
-template <bool INV, class IO>
-__global__ __launch_bounds__(kThreads) void k_stockham_mma(const uint32_t* in, uint32_t* out,
-                                                           const c32* tw, int64_t rows) {
+// THREADS lanes per transform (one, two or four waves), each wave taking
+// kBlocks blocks of 32 butterflies: fewer waves mean more independent
+// products per wave and no barrier waits across waves, more waves fewer
+// registers and more transforms in flight.  One wave per transform is held
+// to two waves per SIMD (at most 256 VGPRs).
+template <int THREADS, bool INV, class IO>
+__global__ __launch_bounds__(THREADS, THREADS == 64 ? 2 : 1) void k_stockham_mma(const uint32_t* in, uint32_t* out,
+                                                          const c32* tw, int64_t rows) {
+  constexpr int kBlocks = kNB / 32 / (THREADS / 64);
   using Ops = MmaOps<IO>;
   using V = typename Ops::V;
   __shared__ alignas(16) uint32_t lds[kLds];  // 16-bit pairs, one pad per 16
@@ -139,7 +145,7 @@ __global__ __launch_bounds__(kThreads) void k_stockham_mma(const uint32_t* in, u
 
   int j[kBlocks];
 #pragma unroll
-  for (int b = 0; b < kBlocks; ++b) j[b] = 32 * ((tid >> 6) * kBlocks + b) + jl;
+  for (int b = 0; b < kBlocks; ++b) j[b] = 32 * ((tid >> 6) * kBlocks + b) + jl;  // butterfly
 
   // Legs 8h + e of each butterfly as stored pairs: the first pass takes its
   // operands straight from HBM, the later ones from LDS, where the writer has
@@ -211,21 +217,36 @@ __global__ __launch_bounds__(kThreads) void k_stockham_mma(const uint32_t* in, u
   }
 }
 
-template <class IO>
-hipError_t launch_mma(const void* in, void* out, const void* tw, int64_t batch, bool inverse,
-                      hipStream_t s) {
+template <int THREADS, class IO>
+hipError_t launch_mma_threads(const void* in, void* out, const void* tw, int64_t batch,
+                              bool inverse, hipStream_t s) {
   const int64_t cap = max_groups_per_launch();
   for (int64_t r0 = 0; r0 < batch; r0 += cap) {
     const int64_t g = batch - r0 < cap ? batch - r0 : cap;
     const uint32_t* ip = static_cast<const uint32_t*>(in) + r0 * kN;
     uint32_t* op = static_cast<uint32_t*>(out) + r0 * kN;
     const c32* twp = static_cast<const c32*>(tw);
+    const dim3 grid((unsigned)g), block(THREADS);
     if (inverse)
-      k_stockham_mma<true, IO><<<dim3((unsigned)g), dim3(kThreads), 0, s>>>(ip, op, twp, batch - r0);
+      k_stockham_mma<THREADS, true, IO><<<grid, block, 0, s>>>(ip, op, twp, batch - r0);
     else
-      k_stockham_mma<false, IO><<<dim3((unsigned)g), dim3(kThreads), 0, s>>>(ip, op, twp, batch - r0);
+      k_stockham_mma<THREADS, false, IO><<<grid, block, 0, s>>>(ip, op, twp, batch - r0);
   }
   return hipGetLastError();
+}
+
+// Lanes per transform by batch, from measurements at N = 4096 (binary16,
+// microseconds per launch for 256 / 128 / 64 lanes): batch 256: 5.2 / 5.7 / 7.3,
+// 2048: 23.0 / 17.1 / 17.5, 16384: 152 / 131 / 120.  The bfloat16 kernel
+// needs more registers (its twiddle product and rounding do not fuse), and
+// with one wave per transform it spills: it stops at two waves.
+template <class IO>
+hipError_t launch_mma(const void* in, void* out, const void* tw, int64_t batch, bool inverse,
+                      hipStream_t s) {
+  if (batch <= 512) return launch_mma_threads<256, IO>(in, out, tw, batch, inverse, s);
+  if constexpr (std::is_same<IO, IoF16>::value)
+    if (batch > 4096) return launch_mma_threads<64, IO>(in, out, tw, batch, inverse, s);
+  return launch_mma_threads<128, IO>(in, out, tw, batch, inverse, s);
 }
 
 }  // namespace

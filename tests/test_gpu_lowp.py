@@ -192,6 +192,26 @@ def test_mma_large_batch_split_in_place_and_repeatable():
     assert ok, (worst, ab)
 
 
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+@pytest.mark.parametrize("batch", [700, 5000], ids=["two_waves", "one_wave"])
+def test_mma_lanes_per_transform_by_batch(fmt, batch):
+    # Larger batches run the kernel with two waves, then one wave, per
+    # transform: sampled rows against the oracle, both directions.
+    n = 4096
+    x = workloads.plain_normal(n, batch, seed=batch)
+    stored, xv = workloads.to_storage(x, fmt)
+    rows = [0, 1, batch // 2, batch - 1]
+    xt = _device(stored, fmt)
+    for inverse in (False, True):
+        p = sf.Plan(n, batch, sf.FFT_BACKWARD if inverse else sf.FFT_FORWARD,
+                    sf.FFT_ALGO_SINGLE_PASS)
+        y = _host(_run_io(p, xt, MMA_IO[fmt])[rows], fmt)
+        p.close()
+        ok, worst, _, ab = metrics.gate_storage(y, oracle.fft(xv[rows], inverse=inverse), xv[rows],
+                                                fmt, mma=True)
+        assert ok, (inverse, worst, ab)
+
+
 def test_mma_unsupported_plans():
     L = sf._lib.lib()
     vp = ctypes.c_void_p
