@@ -116,8 +116,8 @@ __device__ __forceinline__ V gather_halves(const uint32_t (&d)[8], bool hi) {
 // registers and more transforms in flight.  One wave per transform is held
 // to two waves per SIMD (at most 256 VGPRs).
 template <int THREADS, bool INV, class IO>
-__global__ __launch_bounds__(THREADS, THREADS == 64 ? 2 : 1) void k_stockham_mma(const uint32_t* in, uint32_t* out,
-                                                          const c32* tw, int64_t rows) {
+__global__ __launch_bounds__(THREADS, THREADS == 64 ? 2 : 1) void k_stockham_mma(
+    const uint32_t* in, uint32_t* out, const c32* tw, int64_t rows) {
   constexpr int kBlocks = kNB / 32 / (THREADS / 64);
   using Ops = MmaOps<IO>;
   using V = typename Ops::V;
@@ -155,7 +155,8 @@ __global__ __launch_bounds__(THREADS, THREADS == 64 ? 2 : 1) void k_stockham_mma
 #pragma unroll
   for (int b = 0; b < kBlocks; ++b)
 #pragma unroll
-    for (int e = 0; e < 8; ++e) d[b][e] = __builtin_nontemporal_load(src + j[b] + (8 * h + e) * kNB);
+    for (int e = 0; e < 8; ++e)
+      d[b][e] = __builtin_nontemporal_load(src + j[b] + (8 * h + e) * kNB);
 
 #pragma unroll
   for (int p = 0; p < 3; ++p) {
@@ -180,7 +181,8 @@ __global__ __launch_bounds__(THREADS, THREADS == 64 ? 2 : 1) void k_stockham_mma
     }
     f32x16 acc[kBlocks];
 #pragma unroll
-    for (int b = 0; b < kBlocks; ++b) acc[b] = Ops::mma(a_re, gather_halves<V>(d[b], false), f32x16{});
+    for (int b = 0; b < kBlocks; ++b)
+      acc[b] = Ops::mma(a_re, gather_halves<V>(d[b], false), f32x16{});
 #pragma unroll
     for (int b = 0; b < kBlocks; ++b) acc[b] = Ops::mma(a_im, gather_halves<V>(d[b], true), acc[b]);
     if (p < 2) {
