@@ -367,7 +367,9 @@ def ifft_unnormalized(x, out=None):
 def spectral_energy(x, w, grad_scale=None, want_grad=True):
     """Fused kernel: returns (loss_total[1], row_loss[batch], grad or None).
 
-    loss = sum_b sum_k w_k^2 |(F x_b)[k]|^2; grad = scale * F^H(2 w^2 F x_b)."""
+    loss = sum_b sum_k w_k^2 |(F x_b)[k]|^2; grad = scale * F^H(2 w^2 F x_b).
+    The plan is cached per (n, batch, device) and its loss-total counters are
+    shared: calls with the same shape on different streams must be ordered."""
     import torch
     _check_tensor(x)
     if w.device != x.device or w.dtype != torch.float32 or not w.is_contiguous():
