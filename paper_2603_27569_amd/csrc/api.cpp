@@ -743,8 +743,10 @@ extern "C" int fft_tune_clear(void) {
 static int barriers_of(const SingleVariant& v) {
   // Per exchange round one barrier after the writes and one after the reads,
   // except after the reads of the last round of the last exchange (the last
-  // pass writes global memory directly, as the first pass reads it).
-  return v.npass >= 2 ? 2 * v.chunks * (v.npass - 1) - 1 : 0;
+  // pass writes global memory directly, as the first pass reads it); with
+  // two alternating buffers only the one after the writes.
+  if (v.npass < 2) return 0;
+  return v.double_buffered ? v.npass - 1 : 2 * v.chunks * (v.npass - 1) - 1;
 }
 
 static std::string radices_json(const SingleVariant& v) {
@@ -763,10 +765,12 @@ static std::string describe_single(const SingleVariant& v) {
                 "\"lanes_per_transform\":%d,\"transforms_per_workgroup\":%d,\"pad_log2\":%d,"
                 "\"lds_layout\":\"%s\","
                 "\"passes\":%d,\"radices\":%s,\"exchange_rounds\":%d,\"threads\":%d,"
-                "\"lds_bytes\":%d,\"twiddle_entries\":%d,\"barriers\":%d}",
+                "\"lds_bytes\":%d,\"twiddle_entries\":%d,\"barriers\":%d,"
+                "\"double_buffered\":%s}",
                 v.name, v.n, v.e, v.t, v.tpb, v.padlog,
                 v.padlog > 0 ? "pad" : v.padlog < 0 ? "xor" : "none", v.npass, radices_json(v).c_str(),
-                v.chunks, v.threads, v.lds_bytes, v.tw_elems, barriers_of(v));
+                v.chunks, v.threads, v.lds_bytes, v.tw_elems, barriers_of(v),
+                v.double_buffered ? "true" : "false");
   return buf;
 }
 

@@ -23,6 +23,8 @@
 // a[m] <-> x[t + m T]: consecutive lanes touch consecutive 8-byte elements.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -231,6 +233,24 @@ struct ShapeX {
   }
 };
 
+// Double-buffered exchange: consecutive exchanges alternate between two LDS
+// buffers, so a pass's writes never meet the previous exchange's reads and
+// the barrier after each exchange's reads is not needed (P - 1 barriers per
+// transform instead of 2P - 3), for twice the LDS.  Whole-transform
+// exchanges only (C = 1).
+template <class Base>
+struct DoubleBuffered : Base {
+  static_assert(Base::C == 1, "double buffering takes whole-transform exchanges");
+  static constexpr bool DB = true;
+  static constexpr int BUF = Base::LDS_ELEMS;
+  static constexpr int LDS_ELEMS = 2 * Base::LDS_ELEMS;
+};
+
+template <class S, class = void>
+struct double_buffered : std::false_type {};
+template <class S>
+struct double_buffered<S, std::void_t<decltype(S::DB)>> : std::integral_constant<bool, S::DB> {};
+
 // The common case: whole-transform exchange buffer, twiddles one pass ahead.
 template <int N_, int E_, int TPB_, int PADLOG_, int... Rs>
 using Shape = ShapeX<1, true, 1, N_, E_, TPB_, PADLOG_, Rs...>;
@@ -353,7 +373,8 @@ __device__ __forceinline__ void exchange(c32 (&a)[S::E], c32* lds, int t) {
   }
 #pragma unroll
   for (int m = 0; m < S::E; ++m) a[m] = nxt[m];
-  if constexpr (p + 2 < S::P) __syncthreads();  // all reads done before the next overwrite
+  if constexpr (p + 2 < S::P && !double_buffered<S>::value)
+    __syncthreads();  // all reads done before the next overwrite
 }
 
 // Runs passes p..P-1.  On entry a[] holds the pass-p inputs in the register
@@ -365,7 +386,10 @@ __device__ __forceinline__ void run_passes_from(c32 (&a)[S::E], c32 (&w)[S::TW_R
                                                 const c32* tw, int t) {
   pass_compute<S, p, INV>(a, w, tw, t);
   if constexpr (p + 1 < S::P) {
-    exchange<S, p>(a, lds, t);
+    if constexpr (double_buffered<S>::value)
+      exchange<S, p>(a, lds + (p & 1) * S::BUF, t);
+    else
+      exchange<S, p>(a, lds, t);
     run_passes_from<S, p + 1, INV>(a, w, lds, tw, t);
   }
 }

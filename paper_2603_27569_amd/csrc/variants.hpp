@@ -44,6 +44,7 @@ struct SingleVariant {
   int n, e, t, tpb, padlog, npass;
   int radix[kMaxPasses];
   int chunks;  // exchange rounds per pass (the LDS holds N / chunks elements per transform)
+  bool double_buffered;  // exchanges alternate between two LDS buffers
   int threads;
   int lds_bytes;
   int tw_elems;

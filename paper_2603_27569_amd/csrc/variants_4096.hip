@@ -16,5 +16,7 @@ STOCKFFT_VARIANT_GROUP(variants_4096,
   // Every pass's twiddles loaded with the input (measured slower at 4096 x 256
   // than one pass ahead: the extra loads delay the input's arrival).
   make_variant<ShapeX<1, 2, 1, 4096, 16, 1, -1, 16, 16, 16>>("n4096_e16_b1_px_r16.16.16_tall"),
+  make_variant<DoubleBuffered<Shape<4096, 16, 1, 5, 16, 16, 16>>>("n4096_e16_b1_p5_r16.16.16_db"),
+  make_variant<DoubleBuffered<Shape<4096, 16, 1, -1, 16, 16, 16>>>("n4096_e16_b1_px_r16.16.16_db"),
   make_variant<Shape<4096, 32, 1, 4, 16, 16, 16>>("n4096_e32_b1_p4_r16.16.16"),
   make_variant<Shape<4096, 32, 2, 4, 16, 16, 16>>("n4096_e32_b2_p4_r16.16.16"))

@@ -199,10 +199,14 @@ def test_variant_inventory():
         chunk = v["n"] // v["exchange_rounds"]
         pad = (chunk >> v["pad_log2"]) if v["pad_log2"] > 0 else 0
         assert v["lds_layout"] == ("pad" if v["pad_log2"] > 0 else "xor" if v["pad_log2"] < 0 else "none")
-        assert v["lds_bytes"] == v["transforms_per_workgroup"] * (chunk + pad) * 8
+        bufs = 2 if v["double_buffered"] else 1
+        assert v["lds_bytes"] == v["transforms_per_workgroup"] * bufs * (chunk + pad) * 8
         assert v["lds_bytes"] <= 160 * 1024  # gfx950 LDS per workgroup
         c = v["exchange_rounds"]
-        assert v["barriers"] == (2 * c * (v["passes"] - 1) - 1 if v["passes"] > 1 else 0)
+        if v["double_buffered"]:  # one barrier per exchange, whole-transform rounds
+            assert c == 1 and v["barriers"] == v["passes"] - 1
+        else:
+            assert v["barriers"] == (2 * c * (v["passes"] - 1) - 1 if v["passes"] > 1 else 0)
         if c > 1:  # every exchange pass splits evenly into the rounds
             assert all((v["values_per_lane"] // r) % c == 0 for r in v["radices"][:-1])
 
