@@ -125,16 +125,18 @@ int fft_exec(fft_plan_t plan, const void *in, void *out, void *stream);
  * the input row's 2-norm, so inputs must be scaled for that; bfloat16 has
  * float32's range.  Single-pass plans only (n <= 16384).  Asynchronous; does
  * not allocate.  in == out allowed.
- * FFT_IO_C16_MMA / FFT_IO_BC16_MMA: the same storage, n = 4096 only (plans
- * whose kernel uses three radix-16 passes), with every 16-point DFT computed
- * on the matrix cores (the paper's matrix-multiply DFT, Section VI, with its
- * half-precision future-work item, Section VIII): twiddles are applied in
- * FP32, then each pass's operands and the DFT matrix are rounded to the
- * storage format and multiplied with FP32 sums, so the error is that of
- * about 2 log16(n) + 1 roundings of the format instead of one.
+ * FFT_IO_C16_MMA / FFT_IO_BC16_MMA: the same storage for n = 16^P * RL
+ * (512, 1024, 2048, 4096, 8192, 16384; any single-pass plan of those
+ * lengths), with every 16-point DFT of the P radix-16 passes computed on the
+ * matrix cores (the paper's matrix-multiply DFT, Section VI, with its
+ * half-precision future-work item, Section VIII) and a last radix-RL pass
+ * (RL = 2, 4, 8) on the vector ALUs: twiddles are applied in FP32, then each
+ * pass's inputs and the DFT matrix are rounded to the storage format and
+ * multiplied with FP32 sums, so the error is that of one rounding per pass
+ * plus the rounded matrix's instead of one rounding in all.
  * Errors: FFT_INVALID_PLAN, FFT_INVALID_ARGUMENT (unknown io),
- * FFT_UNSUPPORTED (four-step plan; for the MMA formats also another length or
- * radix plan), FFT_INVALID_POINTER, FFT_MISALIGNED (not 4-byte aligned),
+ * FFT_UNSUPPORTED (four-step plan; for the MMA formats also another length),
+ * FFT_INVALID_POINTER, FFT_MISALIGNED (not 4-byte aligned),
  * FFT_OVERLAP, FFT_HIP_ERROR.
  */
 int fft_exec_io(fft_plan_t plan, const void *in, void *out, int io, void *stream);

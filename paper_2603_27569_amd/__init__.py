@@ -334,8 +334,8 @@ def fft_lowp(x, inverse=False, out=None, mma=False):
     """The transform with 16-bit storage: x is a contiguous float16 or
     bfloat16 tensor of shape [..., N, 2] (real, imaginary); the result has
     the same dtype and shape.  Arithmetic is FP32; the output is rounded once
-    to x's format.  Single-pass lengths only (N <= 16384).  mma=True (N = 4096
-    only) runs the 16-point DFTs on the matrix cores with operands in x's
+    to x's format.  Single-pass lengths only (N <= 16384).  mma=True (N = 512
+    ... 16384) runs the 16-point DFTs on the matrix cores with operands in x's
     format and FP32 sums."""
     import torch
     if not isinstance(x, torch.Tensor) or not x.is_cuda or not x.is_contiguous():

@@ -464,6 +464,7 @@ struct stockfft_plan_s {
   void* d_ws = nullptr;
   size_t ws_bytes = 0;
   unsigned* d_counters = nullptr;            // fused loss total (kept zeroed)
+  void* d_tw_mma = nullptr;                  // matrix-core table when it differs from sv's
   const SingleVariant* sv_filter = nullptr;  // matched-filter kernel shape (forward plans)
   void* d_tw_filter = nullptr;               // its twiddles when it differs from sv
 };
@@ -475,6 +476,7 @@ static void free_plan(stockfft_plan_s* p) {
   if (p->d_ws) (void)hipFree(p->d_ws);
   if (p->d_tw_filter) (void)hipFree(p->d_tw_filter);
   if (p->d_counters) (void)hipFree(p->d_counters);
+  if (p->d_tw_mma) (void)hipFree(p->d_tw_mma);
   delete p;
 }
 
@@ -555,6 +557,18 @@ extern "C" int fft_plan_config(fft_plan_t* plan, int64_t n, int64_t batch, int d
       rc = hip_fail(e);
     }
   }
+  if (!rc && !fs && mma_supported(n)) {
+    // The matrix-core 16-bit mode runs radix 16 throughout (then one smaller
+    // radix): its own table unless the plan's variant has that radix plan.
+    const SingleVariant* mv = find_single(mma_table_variant(n));
+    bool same = mv && mv->npass == sv->npass;
+    for (int i = 0; same && i < sv->npass; ++i) same = mv->radix[i] == sv->radix[i];
+    if (mv && !same) {
+      std::vector<float> mtw;
+      build_stockham_twiddles(*mv, mtw);
+      rc = upload(mtw, &p->d_tw_mma);
+    }
+  }
   if (!rc && !fs && direction == FFT_FORWARD) {
     // The matched filter's kernel: the named variant, else its own tuned choice.
     p->sv_filter = variant ? sv : tuned_filter_variant(n, batch);
@@ -615,18 +629,23 @@ extern "C" int fft_exec_io(fft_plan_t plan, const void* in, void* out, int io, v
   const bool mma = io == FFT_IO_C16_MMA || io == FFT_IO_BC16_MMA;
   if (io != FFT_IO_C16 && io != FFT_IO_BC16 && !mma) return FFT_INVALID_ARGUMENT;
   if (plan->algorithm != FFT_ALGO_SINGLE_PASS) return FFT_UNSUPPORTED;
-  if (mma && !mma_supported(*plan->sv)) return FFT_UNSUPPORTED;
+  if (mma && !mma_supported(plan->n)) return FFT_UNSUPPORTED;
   if (!in || !out) return FFT_INVALID_POINTER;
   if (((uintptr_t)in & 3u) || ((uintptr_t)out & 3u)) return FFT_MISALIGNED;
   const size_t bytes = (size_t)plan->n * (size_t)plan->batch * 4;
   if (ranges_partially_overlap(in, out, bytes)) return FFT_OVERLAP;
-  LaunchFn fn = io == FFT_IO_C16 ? plan->sv->launch_f16 : plan->sv->launch_bf16;
-  if (io == FFT_IO_C16_MMA) fn = &launch_mma_f16;
-  if (io == FFT_IO_BC16_MMA) fn = &launch_mma_bf16;
-  if (!fn) return FFT_UNSUPPORTED;
+  const LaunchFn fn = io == FFT_IO_C16 ? plan->sv->launch_f16 : plan->sv->launch_bf16;
+  if (!mma && !fn) return FFT_UNSUPPORTED;
   DeviceGuard g(plan->device);
-  const hipError_t e = fn(in, out, plan->d_tw, plan->batch, plan->direction == FFT_BACKWARD,
-                          (hipStream_t)stream);
+  const bool inv = plan->direction == FFT_BACKWARD;
+  hipError_t e;
+  if (mma) {
+    const void* tw = plan->d_tw_mma ? plan->d_tw_mma : plan->d_tw;
+    e = (io == FFT_IO_C16_MMA ? launch_mma_f16 : launch_mma_bf16)(plan->n, in, out, tw, plan->batch,
+                                                                  inv, (hipStream_t)stream);
+  } else {
+    e = fn(in, out, plan->d_tw, plan->batch, inv, (hipStream_t)stream);
+  }
   return e == hipSuccess ? FFT_SUCCESS : hip_fail(e);
 }
 

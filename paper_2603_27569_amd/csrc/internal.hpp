@@ -24,12 +24,14 @@ bool valid_size(int64_t n);         // any plan length
 bool valid_single_size(int64_t n);  // lengths with a single-pass kernel (and ragged batches)
 int ilog2(int64_t n);
 void build_stockham_twiddles(const SingleVariant& v, std::vector<float>& out);
-// Matrix-core DFT stages with 16-bit storage (mma.hip): lengths whose plan
-// table is the radix-16 one of N = 4096.
-bool mma_supported(const SingleVariant& v);
-hipError_t launch_mma_f16(const void* in, void* out, const void* tw, int64_t batch, bool inverse,
-                          hipStream_t s);
-hipError_t launch_mma_bf16(const void* in, void* out, const void* tw, int64_t batch,
+// Matrix-core DFT stages with 16-bit storage (mma.hip): N = 16^P RL for
+// N = 512 ... 16384, on the twiddle table of the variant mma_table_variant(n)
+// (radix 16 throughout, then RL).
+bool mma_supported(int64_t n);
+const char* mma_table_variant(int64_t n);
+hipError_t launch_mma_f16(int64_t n, const void* in, void* out, const void* tw, int64_t batch,
+                          bool inverse, hipStream_t s);
+hipError_t launch_mma_bf16(int64_t n, const void* in, void* out, const void* tw, int64_t batch,
                            bool inverse, hipStream_t s);
 int upload(const std::vector<float>& host, void** dev);
 int check_device(int* dev);

@@ -38,9 +38,23 @@ typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-constexpr int kN = 4096;
-constexpr int kNB = kN / 16;              // butterflies per pass
-constexpr int kLds = kN + kN / 16;        // one pad slot per 16 against bank conflicts
+// N = 16^P * RL: P radix-16 passes on the matrix cores, then (RL > 1) one
+// radix-RL pass on the vector ALUs.
+template <int N>
+struct MmaPlan {
+  static constexpr int RL = N == 512 || N == 8192 ? 2 : N == 1024 || N == 16384 ? 4 : N == 2048 ? 8 : 1;
+  static constexpr int P = N / RL == 256 ? 2 : 3;
+  static constexpr int NB = N / 16;     // butterflies per radix-16 pass
+  static constexpr int NL = N / RL;     // butterflies of the last pass (RL > 1)
+  static constexpr int LDS = N + N / 16;  // one pad slot per 16 against bank conflicts
+  static_assert(N / RL == (P == 2 ? 256 : 4096) && NB % 32 == 0, "unsupported length");
+  // Offset of pass p's twiddle table (entries [r - 1][k], as the host builds it).
+  static constexpr int tw_off(int p) {
+    int o = 0, ns = 16;
+    for (int i = 1; i < p; ++i, ns *= 16) o += 15 * ns;
+    return o;
+  }
+};
 
 __device__ __forceinline__ int pidx(int i) { return i + (i >> 4); }
 
@@ -110,18 +124,20 @@ __device__ __forceinline__ V gather_halves(const uint32_t (&d)[8], bool hi) {
   return __builtin_bit_cast(V, w);
 }
 
-// THREADS lanes per transform (one, two or four waves), each wave taking
-// kBlocks blocks of 32 butterflies: fewer waves mean more independent
-// products per wave and no barrier waits across waves, more waves fewer
-// registers and more transforms in flight.  One wave per transform is held
-// to two waves per SIMD (at most 256 VGPRs).
-template <int THREADS, bool INV, class IO>
+// THREADS lanes per transform, each wave taking kBlocks blocks of 32
+// butterflies: fewer waves mean more independent products per wave and no
+// barrier waits across waves, more waves fewer registers and more transforms
+// in flight.  One wave per transform is held to two waves per SIMD.
+template <int N, int THREADS, bool INV, class IO>
 __global__ __launch_bounds__(THREADS, THREADS == 64 ? 2 : 1) void k_stockham_mma(
     const uint32_t* in, uint32_t* out, const c32* tw, int64_t rows) {
-  constexpr int kBlocks = kNB / 32 / (THREADS / 64);
+  using M = MmaPlan<N>;
+  constexpr int NB = M::NB;
+  constexpr int kBlocks = NB / 32 / (THREADS / 64);
+  static_assert(kBlocks >= 1 && kBlocks * 32 * (THREADS / 64) == NB, "lanes per transform");
   using Ops = MmaOps<IO>;
   using V = typename Ops::V;
-  __shared__ alignas(16) uint32_t lds[kLds];  // 16-bit pairs, one pad per 16
+  __shared__ alignas(16) uint32_t lds[M::LDS];  // 16-bit pairs, one pad per 16
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int jl = lane & 31;
@@ -151,31 +167,36 @@ __global__ __launch_bounds__(THREADS, THREADS == 64 ? 2 : 1) void k_stockham_mma
   // operands straight from HBM, the later ones from LDS, where the writer has
   // already applied their twiddles and rounded.
   uint32_t d[kBlocks][8];
-  const uint32_t* src = in + row * kN;
+  const uint32_t* src = in + row * N;
+  uint32_t* dst = out + row * N;
 #pragma unroll
   for (int b = 0; b < kBlocks; ++b)
 #pragma unroll
     for (int e = 0; e < 8; ++e)
-      d[b][e] = __builtin_nontemporal_load(src + j[b] + (8 * h + e) * kNB);
+      d[b][e] = __builtin_nontemporal_load(src + j[b] + (8 * h + e) * NB);
 
 #pragma unroll
-  for (int p = 0; p < 3; ++p) {
-    // Bin k of butterfly j goes to x = (j / Ns) Ns 16 + j mod Ns + k Ns, which
-    // the next pass reads as leg r' = x / 256 = j / 16 of butterfly j' = x mod
-    // 256; its twiddle there is W_{16 Ns'}^{r' (j' mod Ns')} (Ns' = 16 Ns):
-    // table entry (r' - 1) 16 + k after the first pass, 240 + (r' - 1) 256 +
-    // j mod 16 + 16 k after the second.  Loaded before the products.
+  for (int p = 0; p < M::P; ++p) {
+    const int ns = 1 << (4 * p);  // Ns of this pass
+    const bool last16 = p == M::P - 1;
+    // Bin k of butterfly j goes to x = (j / Ns) Ns 16 + j mod Ns + k Ns.  The
+    // next pass (radix R', Ns' = 16 Ns, N / R' butterflies) reads it as leg
+    // r' = x / (N / R') of butterfly j' = x mod (N / R'), whose twiddle there
+    // is W_{Ns' R'}^{r' (j' mod Ns')}: table entry tw_off + (r' - 1) Ns' + j'
+    // mod Ns'.  Loaded before the products.
     c32 wn[kBlocks][8];
-    if (p < 2) {
+    if (!last16 || M::RL > 1) {
+      const int nsn = 16 * ns;
+      const int span = last16 ? M::NL : NB;  // N / R' (a power of two)
+      const int off = M::tw_off(p + 1);
 #pragma unroll
       for (int b = 0; b < kBlocks; ++b) {
-        const int r = j[b] >> 4;
-        const int r1 = r > 0 ? r - 1 : 0;
+        const int base = (j[b] / ns) * ns * 16 + (j[b] & (ns - 1));
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
-          const int k = out_bin(q, h);
-          const int idx = p == 0 ? r1 * 16 + k : 240 + r1 * 256 + (j[b] & 15) + 16 * k;
-          wn[b][q] = r > 0 ? tw[idx] : c32{1.f, 0.f};
+          const int x = base + out_bin(q, h) * ns;
+          const int r = x / span, jn = x & (span - 1);
+          wn[b][q] = r > 0 ? tw[off + (r - 1) * nsn + (jn & (nsn - 1))] : c32{1.f, 0.f};
         }
       }
     }
@@ -185,86 +206,123 @@ __global__ __launch_bounds__(THREADS, THREADS == 64 ? 2 : 1) void k_stockham_mma
       acc[b] = Ops::mma(a_re, gather_halves<V>(d[b], false), f32x16{});
 #pragma unroll
     for (int b = 0; b < kBlocks; ++b) acc[b] = Ops::mma(a_im, gather_halves<V>(d[b], true), acc[b]);
-    if (p < 2) {
-      // With one pad element per 16 the padded slots are affine in k and r:
-      // pidx(x) = pidx(x at k = 0) + k for Ns = 1 (x = 16 j + k) and + 17 k
-      // for Ns = 16, and pidx(j + 256 r) = pidx(j) + 272 r.
-      const int ns = p == 0 ? 1 : 16;
-      const int step = p == 0 ? 1 : 17;
-#pragma unroll
-      for (int b = 0; b < kBlocks; ++b) {
-        uint32_t* wr = lds + pidx((j[b] / ns) * ns * 16 + (j[b] & (ns - 1))) + step * 4 * h;
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-          wr[step * (q + (q & 4))] = IO::store(ctw<INV>(c32{acc[b][q], acc[b][8 + q]}, wn[b][q]));
-      }
-      __syncthreads();
-#pragma unroll
-      for (int b = 0; b < kBlocks; ++b) {
-        const uint32_t* rd = lds + pidx(j[b]) + 272 * 8 * h;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) d[b][e] = rd[272 * e];
-      }
-      __syncthreads();
-    } else {
-      // Last pass (Ns = 256): bin k of butterfly j is element j + 256 k.
-      uint32_t* dst = out + row * kN;
+    if (last16 && M::RL == 1) {
+      // Last pass (Ns = N / 16): bin k of butterfly j is element j + k N / 16.
 #pragma unroll
       for (int b = 0; b < kBlocks; ++b)
 #pragma unroll
         for (int q = 0; q < 8; ++q)
           __builtin_nontemporal_store(IO::store(c32{acc[b][q], acc[b][8 + q]}),
-                                      dst + j[b] + out_bin(q, h) * kNB);
+                                      dst + j[b] + out_bin(q, h) * NB);
+      return;
+    }
+    // With one pad element per 16 the padded slots are affine in k: pidx(x) =
+    // pidx(x at k = 0) + k for Ns = 1 (x = 16 j + k) and + 17 Ns / 16 k for
+    // Ns >= 16, so every write is a base address plus a constant.
+    const int step = p == 0 ? 1 : 17 * ns / 16;
+#pragma unroll
+    for (int b = 0; b < kBlocks; ++b) {
+      uint32_t* wr = lds + pidx((j[b] / ns) * ns * 16 + (j[b] & (ns - 1))) + step * 4 * h;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        wr[step * (q + (q & 4))] = IO::store(ctw<INV>(c32{acc[b][q], acc[b][8 + q]}, wn[b][q]));
+    }
+    __syncthreads();
+    if (!last16) {
+      // pidx(j + r N / 16) = pidx(j) + 17 N / 256 r.
+#pragma unroll
+      for (int b = 0; b < kBlocks; ++b) {
+        const uint32_t* rd = lds + pidx(j[b]) + (17 * NB / 16) * 8 * h;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) d[b][e] = rd[(17 * NB / 16) * e];
+      }
+      __syncthreads();
+    }
+  }
+  if constexpr (M::RL > 1) {
+    // The radix-RL pass (Ns = N / RL) on the vector ALUs in FP32: butterfly j
+    // reads legs j + r N / RL (twiddles already applied) and writes bin k to
+    // element j + k N / RL.
+    constexpr int R = M::RL, NL = M::NL;
+#pragma unroll
+    for (int jb = tid; jb < NL; jb += THREADS) {
+      c32 v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[r] = IO::load(lds[pidx(jb + r * NL)]);
+      Dft<R, INV>::run(v);
+#pragma unroll
+      for (int k = 0; k < R; ++k) __builtin_nontemporal_store(IO::store(v[k]), dst + jb + k * NL);
     }
   }
 }
 
-template <int THREADS, class IO>
+template <int N, int THREADS, class IO>
 hipError_t launch_mma_threads(const void* in, void* out, const void* tw, int64_t batch,
                               bool inverse, hipStream_t s) {
   const int64_t cap = max_groups_per_launch();
   for (int64_t r0 = 0; r0 < batch; r0 += cap) {
     const int64_t g = batch - r0 < cap ? batch - r0 : cap;
-    const uint32_t* ip = static_cast<const uint32_t*>(in) + r0 * kN;
-    uint32_t* op = static_cast<uint32_t*>(out) + r0 * kN;
+    const uint32_t* ip = static_cast<const uint32_t*>(in) + r0 * N;
+    uint32_t* op = static_cast<uint32_t*>(out) + r0 * N;
     const c32* twp = static_cast<const c32*>(tw);
     const dim3 grid((unsigned)g), block(THREADS);
     if (inverse)
-      k_stockham_mma<THREADS, true, IO><<<grid, block, 0, s>>>(ip, op, twp, batch - r0);
+      k_stockham_mma<N, THREADS, true, IO><<<grid, block, 0, s>>>(ip, op, twp, batch - r0);
     else
-      k_stockham_mma<THREADS, false, IO><<<grid, block, 0, s>>>(ip, op, twp, batch - r0);
+      k_stockham_mma<N, THREADS, false, IO><<<grid, block, 0, s>>>(ip, op, twp, batch - r0);
   }
   return hipGetLastError();
 }
 
-// Lanes per transform by batch, from measurements at N = 4096 (binary16,
-// microseconds per launch for 256 / 128 / 64 lanes): batch 256: 5.2 / 5.7 / 7.3,
-// 2048: 23.0 / 17.1 / 17.5, 16384: 152 / 131 / 120.  The bfloat16 kernel
+// Lanes per transform.  N = 4096 by batch, from measurements (binary16,
+// microseconds per launch for 256 / 128 / 64 lanes): batch 256: 5.2 / 5.7 /
+// 7.3, 2048: 23.0 / 17.1 / 17.5, 16384: 152 / 131 / 120.  The bfloat16 kernel
 // needs more registers (its twiddle product and rounding do not fuse), and
-// with one wave per transform it spills: it stops at two waves.
+// with one wave per transform it spills: it stops at two waves.  Other
+// lengths: two blocks of 32 butterflies per wave.
 template <class IO>
-hipError_t launch_mma(const void* in, void* out, const void* tw, int64_t batch, bool inverse,
-                      hipStream_t s) {
-  if (batch <= 512) return launch_mma_threads<256, IO>(in, out, tw, batch, inverse, s);
+hipError_t launch_mma(int64_t n, const void* in, void* out, const void* tw, int64_t batch,
+                      bool inverse, hipStream_t s) {
+  switch (n) {
+    case 512: return launch_mma_threads<512, 64, IO>(in, out, tw, batch, inverse, s);
+    case 1024: return launch_mma_threads<1024, 64, IO>(in, out, tw, batch, inverse, s);
+    case 2048: return launch_mma_threads<2048, 128, IO>(in, out, tw, batch, inverse, s);
+    case 8192: return launch_mma_threads<8192, 512, IO>(in, out, tw, batch, inverse, s);
+    case 16384: return launch_mma_threads<16384, 1024, IO>(in, out, tw, batch, inverse, s);
+    default: break;
+  }
+  if (batch <= 512) return launch_mma_threads<4096, 256, IO>(in, out, tw, batch, inverse, s);
   if constexpr (std::is_same<IO, IoF16>::value)
-    if (batch > 4096) return launch_mma_threads<64, IO>(in, out, tw, batch, inverse, s);
-  return launch_mma_threads<128, IO>(in, out, tw, batch, inverse, s);
+    if (batch > 4096) return launch_mma_threads<4096, 64, IO>(in, out, tw, batch, inverse, s);
+  return launch_mma_threads<4096, 128, IO>(in, out, tw, batch, inverse, s);
 }
 
 }  // namespace
 
-bool mma_supported(const SingleVariant& v) {
-  return v.n == kN && v.npass == 3 && v.radix[0] == 16 && v.radix[1] == 16 && v.radix[2] == 16;
+bool mma_supported(int64_t n) {
+  return n == 512 || n == 1024 || n == 2048 || n == 4096 || n == 8192 || n == 16384;
 }
 
-hipError_t launch_mma_f16(const void* in, void* out, const void* tw, int64_t batch, bool inverse,
-                          hipStream_t s) {
-  return launch_mma<IoF16>(in, out, tw, batch, inverse, s);
+const char* mma_table_variant(int64_t n) {
+  switch (n) {
+    case 512: return "n512_e16_b2_p4_r16.16.2";
+    case 1024: return "n1024_e16_b1_p4_r16.16.4";
+    case 2048: return "n2048_e16_b1_p4_r16.16.8";
+    case 4096: return "n4096_e16_b1_p4_r16.16.16";
+    case 8192: return "n8192_e32_b1_p4_r16.16.16.2";
+    case 16384: return "n16384_e16_b1_p4_r16.16.16.4";
+    default: return nullptr;
+  }
 }
 
-hipError_t launch_mma_bf16(const void* in, void* out, const void* tw, int64_t batch,
+hipError_t launch_mma_f16(int64_t n, const void* in, void* out, const void* tw, int64_t batch,
+                          bool inverse, hipStream_t s) {
+  return launch_mma<IoF16>(n, in, out, tw, batch, inverse, s);
+}
+
+hipError_t launch_mma_bf16(int64_t n, const void* in, void* out, const void* tw, int64_t batch,
                            bool inverse, hipStream_t s) {
-  return launch_mma<IoBF16>(in, out, tw, batch, inverse, s);
+  return launch_mma<IoBF16>(n, in, out, tw, batch, inverse, s);
 }
 
 }  // namespace stockfft

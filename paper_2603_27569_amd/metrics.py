@@ -92,14 +92,27 @@ def dft16_matrix_error(fmt):
     return float(np.linalg.norm(mr - m, 2) / 4.0)
 
 
-def mma_gate_factor(fmt, passes=3):
+def mma_passes(n):
+    """(radix-16 passes on the matrix cores, all passes) of the matrix-core
+    path at length n = 16^P RL (RL = 1, 2, 4 or 8: one more pass on the
+    vector ALUs when RL > 1)."""
+    p, m = 0, n
+    while m % 16 == 0 and m >= 16:
+        m //= 16
+        p += 1
+    return p, p + (1 if m > 1 else 0)
+
+
+def mma_gate_factor(fmt, passes=3, matrix_passes=None):
     """Error factor g (in units of u) for the matrix-core 16-bit path: the
-    operands of each of the `passes` radix-16 passes and the output are each
-    rounded once (relative RMS <= u / sqrt(3) each, independent, so
-    sqrt(passes + 1) u / sqrt(3) together), and every pass adds the rounded
-    matrix's error (linearly, as it is systematic)."""
+    inputs of each of the `passes` passes and the output are each rounded at
+    most once (relative RMS <= u / sqrt(3) each, independent, so
+    sqrt(passes + 1) u / sqrt(3) together), and every radix-16 pass
+    (`matrix_passes`, default all) adds the rounded matrix's error (linearly,
+    as it is systematic)."""
     u = STORAGE_UNIT_ROUNDOFF[fmt]
-    return float(np.sqrt((passes + 1) / 3.0) + passes * dft16_matrix_error(fmt) / u)
+    mp = passes if matrix_passes is None else matrix_passes
+    return float(np.sqrt((passes + 1) / 3.0) + mp * dft16_matrix_error(fmt) / u)
 
 
 def gate_storage(y, ref, x, fmt, mma=False):
@@ -109,14 +122,18 @@ def gate_storage(y, ref, x, fmt, mma=False):
     and about u / sqrt(3) in RMS, so: rel-RMS <= u, and per bin
     |y - X| <= u |X|max + 1e-5 ||x_b||_2 (the FP32 arithmetic's own share, as
     in the FP32 gate).  With mma=True (16-point DFTs on the matrix cores,
-    mma_gate_factor) the RMS bound is g u and the per-bin one 2 g u |X|max +
+    mma_gate_factor for the row length's passes) the RMS bound is g u and the
+    per-bin one 2 g u |X|max +
     1e-5 ||x_b||_2 (a bin's error is the largest of n samples where the RMS
     averages them).  Returns (ok, worst_rel_rms, median_rel_rms,
     worst_abs_ratio) with the abs ratio taken against that bound."""
     u = STORAGE_UNIT_ROUNDOFF[fmt]
-    g = mma_gate_factor(fmt) if mma else 1.0
     rel, mabs, xn = per_row_errors(y, ref, x)
     r = np.asarray(ref).reshape(rel.shape[0], -1)
+    g = 1.0
+    if mma:
+        p16, ptot = mma_passes(r.shape[1])
+        g = mma_gate_factor(fmt, ptot, p16)
     bound = (2.0 * g if mma else 1.0) * u * np.max(np.abs(r), axis=1) + 1e-5 * xn
     with np.errstate(divide="ignore", invalid="ignore"):
         ratio = np.where(bound > 0, mabs / bound, np.where(mabs == 0, 0.0, np.inf))

@@ -110,9 +110,12 @@ def test_lowp_errors():
 
 
 # ---------------------------------------------------------------- matrix cores
-# FFT_IO_C16_MMA / FFT_IO_BC16_MMA: N = 4096, the 16-point DFTs of the three
-# radix-16 passes as matrix-core products with 16-bit operands and FP32 sums,
-# gated by metrics.gate_storage(..., mma=True).
+# FFT_IO_C16_MMA / FFT_IO_BC16_MMA: N = 16^P RL from 512 to 16384, the 16-point
+# DFTs of the radix-16 passes as matrix-core products with 16-bit operands and
+# FP32 sums (then one radix-RL pass on the vector ALUs), gated by
+# metrics.gate_storage(..., mma=True).
+
+MMA_SIZES = [512, 1024, 2048, 4096, 8192, 16384]
 
 MMA_IO = {"f16": sf.FFT_IO_C16_MMA, "bf16": sf.FFT_IO_BC16_MMA}
 
@@ -127,37 +130,37 @@ def _run_io(plan, xt, io, out=None):
 
 @pytest.mark.parametrize("fmt", ["f16", "bf16"])
 @pytest.mark.parametrize("inverse", [False, True], ids=["forward", "backward"])
-@pytest.mark.parametrize("batch", [1, 9])
-def test_mma_matches_oracle(fmt, inverse, batch):
-    n = 4096
-    x = workloads.plain_normal(n, batch, seed=40 + batch)
+@pytest.mark.parametrize("n,batch", [(4096, 1), (4096, 9)] + [(m, 5) for m in MMA_SIZES if m != 4096])
+def test_mma_matches_oracle(fmt, inverse, n, batch):
+    x = workloads.plain_normal(n, batch, seed=40 + batch + n)
     stored, xv = workloads.to_storage(x, fmt)
     p = sf.Plan(n, batch, sf.FFT_BACKWARD if inverse else sf.FFT_FORWARD, sf.FFT_ALGO_SINGLE_PASS)
     y = _host(_run_io(p, _device(stored, fmt), MMA_IO[fmt]), fmt)
     p.close()
     ok, worst, med, ab = metrics.gate_storage(y, oracle.fft(xv, inverse=inverse), xv, fmt, mma=True)
     u = metrics.STORAGE_UNIT_ROUNDOFF[fmt]
-    print(f"mma {fmt} inverse={inverse} b={batch}: worst rel-RMS {worst / u:.3f} u, "
-          f"gate {metrics.mma_gate_factor(fmt):.3f} u, bin ratio {ab:.3f}", flush=True)
+    p16, ptot = metrics.mma_passes(n)
+    print(f"mma {fmt} n={n} inverse={inverse} b={batch}: worst rel-RMS {worst / u:.3f} u, "
+          f"gate {metrics.mma_gate_factor(fmt, ptot, p16):.3f} u, bin ratio {ab:.3f}", flush=True)
     assert ok, (worst / u, ab)
     assert med > 0.2 * u  # the path rounds; an exact result would mean it did not run
 
 
 @pytest.mark.parametrize("fmt", ["f16", "bf16"])
-def test_mma_every_radix16_variant_and_closed_forms(fmt):
-    # The kernel takes the plan's twiddle table; every N = 4096 variant with
-    # three radix-16 passes builds the same one.  Closed forms: a delta row
-    # gives all ones, a tone e^{2 pi i k0 n / N} gives N at bin k0 (within
-    # the gate).
-    n = 4096
+@pytest.mark.parametrize("n", [1024, 4096])
+def test_mma_any_plan_variant_and_closed_forms(fmt, n):
+    # The kernel runs on the plan's twiddle table when the plan's variant has
+    # its radix plan, else on a table of its own: every variant's plan gives
+    # the same answer.  Closed forms: a delta row gives all ones, a tone
+    # e^{2 pi i k0 n / N} gives N at bin k0 (within the gate).
     rows = np.zeros((3, n), dtype=np.complex128)
     rows[0, 0] = 1.0
-    rows[1] = np.exp(2j * np.pi * 37 * np.arange(n) / n) / 64.0  # N / 64 = 64 at bin 37
+    rows[1] = np.exp(2j * np.pi * 37 * np.arange(n) / n) / 64.0  # N / 64 at bin 37
     rows[2] = workloads.plain_normal(n, 1, seed=2)[0]
     stored, xv = workloads.to_storage(rows, fmt)
     ref = oracle.fft(xv)
     for v in SINGLE:
-        if v["n"] != n or v["radices"] != [16, 16, 16]:
+        if v["n"] != n:
             continue
         p = sf.Plan(n, 3, sf.FFT_FORWARD, sf.FFT_ALGO_SINGLE_PASS, v["name"])
         y = _host(_run_io(p, _device(stored, fmt), MMA_IO[fmt]), fmt)
@@ -215,12 +218,11 @@ def test_mma_lanes_per_transform_by_batch(fmt, batch):
 def test_mma_unsupported_plans():
     L = sf._lib.lib()
     vp = ctypes.c_void_p
-    buf = torch.zeros(8192 * 4, dtype=torch.float16, device=DEV)
+    buf = torch.zeros(65536 * 4, dtype=torch.float16, device=DEV)
     base = buf.data_ptr()
-    radix8 = [v["name"] for v in SINGLE if v["n"] == 4096 and v["radices"] != [16, 16, 16]][0]
-    for args in ((2048, 2, sf.FFT_FORWARD, sf.FFT_ALGO_SINGLE_PASS),
-                 (4096, 1, sf.FFT_FORWARD, sf.FFT_ALGO_SINGLE_PASS, radix8),
-                 (8192, 1, sf.FFT_FORWARD, sf.FFT_ALGO_FOUR_STEP)):
+    for args in ((256, 2, sf.FFT_FORWARD, sf.FFT_ALGO_SINGLE_PASS),
+                 (8192, 1, sf.FFT_FORWARD, sf.FFT_ALGO_FOUR_STEP),
+                 (65536, 1, sf.FFT_FORWARD)):
         p = sf.Plan(*args)
         for io in (sf.FFT_IO_C16_MMA, sf.FFT_IO_BC16_MMA):
             assert L.fft_exec_io(vp(p.handle), vp(base), vp(base), io, None) == \

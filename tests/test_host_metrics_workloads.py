@@ -185,7 +185,10 @@ def test_mma_gate_factor():
     # binary16: cos(pi / 8), cos(pi / 4), cos(3 pi / 8) round by 5.6e-5, 1.1e-4
     # and 3.0e-4 relative, giving 0.258 u per pass
     assert metrics.dft16_matrix_error("f16") / 2.0 ** -11 == pytest.approx(0.2581, abs=1e-3)
-    x = workloads.plain_normal(256, 4, seed=3)
+    # pass counts: radix-16 passes on the matrix cores, then one smaller radix
+    assert [metrics.mma_passes(n) for n in (512, 1024, 2048, 4096, 8192, 16384)] == \
+        [(2, 3), (2, 3), (2, 3), (3, 3), (3, 4), (3, 4)]
+    x = workloads.plain_normal(4096, 4, seed=3)
     stored, v = workloads.to_storage(x, "f16")
     ref = np.fft.fft(v)
     u = 2.0 ** -11
