@@ -279,15 +279,18 @@ hipError_t launch_mma_threads(const void* in, void* out, const void* tw, int64_t
 // 7.3, 2048: 23.0 / 17.1 / 17.5, 16384: 152 / 131 / 120.  The bfloat16 kernel
 // needs more registers (its twiddle product and rounding do not fuse), and
 // with one wave per transform it spills: it stops at two waves.  Other
-// lengths: two blocks of 32 butterflies per wave.
+// lengths (measured at about 64 MiB per launch): 512 and 1024 one wave,
+// 2048 one wave of four blocks (17.8 against 23.1 us with two waves at
+// 2048 x 4096), 8192 four blocks per wave (23.1 against 24.3 with two),
+// 16384 two blocks per wave (28.8 against 29.4 with four).
 template <class IO>
 hipError_t launch_mma(int64_t n, const void* in, void* out, const void* tw, int64_t batch,
                       bool inverse, hipStream_t s) {
   switch (n) {
     case 512: return launch_mma_threads<512, 64, IO>(in, out, tw, batch, inverse, s);
     case 1024: return launch_mma_threads<1024, 64, IO>(in, out, tw, batch, inverse, s);
-    case 2048: return launch_mma_threads<2048, 128, IO>(in, out, tw, batch, inverse, s);
-    case 8192: return launch_mma_threads<8192, 512, IO>(in, out, tw, batch, inverse, s);
+    case 2048: return launch_mma_threads<2048, 64, IO>(in, out, tw, batch, inverse, s);
+    case 8192: return launch_mma_threads<8192, 256, IO>(in, out, tw, batch, inverse, s);
     case 16384: return launch_mma_threads<16384, 1024, IO>(in, out, tw, batch, inverse, s);
     default: break;
   }
