@@ -465,6 +465,7 @@ struct stockfft_plan_s {
   size_t ws_bytes = 0;
   unsigned* d_counters = nullptr;            // fused loss total (kept zeroed)
   void* d_tw_mma = nullptr;                  // matrix-core table when it differs from sv's
+  const void* tw_mma = nullptr;              // the matrix-core table (d_tw or d_tw_mma)
   const SingleVariant* sv_filter = nullptr;  // matched-filter kernel shape (forward plans)
   void* d_tw_filter = nullptr;               // its twiddles when it differs from sv
 };
@@ -568,6 +569,7 @@ extern "C" int fft_plan_config(fft_plan_t* plan, int64_t n, int64_t batch, int d
       build_stockham_twiddles(*mv, mtw);
       rc = upload(mtw, &p->d_tw_mma);
     }
+    if (mv) p->tw_mma = same ? p->d_tw : p->d_tw_mma;
   }
   if (!rc && !fs && direction == FFT_FORWARD) {
     // The matched filter's kernel: the named variant, else its own tuned choice.
@@ -629,7 +631,7 @@ extern "C" int fft_exec_io(fft_plan_t plan, const void* in, void* out, int io, v
   const bool mma = io == FFT_IO_C16_MMA || io == FFT_IO_BC16_MMA;
   if (io != FFT_IO_C16 && io != FFT_IO_BC16 && !mma) return FFT_INVALID_ARGUMENT;
   if (plan->algorithm != FFT_ALGO_SINGLE_PASS) return FFT_UNSUPPORTED;
-  if (mma && !mma_supported(plan->n)) return FFT_UNSUPPORTED;
+  if (mma && !plan->tw_mma) return FFT_UNSUPPORTED;
   if (!in || !out) return FFT_INVALID_POINTER;
   if (((uintptr_t)in & 3u) || ((uintptr_t)out & 3u)) return FFT_MISALIGNED;
   const size_t bytes = (size_t)plan->n * (size_t)plan->batch * 4;
@@ -640,9 +642,8 @@ extern "C" int fft_exec_io(fft_plan_t plan, const void* in, void* out, int io, v
   const bool inv = plan->direction == FFT_BACKWARD;
   hipError_t e;
   if (mma) {
-    const void* tw = plan->d_tw_mma ? plan->d_tw_mma : plan->d_tw;
-    e = (io == FFT_IO_C16_MMA ? launch_mma_f16 : launch_mma_bf16)(plan->n, in, out, tw, plan->batch,
-                                                                  inv, (hipStream_t)stream);
+    e = (io == FFT_IO_C16_MMA ? launch_mma_f16 : launch_mma_bf16)(
+        plan->n, in, out, plan->tw_mma, plan->batch, inv, (hipStream_t)stream);
   } else {
     e = fn(in, out, plan->d_tw, plan->batch, inv, (hipStream_t)stream);
   }
