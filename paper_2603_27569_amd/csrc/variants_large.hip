@@ -15,4 +15,8 @@ STOCKFFT_VARIANT_GROUP(variants_large,
   make_variant<Shape<16384, 32, 1, 4, 16, 16, 16, 4>>("n16384_e32_b1_p4_r16.16.16.4"),
   // Two-round exchanges: half the LDS, two (16384) or four (8192) workgroups per CU.
   make_variant<ShapeX<2, false, 4, 16384, 32, 1, 4, 16, 16, 16, 4>>("n16384_e32_c2_b1_p4_r16.16.16.4"),
-  make_variant<ShapeX<2, false, 4, 8192, 32, 1, 4, 16, 16, 16, 2>>("n8192_e32_c2_b1_p4_r16.16.16.2"))
+  make_variant<ShapeX<2, false, 4, 8192, 32, 1, 4, 16, 16, 16, 2>>("n8192_e32_c2_b1_p4_r16.16.16.2"),
+  // Four-round exchanges (a quarter of the LDS): radix 8 before the last
+  // pass, so that every exchange splits into four rounds.
+  make_variant<ShapeX<4, false, 4, 16384, 32, 1, 4, 8, 8, 8, 8, 4>>("n16384_e32_c4_b1_p4_r8.8.8.8.4"),
+  make_variant<ShapeX<4, false, 4, 8192, 32, 1, 4, 8, 8, 8, 16>>("n8192_e32_c4_b1_p4_r8.8.8.16"))
