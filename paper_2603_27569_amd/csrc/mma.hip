@@ -124,26 +124,28 @@ __device__ __forceinline__ V gather_halves(const uint32_t (&d)[8], bool hi) {
   return __builtin_bit_cast(V, w);
 }
 
-// THREADS lanes per transform, each wave taking kBlocks blocks of 32
-// butterflies: fewer waves mean more independent products per wave and no
-// barrier waits across waves, more waves fewer registers and more transforms
-// in flight.  One wave per transform is held to two waves per SIMD.
-template <int N, int THREADS, bool INV, class IO>
+// TPWG transforms per workgroup of THREADS lanes, each wave taking kBlocks
+// blocks of 32 butterflies (of one transform or, for short transforms,
+// several): fewer waves per block of work mean more independent products per
+// wave and no barrier waits across waves, more waves fewer registers and more
+// transforms in flight.  One wave per workgroup is held to two waves per SIMD.
+template <int N, int THREADS, int TPWG, bool INV, class IO>
 __global__ __launch_bounds__(THREADS, THREADS == 64 ? 2 : 1) void k_stockham_mma(
     const uint32_t* in, uint32_t* out, const c32* tw, int64_t rows) {
   using M = MmaPlan<N>;
   constexpr int NB = M::NB;
-  constexpr int kBlocks = NB / 32 / (THREADS / 64);
-  static_assert(kBlocks >= 1 && kBlocks * 32 * (THREADS / 64) == NB, "lanes per transform");
+  constexpr int BPT = NB / 32;  // blocks per transform
+  constexpr int kBlocks = TPWG * BPT / (THREADS / 64);
+  static_assert(kBlocks >= 1 && kBlocks * (THREADS / 64) == TPWG * BPT, "lanes per transform");
   using Ops = MmaOps<IO>;
   using V = typename Ops::V;
-  __shared__ alignas(16) uint32_t lds[M::LDS];  // 16-bit pairs, one pad per 16
+  __shared__ alignas(16) uint32_t lds[TPWG * M::LDS];  // 16-bit pairs, one pad per 16
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int jl = lane & 31;
   const int h = lane >> 5;
-  const int64_t row = blockIdx.x;
-  if (row >= rows) return;  // whole workgroup, before any barrier
+  const int64_t row0 = (int64_t)blockIdx.x * TPWG;
+  if (row0 >= rows) return;  // whole workgroup, before any barrier
 
   // The DFT matrix as the A operand: row jl, columns 8h + e (first product,
   // real legs) and 16 + 8h + e (second product, imaginary legs).
@@ -159,21 +161,30 @@ __global__ __launch_bounds__(THREADS, THREADS == 64 ? 2 : 1) void k_stockham_mma
     a_im = Ops::pack(im);
   }
 
-  int j[kBlocks];
+  // Block b of this wave: transform tr[b] of the workgroup, butterfly j[b];
+  // rows past the batch (a last, partial workgroup) compute on zeros and
+  // store nothing.
+  int j[kBlocks], tr[kBlocks];
+  bool live[kBlocks];
 #pragma unroll
-  for (int b = 0; b < kBlocks; ++b) j[b] = 32 * ((tid >> 6) * kBlocks + b) + jl;  // butterfly
+  for (int b = 0; b < kBlocks; ++b) {
+    const int g = (tid >> 6) * kBlocks + b;
+    tr[b] = TPWG > 1 ? g / BPT : 0;
+    j[b] = 32 * (g - tr[b] * BPT) + jl;
+    live[b] = TPWG == 1 || row0 + tr[b] < rows;  // one transform: row0 < rows
+  }
 
   // Legs 8h + e of each butterfly as stored pairs: the first pass takes its
   // operands straight from HBM, the later ones from LDS, where the writer has
   // already applied their twiddles and rounded.
   uint32_t d[kBlocks][8];
-  const uint32_t* src = in + row * N;
-  uint32_t* dst = out + row * N;
 #pragma unroll
-  for (int b = 0; b < kBlocks; ++b)
+  for (int b = 0; b < kBlocks; ++b) {
+    const uint32_t* src = in + (row0 + tr[b]) * N;
 #pragma unroll
     for (int e = 0; e < 8; ++e)
-      d[b][e] = __builtin_nontemporal_load(src + j[b] + (8 * h + e) * NB);
+      d[b][e] = live[b] ? __builtin_nontemporal_load(src + j[b] + (8 * h + e) * NB) : 0u;
+  }
 
 #pragma unroll
   for (int p = 0; p < M::P; ++p) {
@@ -209,11 +220,14 @@ __global__ __launch_bounds__(THREADS, THREADS == 64 ? 2 : 1) void k_stockham_mma
     if (last16 && M::RL == 1) {
       // Last pass (Ns = N / 16): bin k of butterfly j is element j + k N / 16.
 #pragma unroll
-      for (int b = 0; b < kBlocks; ++b)
+      for (int b = 0; b < kBlocks; ++b) {
+        if (!live[b]) continue;
+        uint32_t* dst = out + (row0 + tr[b]) * N;
 #pragma unroll
         for (int q = 0; q < 8; ++q)
           __builtin_nontemporal_store(IO::store(c32{acc[b][q], acc[b][8 + q]}),
                                       dst + j[b] + out_bin(q, h) * NB);
+      }
       return;
     }
     // With one pad element per 16 the padded slots are affine in k: pidx(x) =
@@ -222,7 +236,8 @@ __global__ __launch_bounds__(THREADS, THREADS == 64 ? 2 : 1) void k_stockham_mma
     const int step = p == 0 ? 1 : 17 * ns / 16;
 #pragma unroll
     for (int b = 0; b < kBlocks; ++b) {
-      uint32_t* wr = lds + pidx((j[b] / ns) * ns * 16 + (j[b] & (ns - 1))) + step * 4 * h;
+      uint32_t* wr = lds + tr[b] * M::LDS + pidx((j[b] / ns) * ns * 16 + (j[b] & (ns - 1))) +
+                     step * 4 * h;
 #pragma unroll
       for (int q = 0; q < 8; ++q)
         wr[step * (q + (q & 4))] = IO::store(ctw<INV>(c32{acc[b][q], acc[b][8 + q]}, wn[b][q]));
@@ -232,7 +247,7 @@ __global__ __launch_bounds__(THREADS, THREADS == 64 ? 2 : 1) void k_stockham_mma
       // pidx(j + r N / 16) = pidx(j) + 17 N / 256 r.
 #pragma unroll
       for (int b = 0; b < kBlocks; ++b) {
-        const uint32_t* rd = lds + pidx(j[b]) + (17 * NB / 16) * 8 * h;
+        const uint32_t* rd = lds + tr[b] * M::LDS + pidx(j[b]) + (17 * NB / 16) * 8 * h;
 #pragma unroll
         for (int e = 0; e < 8; ++e) d[b][e] = rd[(17 * NB / 16) * e];
       }
@@ -245,31 +260,35 @@ __global__ __launch_bounds__(THREADS, THREADS == 64 ? 2 : 1) void k_stockham_mma
     // element j + k N / RL.
     constexpr int R = M::RL, NL = M::NL;
 #pragma unroll
-    for (int jb = tid; jb < NL; jb += THREADS) {
+    for (int i = tid; i < TPWG * NL; i += THREADS) {
+      const int t = i / NL, jb = i - t * NL;
+      if (row0 + t >= rows) continue;
+      const uint32_t* rd = lds + t * M::LDS;
       c32 v[R];
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[r] = IO::load(lds[pidx(jb + r * NL)]);
+      for (int r = 0; r < R; ++r) v[r] = IO::load(rd[pidx(jb + r * NL)]);
       Dft<R, INV>::run(v);
+      uint32_t* dst = out + (row0 + t) * N;
 #pragma unroll
       for (int k = 0; k < R; ++k) __builtin_nontemporal_store(IO::store(v[k]), dst + jb + k * NL);
     }
   }
 }
 
-template <int N, int THREADS, class IO>
+template <int N, int THREADS, class IO, int TPWG = 1>
 hipError_t launch_mma_threads(const void* in, void* out, const void* tw, int64_t batch,
                               bool inverse, hipStream_t s) {
-  const int64_t cap = max_groups_per_launch();
+  const int64_t cap = max_groups_per_launch() * TPWG;  // rows per launch
   for (int64_t r0 = 0; r0 < batch; r0 += cap) {
-    const int64_t g = batch - r0 < cap ? batch - r0 : cap;
+    const int64_t rows = batch - r0 < cap ? batch - r0 : cap;
     const uint32_t* ip = static_cast<const uint32_t*>(in) + r0 * N;
     uint32_t* op = static_cast<uint32_t*>(out) + r0 * N;
     const c32* twp = static_cast<const c32*>(tw);
-    const dim3 grid((unsigned)g), block(THREADS);
+    const dim3 grid((unsigned)((rows + TPWG - 1) / TPWG)), block(THREADS);
     if (inverse)
-      k_stockham_mma<N, THREADS, true, IO><<<grid, block, 0, s>>>(ip, op, twp, batch - r0);
+      k_stockham_mma<N, THREADS, TPWG, true, IO><<<grid, block, 0, s>>>(ip, op, twp, rows);
     else
-      k_stockham_mma<N, THREADS, false, IO><<<grid, block, 0, s>>>(ip, op, twp, batch - r0);
+      k_stockham_mma<N, THREADS, TPWG, false, IO><<<grid, block, 0, s>>>(ip, op, twp, rows);
   }
   return hipGetLastError();
 }
@@ -279,23 +298,26 @@ hipError_t launch_mma_threads(const void* in, void* out, const void* tw, int64_t
 // 7.3, 2048: 23.0 / 17.1 / 17.5, 16384: 152 / 131 / 120.  The bfloat16 kernel
 // needs more registers (its twiddle product and rounding do not fuse), and
 // with one wave per transform it spills: it stops at two waves.  Other
-// lengths (measured at about 64 MiB per launch): 512 and 1024 one wave,
-// 2048 one wave of four blocks (17.8 against 23.1 us with two waves at
-// 2048 x 4096), 8192 four blocks per wave (23.1 against 24.3 with two),
-// 16384 two blocks per wave (28.8 against 29.4 with four).
+// lengths (measured at about 64 MiB per launch): up to 2048 one wave per
+// workgroup with four blocks of 32 butterflies (eight spill), so 512 and 1024
+// take several transforms per workgroup (2048: 17.8 against 23.1 us with two
+// waves of two blocks at 2048 x 4096), 8192
+// four blocks per wave (23.1 against 24.3 with two), 16384 two blocks per
+// wave (28.8 against 29.4 with four).
 template <class IO>
 hipError_t launch_mma(int64_t n, const void* in, void* out, const void* tw, int64_t batch,
                       bool inverse, hipStream_t s) {
+  constexpr bool f16 = std::is_same<IO, IoF16>::value;
   switch (n) {
-    case 512: return launch_mma_threads<512, 64, IO>(in, out, tw, batch, inverse, s);
-    case 1024: return launch_mma_threads<1024, 64, IO>(in, out, tw, batch, inverse, s);
-    case 2048: return launch_mma_threads<2048, 64, IO>(in, out, tw, batch, inverse, s);
+    case 512: return launch_mma_threads<512, 64, IO, 4>(in, out, tw, batch, inverse, s);
+    case 1024: return launch_mma_threads<1024, 64, IO, 2>(in, out, tw, batch, inverse, s);
+    case 2048: return launch_mma_threads<2048, 64, IO, 1>(in, out, tw, batch, inverse, s);
     case 8192: return launch_mma_threads<8192, 256, IO>(in, out, tw, batch, inverse, s);
     case 16384: return launch_mma_threads<16384, 1024, IO>(in, out, tw, batch, inverse, s);
     default: break;
   }
   if (batch <= 512) return launch_mma_threads<4096, 256, IO>(in, out, tw, batch, inverse, s);
-  if constexpr (std::is_same<IO, IoF16>::value)
+  if constexpr (f16)
     if (batch > 4096) return launch_mma_threads<4096, 64, IO>(in, out, tw, batch, inverse, s);
   return launch_mma_threads<4096, 128, IO>(in, out, tw, batch, inverse, s);
 }
