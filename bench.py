@@ -206,6 +206,9 @@ def main():
     t_copy = T.run(lambda i: cp_dst[i % K].copy_(cp_src[i % K]), args.steps, args.warmup) / args.steps
     refs["device_copy_same_bytes"] = {"us": round(t_copy * 1e6, 3),
                                       "GBs": round(bytes_launch / t_copy / 1e9, 1)}
+    # The same launch-bound shape as a plain device copy: how close the FFT
+    # comes to moving its bytes with no arithmetic at all.
+    roofline["frac_of_same_size_copy"] = round(t_copy / t_kernel, 4)
     tiny = torch.zeros(1, device=dev)
     t_min = T.run(lambda i: tiny.add_(1.0), args.steps, args.warmup) / args.steps
     refs["minimal_kernel_us"] = round(t_min * 1e6, 3)
