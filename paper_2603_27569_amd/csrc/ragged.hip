@@ -83,17 +83,18 @@ const ShapeInfo kShapes[kNumShapes] = {
     info<A16384>("ragged_n16384_e32c2_r8"), info<B16384>("ragged_n16384_e32c2_r16"),
 };
 
-// Duration of one full task of each shape in microseconds, two workgroups per
-// CU and every CU busy (median over about a thousand tasks of that shape on
-// an MI355X).  The list schedule uses them as task costs.
+// Duration of one full task of each shape in microseconds on an MI355X: a
+// batch of one length and shape, 4096 full tasks over 512 workgroups (two per
+// CU, every CU busy), kernel time x 512 / 4096.  The list schedule uses them
+// as task costs; only their ratios matter to it.
 constexpr float kShapeTaskUs[kNumShapes] = {
-    16.80f, 6.88f,   // 256
-    18.34f, 8.26f,   // 512
-    20.18f, 8.92f,   // 1024
-    19.00f, 9.76f,   // 2048
-    19.56f, 9.88f,   // 4096
-    21.76f, 11.64f,  // 8192
-    26.16f, 23.72f,  // 16384
+    29.22f, 13.76f,  // 256
+    29.60f, 14.43f,  // 512
+    29.07f, 14.09f,  // 1024
+    28.39f, 14.41f,  // 2048
+    28.27f, 14.77f,  // 4096
+    31.17f, 16.07f,  // 8192
+    31.26f, 31.47f,  // 16384
 };
 
 struct Task {
