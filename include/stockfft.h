@@ -75,7 +75,9 @@ enum fft_status {
  *   n          transform length, a power of two in [256, 1048576].  Up to
  *              16384 a whole transform fits in one CU's LDS and a single-pass
  *              kernel is available; above it only the four-step (eq. (3),
- *              Section IV-D rule 3: N1 x 16384 with N1 <= 64) exists.
+ *              Section IV-D rule 3) exists: N1 x 16384 with N1 <= 64, or
+ *              N1 x N2 with N1, N2 in {256, 512, 1024}, whichever the tuned
+ *              table names for (n, batch).
  *   batch      number of rows, >= 1.
  *   direction  FFT_FORWARD or FFT_BACKWARD.
  * The plan owns device memory for its twiddle tables (computed in FP64 on
@@ -221,7 +223,7 @@ int fft_exec_ragged(fft_ragged_plan_t plan, const void *in, void *out, void *str
  * fft_exec_ragged_direct -- the same persistent kernel as fft_exec_ragged,
  * started with a plain kernel launch instead of the plan's graph (for callers
  * that capture it into a graph of their own, or that want the lower launch
- * cost: about 4 us less per call on ROCm 7 with one MI355X).  Same arguments,
+ * cost: about 5 us less per call on ROCm 7 with one MI355X).  Same arguments,
  * results and errors as fft_exec_ragged; the plan's graph is not touched.
  */
 int fft_exec_ragged_direct(fft_ragged_plan_t plan, const void *in, void *out, void *stream);
@@ -246,7 +248,7 @@ int fft_destroy_ragged(fft_ragged_plan_t plan);
  * fft_ragged_shapes: comma-separated shape names for length n, into buf.
  * fft_tune_set_ragged: use `shape` for length n in ragged plans made later.
  * fft_tune_query_ragged: the shape ragged plans would use for n, into buf.
- * fft_tune_clear_ragged: back to the built-in shapes (radix 16 everywhere).
+ * fft_tune_clear_ragged: back to the built-in shapes (the tuned MI355X choice).
  * Host only.  Errors: FFT_INVALID_POINTER, FFT_INVALID_SIZE,
  * FFT_INVALID_ARGUMENT (unknown shape, shape for another length, small buffer).
  */
