@@ -262,7 +262,8 @@ int fft_tune_clear_ragged(void);
  * autotuner: {"arch": "gfx950", "entries": [{"n": N, "batch_min": a,
  * "batch_max": b, "variant": "<name>"}, ...]}.  A missing or unreadable
  * file, or one tuned for another architecture, leaves the built-in table in
- * force and returns FFT_INVALID_ARGUMENT.  Entries naming unknown variants
+ * force and returns FFT_INVALID_ARGUMENT; so does a file whose "cus" differs
+ * from the device's compute-unit count.  Entries naming unknown variants
  * are skipped.  fft_tune_set adds one entry; fft_tune_clear drops all.
  * Later entries win.  Plans made before a change keep their variant.
  */

@@ -357,15 +357,23 @@ int load_tune_file_locked(const char* path) {
     std::fprintf(stderr, "stockfft: tune file %s is not valid JSON; ignored\n", path);
     return FFT_INVALID_ARGUMENT;
   }
+  // A file tuned for another architecture, or on another CU count (a
+  // partitioned GPU exposes fewer CUs per device), is stale for this device.
   const json::Value* arch = doc.get("arch");
-  if (arch && arch->kind == json::Value::String) {
-    int count = 0, dev = 0;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceCount(&count) == hipSuccess && count > 0 && hipGetDevice(&dev) == hipSuccess &&
-        hipGetDeviceProperties(&prop, dev) == hipSuccess &&
+  const json::Value* cus = doc.get("cus");
+  int count = 0, dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceCount(&count) == hipSuccess && count > 0 && hipGetDevice(&dev) == hipSuccess &&
+      hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+    if (arch && arch->kind == json::Value::String &&
         std::strncmp(prop.gcnArchName, arch->str.c_str(), arch->str.size()) != 0) {
       std::fprintf(stderr, "stockfft: tune file %s is for %s, device is %s; ignored\n", path,
                    arch->str.c_str(), prop.gcnArchName);
+      return FFT_INVALID_ARGUMENT;
+    }
+    if (cus && cus->kind == json::Value::Number && (int64_t)cus->num != prop.multiProcessorCount) {
+      std::fprintf(stderr, "stockfft: tune file %s was tuned on %lld CUs, device has %d; ignored\n",
+                   path, (long long)cus->num, prop.multiProcessorCount);
       return FFT_INVALID_ARGUMENT;
     }
   }

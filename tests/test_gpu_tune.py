@@ -54,3 +54,30 @@ def test_ragged_shape_tuner():
     for o in out:
         assert o["shape"] in sf.fft_ragged_shapes(o["n"])
     assert sf.fft_tune_query_ragged(4096) == before  # the tuner leaves no state behind
+
+
+def test_stale_tune_files_are_ignored(tmp_path):
+    """A file tuned for another architecture or on another CU count leaves the
+    table as it was; a file for this device is applied."""
+    props = torch.cuda.get_device_properties(0)
+    arch = props.gcnArchName.split(":")[0]
+    cus = props.multi_processor_count
+    sf.fft_tune_clear()
+    try:
+        before = sf.fft_tune_query(2048, 5)
+        other = next(v["name"] for v in sf.variants()
+                     if v["kind"] == "single" and v["n"] == 2048 and v["name"] != before)
+        entries = [{"n": 2048, "batch_min": 1, "batch_max": 10 ** 9, "variant": other}]
+        path = tmp_path / "tune.json"
+        for doc in ({"arch": "gfx942", "cus": cus, "entries": entries},
+                    {"arch": arch, "cus": cus + 1, "entries": entries},
+                    {"arch": arch, "cus": cus // 4, "entries": entries}):
+            path.write_text(json.dumps(doc))
+            with pytest.raises(sf.StockfftError):
+                sf.fft_tune_load(str(path))
+            assert sf.fft_tune_query(2048, 5) == before
+        path.write_text(json.dumps({"arch": arch, "cus": cus, "entries": entries}))
+        sf.fft_tune_load(str(path))
+        assert sf.fft_tune_query(2048, 5) == other
+    finally:
+        sf.fft_tune_clear()
