@@ -234,7 +234,8 @@ const BuiltinEntry kBuiltin[] = {
     {8192, 513, INT64_MAX, "n8192_e32_c2_b1_p4_r16.16.16.2"},
     {16384, 1, 64, "fs16384_8x2048"},
     {16384, 65, 512, "n16384_e16_b1_p4_r16.16.16.4"},
-    {16384, 513, INT64_MAX, "n16384_e32_c2_b1_p4_r16.16.16.4"},
+    {16384, 513, 4096, "n16384_e16_c2_b1_p4_r8.8.8.8.4"},
+    {16384, 4097, INT64_MAX, "n16384_e32_c2_b1_p4_r16.16.16.4"},
     {32768, 1, INT64_MAX, "fs32768_2x16384"},
     {65536, 1, 64, "fs65536_tile256x256"},
     {65536, 65, INT64_MAX, "fs65536_4x16384"},

@@ -19,4 +19,8 @@ STOCKFFT_VARIANT_GROUP(variants_large,
   // Four-round exchanges (a quarter of the LDS): radix 8 before the last
   // pass, so that every exchange splits into four rounds.
   make_variant<ShapeX<4, false, 4, 16384, 32, 1, 4, 8, 8, 8, 8, 4>>("n16384_e32_c4_b1_p4_r8.8.8.8.4"),
-  make_variant<ShapeX<4, false, 4, 8192, 32, 1, 4, 8, 8, 8, 16>>("n8192_e32_c4_b1_p4_r8.8.8.16"))
+  make_variant<ShapeX<4, false, 4, 8192, 32, 1, 4, 8, 8, 8, 16>>("n8192_e32_c4_b1_p4_r8.8.8.16"),
+  // Sixteen values per lane with two-round exchanges: radix 8 leaves two
+  // butterflies per lane per pass, so each round takes one, and the body fits
+  // 64 VGPRs; two 1024-lane workgroups (32 waves) then share a CU.
+  make_variant<ShapeX<2, false, 8, 16384, 16, 1, 4, 8, 8, 8, 8, 4>>("n16384_e16_c2_b1_p4_r8.8.8.8.4"))
