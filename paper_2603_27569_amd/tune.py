@@ -41,7 +41,7 @@ SIZES = (256, 512, 1024, 2048, 4096, 8192, 16384)
 # single-pass); the timed batch is capped by MAX_BYTES per buffer.
 SIZES_LARGE = tuple(1 << e for e in range(15, 21))
 # Batch buckets: (batch_min, batch_max, representative batch timed).
-BUCKETS = ((1, 64, 32), (65, 512, 256), (513, 4096, 2048), (4097, 2 ** 62, 16384))
+BUCKETS = ((1, 64, 32), (65, 512, 256), (513, 1536, 1024), (1537, 4096, 2048), (4097, 2 ** 62, 16384))
 RING_BYTES = 1 << 30
 MAX_BYTES = 2 << 30  # cap on one timed buffer
 
