@@ -225,11 +225,13 @@ const BuiltinEntry kBuiltin[] = {
     {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4"},
     {1024, 65, INT64_MAX, "n1024_e16_b1_p4_r16.16.4"},
     {2048, 1, 512, "n2048_e8_b1_p4_r8.8.8.4"},
-    {2048, 513, INT64_MAX, "n2048_e16_b1_p4_r16.16.8"},
+    {2048, 513, 1536, "n2048_e16_b1_p4_r16.16.8"},
+    {2048, 1537, 4096, "n2048_e32_c2_b2_p4_r16.16.8"},
+    {2048, 4097, INT64_MAX, "n2048_e32_c2_b1_p4_r16.16.8"},
     {4096, 1, 64, "n4096_e16_b1_p5_r16.16.16"},
     {4096, 65, 512, "n4096_e16_b1_px_r16.16.16_db"},
-    {4096, 513, 1536, "n4096_e32_b1_p4_r16.16.16"},
-    {4096, 1537, INT64_MAX, "n4096_e32_b2_p4_r16.16.16"},
+    {4096, 513, 4096, "n4096_e32_c2_b1_p4_r16.16.16"},
+    {4096, 4097, INT64_MAX, "n4096_e32_b1_p4_r16.16.16"},
     {8192, 1, 64, "fs8192_2x4096"},
     {8192, 65, 512, "n8192_e32_b1_p4_r16.16.16.2"},
     {8192, 513, INT64_MAX, "n8192_e32_c2_b1_p4_r16.16.16.2"},
@@ -262,8 +264,8 @@ const BuiltinEntry kBuiltinFilter[] = {
     {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4"},
     {1024, 65, 1536, "n1024_e8_b2_p4_r8.8.8.2"},
     {1024, 1537, INT64_MAX, "n1024_e16_b1_p4_r16.16.4"},
-    {2048, 1, 512, "n2048_e8_b1_p4_r8.8.8.4"},
-    {2048, 513, INT64_MAX, "n2048_e16_b1_p4_r16.16.8"},
+    {2048, 1, 1536, "n2048_e8_b1_p4_r8.8.8.4"},
+    {2048, 1537, INT64_MAX, "n2048_e16_b1_p4_r16.16.8"},
     {4096, 1, 64, "n4096_e8_b1_p4_r8.8.8.8"},
     {4096, 65, 512, "n4096_e16_b1_px_r16.16.16_db"},
     {4096, 513, 1536, "n4096_e16_b1_px_r16.16.16_tall"},

@@ -4,6 +4,7 @@
 #include "variant_maker.hpp"
 
 using stockfft::Shape;
+using stockfft::ShapeX;
 using stockfft::make_variant;
 
 STOCKFFT_VARIANT_GROUP(variants_4096,
@@ -19,4 +20,7 @@ STOCKFFT_VARIANT_GROUP(variants_4096,
   make_variant<DoubleBuffered<Shape<4096, 16, 1, 5, 16, 16, 16>>>("n4096_e16_b1_p5_r16.16.16_db"),
   make_variant<DoubleBuffered<Shape<4096, 16, 1, -1, 16, 16, 16>>>("n4096_e16_b1_px_r16.16.16_db"),
   make_variant<Shape<4096, 32, 1, 4, 16, 16, 16>>("n4096_e32_b1_p4_r16.16.16"),
-  make_variant<Shape<4096, 32, 2, 4, 16, 16, 16>>("n4096_e32_b2_p4_r16.16.16"))
+  make_variant<Shape<4096, 32, 2, 4, 16, 16, 16>>("n4096_e32_b2_p4_r16.16.16"),
+  // Two-round exchanges: half the LDS (17 KiB), so occupancy is set by the
+  // registers (at most 128: four waves per SIMD) rather than by the LDS.
+  make_variant<ShapeX<2, false, 4, 4096, 32, 1, 4, 16, 16, 16>>("n4096_e32_c2_b1_p4_r16.16.16"))

@@ -4,6 +4,7 @@
 #include "variant_maker.hpp"
 
 using stockfft::Shape;
+using stockfft::ShapeX;
 using stockfft::make_variant;
 
 STOCKFFT_VARIANT_GROUP(variants_small,
@@ -22,4 +23,8 @@ STOCKFFT_VARIANT_GROUP(variants_small,
   make_variant<Shape<2048, 4, 1, 4, 4, 4, 4, 4, 4, 2>>("n2048_e4_b1_p4_r4.4.4.4.4.2"),
   make_variant<Shape<2048, 8, 1, 4, 8, 8, 8, 4>>("n2048_e8_b1_p4_r8.8.8.4"),
   make_variant<Shape<2048, 16, 2, 4, 16, 16, 8>>("n2048_e16_b2_p4_r16.16.8"),
-  make_variant<Shape<2048, 16, 1, 4, 16, 16, 8>>("n2048_e16_b1_p4_r16.16.8"))
+  make_variant<Shape<2048, 16, 1, 4, 16, 16, 8>>("n2048_e16_b1_p4_r16.16.8"),
+  // Two-round exchanges (half the LDS), one wave per transform, at most 128
+  // VGPRs: occupancy set by the registers rather than by the LDS.
+  make_variant<ShapeX<2, false, 4, 2048, 32, 1, 4, 16, 16, 8>>("n2048_e32_c2_b1_p4_r16.16.8"),
+  make_variant<ShapeX<2, false, 4, 2048, 32, 2, 4, 16, 16, 8>>("n2048_e32_c2_b2_p4_r16.16.8"))
