@@ -154,7 +154,10 @@ int fft_destroy(fft_plan_t plan);
  * fft_exec_spectral_energy -- fused forward transform, weighting and adjoint
  * in one kernel, for L = sum_b sum_k w_k^2 |(F x_b)[k]|^2 (a differentiable
  * use of the transform; F^H is the adjoint of Section II-A's F).
- *   plan        a forward, single-pass plan of length n and batch rows.
+ *   plan        a forward, single-pass plan of length n and batch rows.  The
+ *               kernel's shape is the plan's variant when one was named, else
+ *               the matched filter's tuned choice (fft_tune_query_filter):
+ *               both kernels run two transforms per load.
  *   x           device, batch * n complex64.
  *   w           device, n float32 spectral weights shared by every row.
  *   grad_scale  device, one float32 multiplying the gradient, or NULL for 1.
@@ -280,10 +283,11 @@ int fft_tune_clear(void);
 int fft_tune_query(int64_t n, int64_t batch, char *buf, int64_t cap);
 
 /*
- * fft_tune_query_filter -- the single-pass variant whose fused kernel
- * fft_exec_matched_filter would use for a forward plan of (n, batch) made
- * without an explicit variant (the matched filter is tuned on its own: it
- * runs two transforms per load and may prefer another shape).  The tune
+ * fft_tune_query_filter -- the single-pass variant whose fused kernels
+ * fft_exec_matched_filter and fft_exec_spectral_energy would use for a
+ * forward plan of (n, batch) made without an explicit variant (the matched
+ * filter is tuned on its own: it runs two transforms per load and may prefer
+ * another shape than the plain transform).  The tune
  * file's "filter_entries" take precedence over the built-in table.  Host
  * only.  Errors: as fft_tune_query (n must be at most 16384).
  */

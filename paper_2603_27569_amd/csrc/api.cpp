@@ -484,7 +484,14 @@ struct stockfft_plan_s {
   const void* tw_mma = nullptr;              // the matrix-core table (d_tw or d_tw_mma)
   const SingleVariant* sv_filter = nullptr;  // matched-filter kernel shape (forward plans)
   void* d_tw_filter = nullptr;               // its twiddles when it differs from sv
+  const SingleVariant* sv_fused = nullptr;   // fused forward/adjoint kernel shape
 };
+
+// Twiddle table of a single-pass shape held by the plan (its own or the
+// two-transform kernels').
+static const void* plan_table(const stockfft_plan_s* p, const SingleVariant* v) {
+  return v == p->sv ? p->d_tw : p->d_tw_filter;
+}
 
 static void free_plan(stockfft_plan_s* p) {
   if (!p) return;
@@ -564,7 +571,20 @@ extern "C" int fft_plan_config(fft_plan_t* plan, int64_t n, int64_t batch, int d
   std::vector<float> host;
   build_stockham_twiddles(*sv, host);
   rc = upload(host, &p->d_tw);
-  if (!rc && !fs && direction == FFT_FORWARD && sv->fused) {
+  if (!rc && !fs && direction == FFT_FORWARD) {
+    // The kernels that run two transforms per load (matched filter, fused
+    // forward -> weight -> adjoint): the named variant, else the matched
+    // filter's tuned choice, which is timed on that structure (its register
+    // pressure differs from a single transform's).
+    p->sv_filter = variant ? sv : tuned_filter_variant(n, batch);
+    if (p->sv_filter != sv) {
+      std::vector<float> ftw;
+      build_stockham_twiddles(*p->sv_filter, ftw);
+      rc = upload(ftw, &p->d_tw_filter);
+    }
+    p->sv_fused = p->sv_filter->fused ? p->sv_filter : (sv->fused ? sv : nullptr);
+  }
+  if (!rc && p->sv_fused) {
     const size_t bytes = (kTotalGroups * 64 + 1) * sizeof(unsigned);
     hipError_t e = hipMalloc((void**)&p->d_counters, bytes);
     if (e == hipSuccess) e = hipMemset(p->d_counters, 0, bytes);
@@ -586,15 +606,6 @@ extern "C" int fft_plan_config(fft_plan_t* plan, int64_t n, int64_t batch, int d
       rc = upload(mtw, &p->d_tw_mma);
     }
     if (mv) p->tw_mma = same ? p->d_tw : p->d_tw_mma;
-  }
-  if (!rc && !fs && direction == FFT_FORWARD) {
-    // The matched filter's kernel: the named variant, else its own tuned choice.
-    p->sv_filter = variant ? sv : tuned_filter_variant(n, batch);
-    if (p->sv_filter != sv) {
-      std::vector<float> ftw;
-      build_stockham_twiddles(*p->sv_filter, ftw);
-      rc = upload(ftw, &p->d_tw_filter);
-    }
   }
   if (!rc && fs) {
     build_four_step_twiddles(*fs, host);
@@ -677,8 +688,8 @@ extern "C" int fft_exec_spectral_energy(fft_plan_t plan, const void* x, const fl
                                         const float* grad_scale, void* grad_x, float* row_loss,
                                         float* loss_total, void* stream) {
   if (!plan || !live_handle(plan)) return FFT_INVALID_PLAN;
-  if (plan->direction != FFT_FORWARD || plan->algorithm != FFT_ALGO_SINGLE_PASS ||
-      !plan->sv->fused)
+  const SingleVariant* fv = plan->sv_fused;
+  if (plan->direction != FFT_FORWARD || plan->algorithm != FFT_ALGO_SINGLE_PASS || !fv)
     return FFT_UNSUPPORTED;
   if (!x || !w || !row_loss) return FFT_INVALID_POINTER;
   if (!aligned8(x) || (grad_x && !aligned8(grad_x)) || ((uintptr_t)w & 3u) ||
@@ -689,8 +700,8 @@ extern "C" int fft_exec_spectral_energy(fft_plan_t plan, const void* x, const fl
   if (grad_x && ranges_partially_overlap(x, grad_x, bytes)) return FFT_OVERLAP;
   DeviceGuard g(plan->device);
   hipStream_t s = (hipStream_t)stream;
-  const hipError_t e = plan->sv->fused(x, w, grad_scale, grad_x, row_loss, loss_total,
-                                       plan->d_counters, plan->d_tw, plan->batch, s);
+  const hipError_t e = fv->fused(x, w, grad_scale, grad_x, row_loss, loss_total,
+                                 plan->d_counters, plan_table(plan, fv), plan->batch, s);
   return e == hipSuccess ? FFT_SUCCESS : hip_fail(e);
 }
 
@@ -706,8 +717,7 @@ extern "C" int fft_exec_matched_filter(fft_plan_t plan, const void* x, const voi
   const size_t bytes = (size_t)plan->n * (size_t)plan->batch * 8;
   if (ranges_partially_overlap(x, out, bytes)) return FFT_OVERLAP;
   DeviceGuard g(plan->device);
-  const void* tw = fv == plan->sv ? plan->d_tw : plan->d_tw_filter;
-  hipError_t e = fv->filter(x, h, out, tw, plan->batch, (hipStream_t)stream);
+  hipError_t e = fv->filter(x, h, out, plan_table(plan, fv), plan->batch, (hipStream_t)stream);
   return e == hipSuccess ? FFT_SUCCESS : hip_fail(e);
 }
 
@@ -875,6 +885,8 @@ extern "C" int fft_plan_describe(fft_plan_t plan, char* buf, int64_t cap) {
                   (plan->fs ? ",\"four_step\":" + describe_four_step(*plan->fs) : "") +
                   (plan->sv_filter ? ",\"filter_variant\":\"" + std::string(plan->sv_filter->name) + "\""
                                    : "") +
+                  (plan->sv_fused ? ",\"fused_variant\":\"" + std::string(plan->sv_fused->name) + "\""
+                                  : "") +
                   "}";
   return put_text(s, buf, cap);
 }

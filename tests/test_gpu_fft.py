@@ -246,6 +246,27 @@ def test_spectral_energy_fused_matches_oracle():
             assert abs(got - fd) <= 1e-4 * np.max(np.abs(ref_grad[b])), (b, i, comp)
 
 
+@pytest.mark.parametrize("n,batch", [(2048, 1600), (4096, 700), (16384, 600)])
+def test_spectral_energy_takes_the_two_transform_shape(n, batch):
+    # The fused kernel runs two transforms per load, like the matched filter,
+    # and takes the matched filter's tuned shape (here one that differs from
+    # the plain transform's choice); its results still match the oracle.
+    p = sf.Plan(n, batch, sf.FFT_FORWARD, sf.FFT_ALGO_SINGLE_PASS)
+    d = p.describe()
+    p.close()
+    assert d["fused_variant"] == d["filter_variant"] == sf.fft_tune_query_filter(n, batch)
+    assert d["fused_variant"] != d["variant"]["name"]
+    x, w = workloads.spectral_energy_inputs(n=n, batch=batch, seed=41, wseed=42)
+    total, rows, grad = sf.spectral_energy(_gpu(x), _gpu(w))
+    ref_rows, ref_grad = oracle.spectral_energy(x, w)
+    rows = _host(rows).astype(np.float64)
+    assert np.max(np.abs(rows - ref_rows) / ref_rows) <= 1e-5
+    assert abs(float(_host(total)[0]) - ref_rows.sum()) / ref_rows.sum() <= 1e-5
+    grad = _host(grad)
+    rel = np.linalg.norm(grad - ref_grad) / np.linalg.norm(ref_grad)
+    assert rel <= 1e-4, rel
+
+
 def test_spectral_energy_loss_only_and_scale():
     x, w = workloads.spectral_energy_inputs(n=1024, batch=40)
     xt, wt = _gpu(x), _gpu(w)
