@@ -143,6 +143,32 @@ def test_builtin_table_is_the_shipped_tuner_output():
             assert sf.fft_tune_query_filter(e["n"], b) == e["variant"], (e["n"], b)
 
 
+def test_shipped_table_buckets_tile_every_batch():
+    """Per length, the shipped entries (plain and matched filter) cover batch 1
+    to the maximum without gaps or overlaps, follow the tuner's bucket list,
+    and each was timed inside its own bucket."""
+    from paper_2603_27569_amd import tune
+    doc = json.load(open(os.path.join(ROOT, "paper_2603_27569_amd", "tune_gfx950.json")))
+    lows = [b[0] for b in tune.BUCKETS]
+    for key in ("entries", "filter_entries"):
+        by_n = {}
+        for e in doc[key]:
+            by_n.setdefault(e["n"], []).append(e)
+        sizes = set(tune.SIZES) | (set(tune.SIZES_LARGE) if key == "entries" else set())
+        assert set(by_n) == sizes, key
+        for n, es in by_n.items():
+            es = sorted(es, key=lambda e: e["batch_min"])
+            assert [e["batch_min"] for e in es] == lows, (key, n)
+            assert es[-1]["batch_max"] >= 2 ** 62, (key, n)
+            for a, b2 in zip(es, es[1:]):
+                assert a["batch_max"] + 1 == b2["batch_min"], (key, n)
+            for e in es:
+                assert e["variant"] in e["candidates"], (key, n)
+                assert e["us"] == min(e["candidates"].values()), (key, n)
+                # timed inside the bucket (large lengths cap the timed batch)
+                assert e["timed_batch"] <= e["batch_max"], (key, n)
+
+
 def test_ragged_shape_tuning_api():
     sf.fft_tune_clear_ragged()
     builtin = {n: sf.fft_tune_query_ragged(n) for n in (256, 512, 1024, 2048, 4096, 8192, 16384)}
