@@ -119,9 +119,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the batched FFT shards by rows with no exchange, "
-              "and this build runs on a single MI355X; --gpus above 1 is not supported.",
-              file=sys.stderr)
+        print("bench.py measures one GPU (the batched FFT shards by rows, with no exchange "
+              "between GPUs); --gpus above 1 is not supported.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
