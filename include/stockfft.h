@@ -156,8 +156,9 @@ int fft_destroy(fft_plan_t plan);
  * use of the transform; F^H is the adjoint of Section II-A's F).
  *   plan        a forward, single-pass plan of length n and batch rows.  The
  *               kernel's shape is the plan's variant when one was named, else
- *               the matched filter's tuned choice (fft_tune_query_filter):
- *               both kernels run two transforms per load.
+ *               this kernel's own tuned choice (fft_tune_query_fused): it runs
+ *               two transforms per load and may prefer another shape than the
+ *               plain transform.
  *   x           device, batch * n complex64.
  *   w           device, n float32 spectral weights shared by every row.
  *   grad_scale  device, one float32 multiplying the gradient, or NULL for 1.
@@ -263,7 +264,9 @@ int fft_tune_clear_ragged(void);
 /*
  * Tuning.  fft_tune_load reads a JSON file written by the project's
  * autotuner: {"arch": "gfx950", "entries": [{"n": N, "batch_min": a,
- * "batch_max": b, "variant": "<name>"}, ...]}.  A missing or unreadable
+ * "batch_max": b, "variant": "<name>"}, ...]}, with "filter_entries" and
+ * "fused_entries" of the same form for the two fused kernels and "ragged":
+ * [{"n": N, "shape": "<name>"}, ...] for ragged plans.  A missing or unreadable
  * file, or one tuned for another architecture, leaves the built-in table in
  * force and returns FFT_INVALID_ARGUMENT; so does a file whose "cus" differs
  * from the device's compute-unit count.  Entries naming unknown variants
@@ -283,15 +286,22 @@ int fft_tune_clear(void);
 int fft_tune_query(int64_t n, int64_t batch, char *buf, int64_t cap);
 
 /*
- * fft_tune_query_filter -- the single-pass variant whose fused kernels
- * fft_exec_matched_filter and fft_exec_spectral_energy would use for a
- * forward plan of (n, batch) made without an explicit variant (the matched
- * filter is tuned on its own: it runs two transforms per load and may prefer
- * another shape than the plain transform).  The tune
- * file's "filter_entries" take precedence over the built-in table.  Host
- * only.  Errors: as fft_tune_query (n must be at most 16384).
+ * fft_tune_query_filter -- the single-pass variant whose fused kernel
+ * fft_exec_matched_filter would use for a forward plan of (n, batch) made
+ * without an explicit variant (the matched filter is tuned on its own: it
+ * runs two transforms per load and may prefer another shape than the plain
+ * transform).  The tune file's "filter_entries" take precedence over the
+ * built-in table.  Host only.  Errors: as fft_tune_query (n must be at most
+ * 16384).
  */
 int fft_tune_query_filter(int64_t n, int64_t batch, char *buf, int64_t cap);
+
+/*
+ * fft_tune_query_fused -- the same for the fused forward -> weight -> adjoint
+ * kernel of fft_exec_spectral_energy, tuned on its own ("fused_entries" in a
+ * tune file).  Host only.  Errors: as fft_tune_query_filter.
+ */
+int fft_tune_query_fused(int64_t n, int64_t batch, char *buf, int64_t cap);
 
 /*
  * fft_set_launch_limit -- largest grid (in workgroups) one kernel launch may

@@ -206,6 +206,8 @@ std::mutex g_tune_mu;
 // multiply -> inverse kernel can prefer another shape than the plain
 // transform.  Tune-file entries ("filter_entries") take precedence.
 std::vector<TuneEntry> g_tune_filter;
+// The same for the fused forward -> weight -> adjoint kernel ("fused_entries").
+std::vector<TuneEntry> g_tune_fused;
 std::vector<TuneEntry> g_tune;
 bool g_env_tune_done = false;
 
@@ -276,6 +278,29 @@ const BuiltinEntry kBuiltinFilter[] = {
     {16384, 1, INT64_MAX, "n16384_e32_b1_p4_r16.16.16.4"},
 };
 
+// Built-in fused forward -> weight -> adjoint choices: the autotuner's result
+// on MI355X (the "fused_entries" of the package's tune_gfx950.json).
+const BuiltinEntry kBuiltinFused[] = {
+    {256, 1, 1536, "n256_e4_b4_p4_r4.4.4.4"},
+    {256, 1537, 4096, "n256_e8_b8_p4_r8.8.4"},
+    {256, 4097, INT64_MAX, "n256_e16_b16_p4_r16.16"},
+    {512, 1, 512, "n512_e4_b2_p4_r4.4.4.4.2"},
+    {512, 513, INT64_MAX, "n512_e8_b4_p4_r8.8.8"},
+    {1024, 1, 512, "n1024_e4_b1_p4_r4.4.4.4.4"},
+    {1024, 513, 4096, "n1024_e8_b2_p4_r8.8.8.2"},
+    {1024, 4097, INT64_MAX, "n1024_e16_b4_p4_r16.16.4"},
+    {2048, 1, 4096, "n2048_e8_b1_p4_r8.8.8.4"},
+    {2048, 4097, INT64_MAX, "n2048_e16_b2_p4_r16.16.8"},
+    {4096, 1, 512, "n4096_e16_b1_px_r16.16.16_db"},
+    {4096, 513, 1536, "n4096_e32_b1_p4_r16.16.16"},
+    {4096, 1537, 4096, "n4096_e16_b1_px_r16.16.16"},
+    {4096, 4097, INT64_MAX, "n4096_e16_b1_px_r16.16.16_tall"},
+    {8192, 1, 64, "n8192_e16_b1_p4_r16.16.16.2"},
+    {8192, 65, 512, "n8192_e8_b1_p4_r8.8.8.8.2"},
+    {8192, 513, INT64_MAX, "n8192_e32_b1_p4_r16.16.16.2"},
+    {16384, 1, INT64_MAX, "n16384_e32_b1_p4_r16.16.16.4"},
+};
+
 // Single-pass fallback when a four-step choice is not wanted.
 const char* builtin_single(int64_t n) {
   switch (n) {
@@ -318,19 +343,33 @@ void tuned_choice(int64_t n, int64_t batch, bool single_only, const SingleVarian
       if (four_step_at(i).n == n) *fs = &four_step_at(i);
 }
 
-// The matched-filter variant for (n, batch): the last matching filter entry
-// (tune file, then built-in), else the plain transform's single-pass choice.
-const SingleVariant* tuned_filter_variant(int64_t n, int64_t batch) {
+// A two-transform kernel's variant for (n, batch): the last matching entry of
+// its table (tune file, then built-in), else the plain transform's
+// single-pass choice.
+template <size_t K>
+const SingleVariant* tuned_table_variant(const BuiltinEntry (&builtin)[K],
+                                         const std::vector<TuneEntry>& tuned, int64_t n,
+                                         int64_t batch) {
   const SingleVariant* sv = nullptr;
   const FourStepVariant* fs = nullptr;
   tuned_choice(n, batch, true, &sv, &fs);
   std::lock_guard<std::mutex> lk(g_tune_mu);
   const SingleVariant* chosen = nullptr;
-  for (const BuiltinEntry& b : kBuiltinFilter)
+  for (const BuiltinEntry& b : builtin)
     if (b.n == n && batch >= b.bmin && batch <= b.bmax) chosen = find_single(b.name);
-  for (const TuneEntry& e : g_tune_filter)
+  for (const TuneEntry& e : tuned)
     if (e.n == n && batch >= e.bmin && batch <= e.bmax && e.v) chosen = e.v;
-  return chosen && chosen->filter ? chosen : sv;
+  return chosen ? chosen : sv;
+}
+
+// The matched filter's variant for (n, batch).
+const SingleVariant* tuned_filter_variant(int64_t n, int64_t batch) {
+  return tuned_table_variant(kBuiltinFilter, g_tune_filter, n, batch);
+}
+
+// The fused forward -> weight -> adjoint kernel's variant for (n, batch).
+const SingleVariant* tuned_fused_variant(int64_t n, int64_t batch) {
+  return tuned_table_variant(kBuiltinFused, g_tune_fused, n, batch);
 }
 
 const SingleVariant* tuned_variant(int64_t n, int64_t batch) {
@@ -410,8 +449,10 @@ int load_tune_file_locked(const char* path) {
       add.push_back({n, num(e, "batch_min", 1), num(e, "batch_max", INT64_MAX), v, fs});
     }
   }
-  std::vector<TuneEntry> add_filter;
-  if (const json::Value* es = doc.get("filter_entries"); es && es->kind == json::Value::Array) {
+  // Single-pass entries of a two-transform kernel's table.
+  auto single_entries = [&](const char* key, std::vector<TuneEntry>* out) {
+    const json::Value* es = doc.get(key);
+    if (!es || es->kind != json::Value::Array) return;
     for (const json::Value& e : es->arr) {
       const std::string* name = str(e, "variant");
       const int64_t n = num(e, "n", 0);
@@ -420,9 +461,12 @@ int load_tune_file_locked(const char* path) {
         ++skipped;
         continue;
       }
-      add_filter.push_back({n, num(e, "batch_min", 1), num(e, "batch_max", INT64_MAX), v, nullptr});
+      out->push_back({n, num(e, "batch_min", 1), num(e, "batch_max", INT64_MAX), v, nullptr});
     }
-  }
+  };
+  std::vector<TuneEntry> add_filter, add_fused;
+  single_entries("filter_entries", &add_filter);
+  single_entries("fused_entries", &add_fused);
   if (const json::Value* rs = doc.get("ragged"); rs && rs->kind == json::Value::Array) {
     for (const json::Value& e : rs->arr) {
       const std::string* shape = str(e, "shape");
@@ -434,6 +478,7 @@ int load_tune_file_locked(const char* path) {
                  skipped, path);
   g_tune.insert(g_tune.end(), add.begin(), add.end());
   g_tune_filter.insert(g_tune_filter.end(), add_filter.begin(), add_filter.end());
+  g_tune_fused.insert(g_tune_fused.end(), add_fused.begin(), add_fused.end());
   return FFT_SUCCESS;
 }
 
@@ -485,12 +530,13 @@ struct stockfft_plan_s {
   const SingleVariant* sv_filter = nullptr;  // matched-filter kernel shape (forward plans)
   void* d_tw_filter = nullptr;               // its twiddles when it differs from sv
   const SingleVariant* sv_fused = nullptr;   // fused forward/adjoint kernel shape
+  void* d_tw_fused = nullptr;                // its twiddles when it differs from both
 };
 
-// Twiddle table of a single-pass shape held by the plan (its own or the
-// two-transform kernels').
+// Twiddle table of a single-pass shape held by the plan (its own or one of
+// the two-transform kernels').
 static const void* plan_table(const stockfft_plan_s* p, const SingleVariant* v) {
-  return v == p->sv ? p->d_tw : p->d_tw_filter;
+  return v == p->sv ? p->d_tw : v == p->sv_filter ? p->d_tw_filter : p->d_tw_fused;
 }
 
 static void free_plan(stockfft_plan_s* p) {
@@ -499,6 +545,7 @@ static void free_plan(stockfft_plan_s* p) {
   if (p->d_tw4) (void)hipFree(p->d_tw4);
   if (p->d_ws) (void)hipFree(p->d_ws);
   if (p->d_tw_filter) (void)hipFree(p->d_tw_filter);
+  if (p->d_tw_fused) (void)hipFree(p->d_tw_fused);
   if (p->d_counters) (void)hipFree(p->d_counters);
   if (p->d_tw_mma) (void)hipFree(p->d_tw_mma);
   delete p;
@@ -573,16 +620,23 @@ extern "C" int fft_plan_config(fft_plan_t* plan, int64_t n, int64_t batch, int d
   rc = upload(host, &p->d_tw);
   if (!rc && !fs && direction == FFT_FORWARD) {
     // The kernels that run two transforms per load (matched filter, fused
-    // forward -> weight -> adjoint): the named variant, else the matched
-    // filter's tuned choice, which is timed on that structure (its register
-    // pressure differs from a single transform's).
+    // forward -> weight -> adjoint): the named variant, else each kernel's
+    // own tuned choice (timed on that kernel: its register pressure differs
+    // from a single transform's), each with its twiddles.
     p->sv_filter = variant ? sv : tuned_filter_variant(n, batch);
+    if (!p->sv_filter->filter) p->sv_filter = sv;
     if (p->sv_filter != sv) {
       std::vector<float> ftw;
       build_stockham_twiddles(*p->sv_filter, ftw);
       rc = upload(ftw, &p->d_tw_filter);
     }
-    p->sv_fused = p->sv_filter->fused ? p->sv_filter : (sv->fused ? sv : nullptr);
+    const SingleVariant* fv = variant ? sv : tuned_fused_variant(n, batch);
+    p->sv_fused = fv->fused ? fv : (sv->fused ? sv : nullptr);
+    if (!rc && p->sv_fused && p->sv_fused != sv && p->sv_fused != p->sv_filter) {
+      std::vector<float> utw;
+      build_stockham_twiddles(*p->sv_fused, utw);
+      rc = upload(utw, &p->d_tw_fused);
+    }
   }
   if (!rc && p->sv_fused) {
     const size_t bytes = (kTotalGroups * 64 + 1) * sizeof(unsigned);
@@ -771,6 +825,15 @@ extern "C" int fft_tune_query_filter(int64_t n, int64_t batch, char* buf, int64_
   return put_text(v->name, buf, cap);
 }
 
+extern "C" int fft_tune_query_fused(int64_t n, int64_t batch, char* buf, int64_t cap) {
+  if (!buf) return FFT_INVALID_POINTER;
+  if (!valid_single_size(n)) return FFT_INVALID_SIZE;
+  if (batch < 1) return FFT_INVALID_BATCH;
+  const SingleVariant* v = tuned_fused_variant(n, batch);
+  if (!v) return FFT_INVALID_SIZE;
+  return put_text(v->name, buf, cap);
+}
+
 extern "C" int fft_set_launch_limit(int64_t max_groups) {
   set_max_groups_per_launch(max_groups > 0 ? max_groups : kDefaultMaxGroupsPerLaunch);
   return FFT_SUCCESS;
@@ -781,6 +844,7 @@ extern "C" int fft_tune_clear(void) {
   g_env_tune_done = true;
   g_tune.clear();
   g_tune_filter.clear();
+  g_tune_fused.clear();
   return FFT_SUCCESS;
 }
 

@@ -4,8 +4,9 @@ For every transform length and batch bucket it times each compiled kernel
 variant -- values per lane (hence the radix and lanes per transform),
 transforms per workgroup, LDS padding, and for N >= 8192 the four-step
 splits (for N > 16384 the only kind) -- through the C ABI, and keeps the
-fastest.  The fused matched
-filter is tuned the same way on its own.  For the ragged persistent kernel
+fastest.  The two fused kernels (the matched filter, and the forward ->
+weight -> adjoint kernel with its loss total) are tuned the same way, each on
+its own.  For the ragged persistent kernel
 it picks one compiled shape per length by coordinate descent on a mixed
 ragged batch.  The result is a JSON file that
 ``fft_tune_load`` (or the STOCKFFT_TUNE_CACHE environment variable) applies:
@@ -13,6 +14,7 @@ ragged batch.  The result is a JSON file that
   {"arch": "gfx950", "cus": 256, "hip_runtime": ..., "entries": [
      {"n": 4096, "batch_min": 129, "batch_max": 1024,
       "variant": "n4096_e16_b1_p4_r16.16.16", "us": ..., "candidates": {...}}],
+   "filter_entries": [...], "fused_entries": [...],   (same form)
    "ragged": [{"n": 4096, "shape": "ragged_n4096_e16", "batch_us": ...}]}
 
 Timing: back-to-back launches over a ring of independent buffers larger
@@ -33,8 +35,8 @@ import statistics
 import sys
 
 from . import (FFT_ALGO_FOUR_STEP, FFT_ALGO_SINGLE_PASS, FFT_FORWARD, Plan, RaggedPlan,
-               fft_exec_matched_filter, fft_ragged_shapes, fft_tune_clear_ragged,
-               fft_tune_set_ragged, variants)
+               fft_exec_matched_filter, fft_exec_spectral_energy, fft_ragged_shapes,
+               fft_tune_clear_ragged, fft_tune_set_ragged, variants)
 
 SIZES = (256, 512, 1024, 2048, 4096, 8192, 16384)
 # Lengths with four-step splits only (plain transform; the fused kernels are
@@ -140,6 +142,40 @@ def tune_filter(torch, dev, stream, sizes=SIZES, buckets=BUCKETS, iters=30, log=
     return entries
 
 
+def tune_fused(torch, dev, stream, sizes=SIZES, buckets=BUCKETS, iters=30, log=print):
+    """The fused forward -> weight -> adjoint kernel (gradient and loss total
+    included) per length and batch bucket, over the single-pass variants."""
+    entries = []
+    for n in sizes:
+        w = torch.rand(n, dtype=torch.float32, device=dev)
+        total = torch.empty(1, dtype=torch.float32, device=dev)
+        for bmin, bmax, b in buckets:
+            while n * b * 8 > MAX_BYTES and b > 1:
+                b //= 2
+            xs, ys = _ring(torch, dev, n, b)
+            k = len(xs)
+            rows = torch.empty(b, dtype=torch.float32, device=dev)
+            times = {}
+            cs = stream.cuda_stream
+            for name, algo in candidates(n):
+                if algo != FFT_ALGO_SINGLE_PASS:
+                    continue
+                p = Plan(n, b, FFT_FORWARD, algo, name)
+                times[name] = _time(torch, stream,
+                                    lambda i: fft_exec_spectral_energy(
+                                        p.handle, xs[i % k].data_ptr(), w.data_ptr(), 0,
+                                        ys[i % k].data_ptr(), rows.data_ptr(), total.data_ptr(), cs),
+                                    iters)
+                p.close()
+            best = min(times, key=times.get)
+            log(f"tune fused n={n} batch={b} -> {best} {times[best]:.2f} us")
+            entries.append({"n": n, "batch_min": bmin, "batch_max": bmax, "variant": best,
+                            "timed_batch": b, "us": round(times[best], 3),
+                            "candidates": {k2: round(v, 3) for k2, v in times.items()}})
+            del xs, ys
+    return entries
+
+
 def tune_ragged(torch, dev, stream, sizes=None, iters=20, sweeps=2, log=print):
     """Choose the ragged kernel's shape per length on a mixed ragged batch.
 
@@ -202,11 +238,12 @@ def run(out_path, quick=False, log=print):
     entries = tune_plain(torch, dev, stream, sizes=SIZES + SIZES_LARGE, buckets=buckets,
                          iters=10 if quick else 30, log=log)
     filters = tune_filter(torch, dev, stream, buckets=buckets, iters=10 if quick else 30, log=log)
+    fused = tune_fused(torch, dev, stream, buckets=buckets, iters=10 if quick else 30, log=log)
     ragged = tune_ragged(torch, dev, stream, iters=5 if quick else 20, sweeps=1 if quick else 2,
                          log=log)
     doc = {"arch": props.gcnArchName.split(":")[0], "cus": props.multi_processor_count,
            "hip_runtime": getattr(torch.version, "hip", None), "entries": entries,
-           "filter_entries": filters, "ragged": ragged}
+           "filter_entries": filters, "fused_entries": fused, "ragged": ragged}
     with open(out_path, "w") as f:
         json.dump(doc, f, indent=1)
     return doc

@@ -141,6 +141,10 @@ def test_builtin_table_is_the_shipped_tuner_output():
     for e in doc.get("filter_entries", []):
         for b in (e["batch_min"], e["timed_batch"], min(e["batch_max"], 10 ** 9)):
             assert sf.fft_tune_query_filter(e["n"], b) == e["variant"], (e["n"], b)
+    assert doc.get("fused_entries")
+    for e in doc["fused_entries"]:
+        for b in (e["batch_min"], e["timed_batch"], min(e["batch_max"], 10 ** 9)):
+            assert sf.fft_tune_query_fused(e["n"], b) == e["variant"], (e["n"], b)
 
 
 def test_shipped_table_buckets_tile_every_batch():
@@ -150,7 +154,7 @@ def test_shipped_table_buckets_tile_every_batch():
     from paper_2603_27569_amd import tune
     doc = json.load(open(os.path.join(ROOT, "paper_2603_27569_amd", "tune_gfx950.json")))
     lows = [b[0] for b in tune.BUCKETS]
-    for key in ("entries", "filter_entries"):
+    for key in ("entries", "filter_entries", "fused_entries"):
         by_n = {}
         for e in doc[key]:
             by_n.setdefault(e["n"], []).append(e)
@@ -350,8 +354,14 @@ def test_tune_table_set_query_load(tmp_path):
             {"n": 2048, "batch_min": 1, "batch_max": 10, "variant": "bogus"}],
             "filter_entries": [
             {"n": 1024, "batch_min": 1, "batch_max": 10 ** 9, "variant": "n1024_e4_b1_p4_r4.4.4.4.4"},
-            {"n": 1024, "batch_min": 1, "batch_max": 10, "variant": "n2048_e8_b1_p4_r8.8.8.4"}]}))
+            {"n": 1024, "batch_min": 1, "batch_max": 10, "variant": "n2048_e8_b1_p4_r8.8.8.4"}],
+            "fused_entries": [
+            {"n": 512, "batch_min": 1, "batch_max": 10 ** 9, "variant": "n512_e4_b2_p4_r4.4.4.4.2"},
+            {"n": 512, "batch_min": 1, "batch_max": 10, "variant": "bogus"}]}))
         sf.fft_tune_load(str(p))
+        assert sf.fft_tune_query_fused(512, 5) == "n512_e4_b2_p4_r4.4.4.4.2"
+        with pytest.raises(sf.StockfftError):
+            sf.fft_tune_query_fused(32768, 5)
         assert sf.fft_tune_query(2048, 5) == "n2048_e8_b1_p4_r8.8.8.4"
         assert sf.fft_tune_query_filter(1024, 5) == "n1024_e4_b1_p4_r4.4.4.4.4"
         with pytest.raises(sf.StockfftError):

@@ -44,6 +44,18 @@ def test_tuner_restricted_search_and_load(tmp_path):
         sf.fft_tune_clear()
 
 
+def test_fused_tuner_restricted_search():
+    dev = torch.device("cuda:0")
+    s = torch.cuda.Stream()
+    entries = tune.tune_fused(torch, dev, s, sizes=(1024,), buckets=((1, 2 ** 62, 64),),
+                              iters=3, log=lambda *a: None)
+    assert [e["n"] for e in entries] == [1024]
+    e = entries[0]
+    names = {v["name"] for v in sf.variants() if v["kind"] == "single" and v["n"] == 1024}
+    assert set(e["candidates"]) == names
+    assert e["variant"] in names and e["us"] == min(e["candidates"].values())
+
+
 def test_ragged_shape_tuner():
     dev = torch.device("cuda:0")
     s = torch.cuda.Stream()
