@@ -121,7 +121,7 @@ int fft_exec(fft_plan_t plan, const void *in, void *out, void *stream);
  * load, every pass runs in FP32 with the plan's FP32 twiddles, and each
  * output is rounded once to the storage format (nearest even).  This halves
  * the bytes of a bandwidth-bound transform (the paper's future-work item on
- * half-precision storage, Section VIII); the error is then that of one
+ * mixed-precision storage, Section IX-A); the error is then that of one
  * rounding of the output, about 2^-11 (binary16) or 2^-8 (bfloat16) relative.
  * binary16 overflows to infinity above 65504: a bin can reach sqrt(n) times
  * the input row's 2-norm, so inputs must be scaled for that; bfloat16 has
@@ -130,9 +130,9 @@ int fft_exec(fft_plan_t plan, const void *in, void *out, void *stream);
  * FFT_IO_C16_MMA / FFT_IO_BC16_MMA: the same storage for n = 16^P * RL
  * (512, 1024, 2048, 4096, 8192, 16384; any single-pass plan of those
  * lengths), with every 16-point DFT of the P radix-16 passes computed on the
- * matrix cores (the paper's matrix-multiply DFT, Section VI, with its
- * half-precision future-work item, Section VIII) and a last radix-RL pass
- * (RL = 2, 4, 8) on the vector ALUs: twiddles are applied in FP32, then each
+ * matrix cores (the paper's matrix-multiply DFT, Sections V-C and VII-C,
+ * with its batched and mixed-precision future-work items, Section IX-A)
+ * and a last radix-RL pass (RL = 2, 4, 8) on the vector ALUs: twiddles are applied in FP32, then each
  * pass's inputs and the DFT matrix are rounded to the storage format and
  * multiplied with FP32 sums, so the error is that of one rounding per pass
  * plus the rounded matrix's instead of one rounding in all.
@@ -181,7 +181,7 @@ int fft_exec_spectral_energy(fft_plan_t plan, const void *x, const float *w,
 
 /*
  * fft_exec_matched_filter -- fused range compression (the paper's future
- * work on SAR pipeline fusion, Section VIII): out_b = F^{-1}(conj(h) .* F x_b)
+ * work on SAR pipeline fusion, Section IX-A): out_b = F^{-1}(conj(h) .* F x_b)
  * with F^{-1} = backward / N, in one kernel.
  *   plan   a forward, single-pass plan; the kernel's shape is the plan's
  *          variant when one was named, else fft_tune_query_filter's choice

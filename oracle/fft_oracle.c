@@ -29,7 +29,7 @@
  * (F is symmetric, so F^H is the backward, sign = +1, unscaled transform).
  *
  * oracle_matched_filter is the reference for the fused range-compression
- * chain named in the paper's future work (Section VIII): out = F^{-1}(conj(H) .* F x).
+ * chain named in the paper's future work (Section IX-A): out = F^{-1}(conj(H) .* F x).
  */
 #include <math.h>
 #include <stdint.h>

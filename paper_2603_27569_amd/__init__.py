@@ -275,9 +275,16 @@ _cache_lock = threading.Lock()
 _plan_cache = {}
 
 
-def cached_plan(n, batch, direction, device_index, algorithm=FFT_ALGO_AUTO, variant=None):
+def cached_plan(n, batch, direction, device_index, algorithm=FFT_ALGO_AUTO, variant=None,
+                stream=0):
+    """A cached Plan per (shape, direction, device, algorithm, variant, stream).
+
+    A plan owns its four-step workspace and its loss-total counters, so one
+    plan must not run on two streams at once: the stream handle is part of
+    the key, and calls on different streams get different plans."""
     import torch
-    key = (int(n), int(batch), int(direction), int(device_index), int(algorithm), variant)
+    key = (int(n), int(batch), int(direction), int(device_index), int(algorithm), variant,
+           int(stream))
     with _cache_lock:
         p = _plan_cache.get(key)
         if p is None:
@@ -324,8 +331,9 @@ def _transform(x, direction, out=None, algorithm=FFT_ALGO_AUTO, variant=None):
             raise ValueError("out must have the shape of x")
     if batch == 0:
         return out
-    p = cached_plan(n, batch, direction, x.device.index, algorithm, variant)
-    fft_exec(p.handle, x.data_ptr(), out.data_ptr(), _stream(x.device))
+    st = _stream(x.device)
+    p = cached_plan(n, batch, direction, x.device.index, algorithm, variant, st)
+    fft_exec(p.handle, x.data_ptr(), out.data_ptr(), st)
     return out
 
 
@@ -361,9 +369,10 @@ def fft_lowp(x, inverse=False, out=None, mma=False):
         raise ValueError("out must match x")
     if batch == 0:
         return out
+    st = _stream(x.device)
     p = cached_plan(n, batch, FFT_BACKWARD if inverse else FFT_FORWARD, x.device.index,
-                    FFT_ALGO_SINGLE_PASS)
-    fft_exec_io(p.handle, x.data_ptr(), out.data_ptr(), io, _stream(x.device))
+                    FFT_ALGO_SINGLE_PASS, stream=st)
+    fft_exec_io(p.handle, x.data_ptr(), out.data_ptr(), io, st)
     return out
 
 
@@ -375,8 +384,8 @@ def spectral_energy(x, w, grad_scale=None, want_grad=True):
     """Fused kernel: returns (loss_total[1], row_loss[batch], grad or None).
 
     loss = sum_b sum_k w_k^2 |(F x_b)[k]|^2; grad = scale * F^H(2 w^2 F x_b).
-    The plan is cached per (n, batch, device) and its loss-total counters are
-    shared: calls with the same shape on different streams must be ordered."""
+    The plan is cached per (n, batch, device, stream): its loss-total
+    counters are shared by the calls on one stream, which the stream orders."""
     import torch
     _check_tensor(x)
     if w.device != x.device or w.dtype != torch.float32 or not w.is_contiguous():
@@ -385,7 +394,8 @@ def spectral_energy(x, w, grad_scale=None, want_grad=True):
     if w.numel() != n:
         raise ValueError("w must have N elements")
     batch = x.numel() // n
-    p = cached_plan(n, batch, FFT_FORWARD, x.device.index, FFT_ALGO_SINGLE_PASS)
+    st = _stream(x.device)
+    p = cached_plan(n, batch, FFT_FORWARD, x.device.index, FFT_ALGO_SINGLE_PASS, stream=st)
     row_loss = torch.empty(batch, dtype=torch.float32, device=x.device)
     total = torch.empty(1, dtype=torch.float32, device=x.device)
     grad = torch.empty_like(x) if want_grad else None
@@ -397,7 +407,7 @@ def spectral_energy(x, w, grad_scale=None, want_grad=True):
         gs = grad_scale.data_ptr()
     fft_exec_spectral_energy(p.handle, x.data_ptr(), w.data_ptr(), gs,
                              grad.data_ptr() if grad is not None else 0,
-                             row_loss.data_ptr(), total.data_ptr(), _stream(x.device))
+                             row_loss.data_ptr(), total.data_ptr(), st)
     return total, row_loss, grad
 
 
@@ -412,8 +422,9 @@ def matched_filter(x, h, out=None):
     batch = x.numel() // n
     if out is None:
         out = torch.empty_like(x)
-    p = cached_plan(n, batch, FFT_FORWARD, x.device.index, FFT_ALGO_SINGLE_PASS)
-    fft_exec_matched_filter(p.handle, x.data_ptr(), h.data_ptr(), out.data_ptr(), _stream(x.device))
+    st = _stream(x.device)
+    p = cached_plan(n, batch, FFT_FORWARD, x.device.index, FFT_ALGO_SINGLE_PASS, stream=st)
+    fft_exec_matched_filter(p.handle, x.data_ptr(), h.data_ptr(), out.data_ptr(), st)
     return out
 
 

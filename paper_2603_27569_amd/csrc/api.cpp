@@ -18,6 +18,7 @@
 
 #include "internal.hpp"
 #include "json_lite.hpp"
+#include "twiddles.hpp"
 #include "variants.hpp"
 
 namespace stockfft {
@@ -85,61 +86,17 @@ const FourStepVariant* find_four_step(const char* name) {
 bool valid_size(int64_t n) { return n >= 256 && n <= kMaxN && (n & (n - 1)) == 0; }
 bool valid_single_size(int64_t n) { return valid_size(n) && n <= kMaxSinglePassN; }
 
-int ilog2(int64_t n) {
-  int l = 0;
-  while ((int64_t(1) << l) < n) ++l;
-  return l;
-}
+int ilog2(int64_t n) { return ilog2_i64(n); }
 
-// exp(-2 pi i m / L) for 0 <= m < L, evaluated in FP64 and rounded once to FP32.
-static void root_f32(int64_t m, int64_t L, float* re, float* im) {
-  const double a = -2.0 * M_PI * (double)m / (double)L;
-  *re = (float)std::cos(a);
-  *im = (float)std::sin(a);
-}
-
-// Per-pass tables of a Stockham plan: for pass p >= 1 with Ns = R_0 ... R_{p-1},
-// entry [r - 1][k] = W_{Ns R_p}^{k r}, r in [1, R_p), k in [0, Ns).
 void build_stockham_twiddles(const SingleVariant& v, std::vector<float>& out) {
-  out.clear();
-  int64_t ns = v.radix[0];
-  for (int p = 1; p < v.npass; ++p) {
-    const int R = v.radix[p];
-    const int64_t L = ns * R;
-    for (int r = 1; r < R; ++r)
-      for (int64_t k = 0; k < ns; ++k) {
-        float re, im;
-        root_f32(k * r, L, &re, &im);
-        out.push_back(re);
-        out.push_back(im);
-      }
-    ns *= R;
-  }
+  stockham_twiddles(v.radix, v.npass, out);
 }
 
-// Four-step second-stage table.  Full layout: entry [n1 - 1][k2] = W_N^{n1 k2},
-// n1 in [1, N1), k2 in [0, N2).  Two-level layout (large N): lo[j] = W_N^j for
-// j < 2^s, hi[j] = W_N^{j 2^s} for j < N / 2^s (s = floor(log2 N / 2)), so
-// W_N^m = hi[m >> s] lo[m mod 2^s]; then W_N1^j for j < N1.
+// The four-step table, plus (tiled splits with N1 != N2) the second stage's
+// N1-point single-pass table appended.
 void build_four_step_twiddles(const FourStepVariant& f, std::vector<float>& out) {
-  out.clear();
-  const int64_t N = (int64_t)f.n1 * f.n2;
-  auto put = [&](int64_t m, int64_t L) {
-    float re, im;
-    root_f32(m, L, &re, &im);
-    out.push_back(re);
-    out.push_back(im);
-  };
-  if (!f.two_level) {
-    for (int n1 = 1; n1 < f.n1; ++n1)
-      for (int64_t k2 = 0; k2 < f.n2; ++k2) put(n1 * k2, N);
-    return;
-  }
-  const int s = ilog2(N) / 2;
-  for (int64_t j = 0; j < (int64_t(1) << s); ++j) put(j, N);
-  for (int64_t j = 0; j < (N >> s); ++j) put(j << s, N);
-  for (int j = 0; j < f.n1; ++j) put(j, f.n1);
-  if (f.sub2_name) {
+  four_step_twiddles(f.n1, f.n2, f.two_level, out);
+  if (f.two_level && f.sub2_name) {
     std::vector<float> sub2;
     build_stockham_twiddles(*find_single(f.sub2_name), sub2);
     out.insert(out.end(), sub2.begin(), sub2.end());
@@ -403,28 +360,52 @@ int load_tune_file_locked(const char* path) {
   }
   // A file tuned for another architecture, or on another CU count (a
   // partitioned GPU exposes fewer CUs per device), is stale for this device.
+  // "arch" and "cus" are optional; when present they must be a non-empty
+  // name and a positive integer, and (with a device) match it: the name up
+  // to its ':' feature suffix, exactly.
   const json::Value* arch = doc.get("arch");
   const json::Value* cus = doc.get("cus");
+  auto base_arch = [](const std::string& a) { return a.substr(0, a.find(':')); };
+  if ((arch && (arch->kind != json::Value::String || base_arch(arch->str).empty())) ||
+      (cus && (cus->kind != json::Value::Number || !(cus->num >= 1.0 && cus->num <= 1e6) ||
+               cus->num != std::floor(cus->num)))) {
+    std::fprintf(stderr, "stockfft: tune file %s has a malformed arch or cus; ignored\n", path);
+    return FFT_INVALID_ARGUMENT;
+  }
   int count = 0, dev = 0;
   hipDeviceProp_t prop;
   if (hipGetDeviceCount(&count) == hipSuccess && count > 0 && hipGetDevice(&dev) == hipSuccess &&
       hipGetDeviceProperties(&prop, dev) == hipSuccess) {
-    if (arch && arch->kind == json::Value::String &&
-        std::strncmp(prop.gcnArchName, arch->str.c_str(), arch->str.size()) != 0) {
+    if (arch && base_arch(arch->str) != base_arch(prop.gcnArchName)) {
       std::fprintf(stderr, "stockfft: tune file %s is for %s, device is %s; ignored\n", path,
                    arch->str.c_str(), prop.gcnArchName);
       return FFT_INVALID_ARGUMENT;
     }
-    if (cus && cus->kind == json::Value::Number && (int64_t)cus->num != prop.multiProcessorCount) {
+    if (cus && (int64_t)cus->num != prop.multiProcessorCount) {
       std::fprintf(stderr, "stockfft: tune file %s was tuned on %lld CUs, device has %d; ignored\n",
                    path, (long long)cus->num, prop.multiProcessorCount);
       return FFT_INVALID_ARGUMENT;
     }
   }
-  auto num = [](const json::Value& o, const char* k, int64_t dflt) {
+  // An integer field: dflt when absent; an integral number >= lo otherwise
+  // (values from 2^63 on saturate to INT64_MAX), else *bad is set.
+  auto num = [](const json::Value& o, const char* k, int64_t dflt, int64_t lo, bool* bad) {
     const json::Value* v = o.get(k);
-    if (!v || v->kind != json::Value::Number) return dflt;
+    if (!v) return dflt;
+    if (v->kind != json::Value::Number || !(v->num >= (double)lo) ||
+        v->num != std::floor(v->num)) {
+      *bad = true;
+      return dflt;
+    }
     return v->num >= 9.2e18 ? INT64_MAX : (int64_t)v->num;
+  };
+  // n, batch_min and batch_max of one entry, checked as fft_tune_set checks them.
+  auto range = [&](const json::Value& e, int64_t* n, int64_t* bmin, int64_t* bmax) {
+    bool bad = false;
+    *n = num(e, "n", 0, 0, &bad);
+    *bmin = num(e, "batch_min", 1, 1, &bad);
+    *bmax = num(e, "batch_max", INT64_MAX, 1, &bad);
+    return !bad && *bmax >= *bmin;
   };
   auto str = [](const json::Value& o, const char* k) -> const std::string* {
     const json::Value* v = o.get(k);
@@ -435,8 +416,8 @@ int load_tune_file_locked(const char* path) {
   if (const json::Value* es = doc.get("entries"); es && es->kind == json::Value::Array) {
     for (const json::Value& e : es->arr) {
       const std::string* name = str(e, "variant");
-      const int64_t n = num(e, "n", 0);
-      if (!name || !valid_size(n)) {
+      int64_t n, bmin, bmax;
+      if (!name || !range(e, &n, &bmin, &bmax) || !valid_size(n)) {
         ++skipped;
         continue;
       }
@@ -446,7 +427,7 @@ int load_tune_file_locked(const char* path) {
         ++skipped;
         continue;
       }
-      add.push_back({n, num(e, "batch_min", 1), num(e, "batch_max", INT64_MAX), v, fs});
+      add.push_back({n, bmin, bmax, v, fs});
     }
   }
   // Single-pass entries of a two-transform kernel's table.
@@ -455,13 +436,15 @@ int load_tune_file_locked(const char* path) {
     if (!es || es->kind != json::Value::Array) return;
     for (const json::Value& e : es->arr) {
       const std::string* name = str(e, "variant");
-      const int64_t n = num(e, "n", 0);
-      const SingleVariant* v = name && valid_single_size(n) ? find_single(name->c_str()) : nullptr;
+      int64_t n, bmin, bmax;
+      const bool ok = range(e, &n, &bmin, &bmax);
+      const SingleVariant* v =
+          ok && name && valid_single_size(n) ? find_single(name->c_str()) : nullptr;
       if (!v || v->n != n) {
         ++skipped;
         continue;
       }
-      out->push_back({n, num(e, "batch_min", 1), num(e, "batch_max", INT64_MAX), v, nullptr});
+      out->push_back({n, bmin, bmax, v, nullptr});
     }
   };
   std::vector<TuneEntry> add_filter, add_fused;
@@ -470,7 +453,9 @@ int load_tune_file_locked(const char* path) {
   if (const json::Value* rs = doc.get("ragged"); rs && rs->kind == json::Value::Array) {
     for (const json::Value& e : rs->arr) {
       const std::string* shape = str(e, "shape");
-      if (!shape || fft_tune_set_ragged(num(e, "n", 0), shape->c_str()) != FFT_SUCCESS) ++skipped;
+      bool bad = false;
+      const int64_t n = num(e, "n", 0, 0, &bad);
+      if (bad || !shape || fft_tune_set_ragged(n, shape->c_str()) != FFT_SUCCESS) ++skipped;
     }
   }
   if (skipped)

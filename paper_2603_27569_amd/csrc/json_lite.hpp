@@ -1,8 +1,10 @@
 // A small JSON reader for the tuning file: objects, arrays, strings (with the
-// standard escapes), numbers, true / false / null.  Parse errors leave the
-// value of kind Null and set ok = false.
+// standard escapes), numbers, true / false / null, nested at most 64 deep.
+// Anything outside JSON's grammar (a bad escape, a hex / inf / nan number, a
+// number that overflows double, trailing text) fails the parse.
 #pragma once
 
+#include <cmath>
 #include <cstdlib>
 #include <map>
 #include <memory>
@@ -64,6 +66,53 @@ class Parser {
     }
     return false;
   }
+  static int hexval(char c) {
+    if (c >= '0' && c <= '9') return c - '0';
+    if (c >= 'a' && c <= 'f') return c - 'a' + 10;
+    if (c >= 'A' && c <= 'F') return c - 'A' + 10;
+    return -1;
+  }
+  bool digit() const { return i_ < s_.size() && s_[i_] >= '0' && s_[i_] <= '9'; }
+  // A number in JSON's grammar, -?(0|[1-9][0-9]*)(.[0-9]+)?([eE][+-]?[0-9]+)?;
+  // no hex, inf or nan spellings, and a finite value.
+  void number(Value* v) {
+    const size_t start = i_;
+    if (i_ < s_.size() && s_[i_] == '-') ++i_;
+    if (!digit()) {
+      ok_ = false;
+      return;
+    }
+    if (s_[i_] == '0') {
+      ++i_;
+    } else {
+      while (digit()) ++i_;
+    }
+    if (i_ < s_.size() && s_[i_] == '.') {
+      ++i_;
+      if (!digit()) {
+        ok_ = false;
+        return;
+      }
+      while (digit()) ++i_;
+    }
+    if (i_ < s_.size() && (s_[i_] == 'e' || s_[i_] == 'E')) {
+      ++i_;
+      if (i_ < s_.size() && (s_[i_] == '+' || s_[i_] == '-')) ++i_;
+      if (!digit()) {
+        ok_ = false;
+        return;
+      }
+      while (digit()) ++i_;
+    }
+    const std::string text = s_.substr(start, i_ - start);
+    const double d = std::strtod(text.c_str(), nullptr);
+    if (!std::isfinite(d)) {
+      ok_ = false;
+      return;
+    }
+    v->kind = Value::Number;
+    v->num = d;
+  }
   void string(std::string* out) {
     // caller consumed the opening quote
     while (i_ < s_.size() && s_[i_] != '"') {
@@ -77,16 +126,24 @@ class Parser {
           case 'r': c = '\r'; break;
           case 'b': c = '\b'; break;
           case 'f': c = '\f'; break;
-          case 'u':  // keep ASCII only; other code points become '?'
-            if (i_ + 4 <= s_.size()) {
-              long cp = std::strtol(s_.substr(i_, 4).c_str(), nullptr, 16);
-              c = cp < 128 ? (char)cp : '?';
-              i_ += 4;
-            } else {
-              ok_ = false;
+          case 'u': {  // exactly four hex digits; ASCII kept, other code points become '?'
+            long cp = 0;
+            for (int d = 0; d < 4; ++d) {
+              const int h = i_ + d < s_.size() ? hexval(s_[i_ + d]) : -1;
+              if (h < 0) {
+                ok_ = false;
+                return;
+              }
+              cp = cp * 16 + h;
             }
+            i_ += 4;
+            c = cp < 128 ? (char)cp : '?';
             break;
-          default: c = e;
+          }
+          case '"': case '\\': case '/': c = e; break;
+          default:  // not a JSON escape
+            ok_ = false;
+            return;
         }
       }
       out->push_back(c);
@@ -149,15 +206,7 @@ class Parser {
     } else if (lit("null")) {
       v->kind = Value::Null;
     } else {
-      const char* start = s_.c_str() + i_;
-      char* end = nullptr;
-      v->num = std::strtod(start, &end);
-      if (end == start) {
-        ok_ = false;
-        return;
-      }
-      v->kind = Value::Number;
-      i_ += (size_t)(end - start);
+      number(v);
     }
   }
 };

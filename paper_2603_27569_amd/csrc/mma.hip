@@ -1,7 +1,7 @@
 // Radix-16 Stockham passes whose 16-point DFTs run on the matrix cores
-// (the paper's Section VI matrix-multiply DFT idea and its future-work item
-// on combining it with half-precision storage, Section VIII), for N = 4096
-// with binary16 or bfloat16 storage.
+// (the paper's matrix-multiply DFT of Sections V-C and VII-C, and its
+// future-work items on batched matrix-core FFTs and mixed precision,
+// Section IX-A), for N = 512 ... 16384 with binary16 or bfloat16 storage.
 //
 // One pass is 256 butterflies of 16 legs.  Written as real arithmetic, a
 // 16-point DFT is a 32 x 32 matrix M acting on the 32 reals of a butterfly

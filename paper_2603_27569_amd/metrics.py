@@ -71,6 +71,23 @@ def gate(y, ref, x, rel_gate=REL_RMS_GATE, abs_gate=None):
         float(ratio.max(initial=0.0))
 
 
+GRAD_REL_GATE = 1e-4
+
+
+def grad_gate(g, ref, rel_gate=GRAD_REL_GATE):
+    """Gradient gate, row by row: every row b must satisfy
+    ||g_b - ref_b||_2 / ||ref_b||_2 <= rel_gate (1e-4 against the analytic
+    FP64 F^H g), and the rows must also pass the transform gate of `gate`
+    taken against the reference gradient itself (rel-RMS <= 5e-6 and max-abs
+    <= 1e-5 ||ref_b||_2), since the gradient is two FP32 transforms deep.
+    A row whose reference is exactly zero must come out exactly zero.
+    Returns (ok, worst_row_rel, worst_abs_ratio)."""
+    rel, _, _ = per_row_errors(g, ref, ref)
+    ok_t, _, _, ab = gate(g, ref, ref)
+    ok = bool(np.all(rel <= rel_gate) and ok_t)
+    return ok, float(rel.max(initial=0.0)), float(ab)
+
+
 # 16-bit storage: unit roundoff of one rounding to the format.
 STORAGE_UNIT_ROUNDOFF = {"f16": 2.0 ** -11, "bf16": 2.0 ** -8}
 

@@ -376,3 +376,61 @@ def test_tune_table_set_query_load(tmp_path):
         assert sf.fft_tune_query(2048, 5) == "n2048_e8_b1_p4_r8.8.8.4"
     finally:
         sf.fft_tune_clear()
+
+
+def test_tune_file_malformed_documents_and_fields(tmp_path):
+    """Tune files outside JSON's grammar are refused whole; entries whose
+    numbers are not integers in range are skipped; a malformed "arch" or
+    "cus" refuses the file (no device needed for these checks)."""
+    sf.fft_tune_clear()
+    try:
+        base = sf.fft_tune_query(2048, 5)
+        bad = tmp_path / "bad.json"
+        docs = [
+            '{"entries": [{"n": 2048, "batch_min": NaN, "variant": "x"}]}',  # not JSON
+            '{"entries": [{"n": 2048, "batch_min": Infinity}]}',
+            '{"entries": [{"n": 2048, "batch_min": 1e400}]}',  # overflows double
+            '{"entries": [{"n": 0x800}]}',
+            '{"entries": [{"n": +2048}]}',
+            '{"entries": [{"n": 2048.}]}',
+            '{"arch": "gfx9\\u00zz"}',  # bad escape digits
+            '{"arch": "gfx9\\u12"}',  # truncated escape
+            '{"arch": "gfx\\q950"}',  # not a JSON escape
+            '{"entries": [' * 100 + ']' * 100 + '}',  # 100-deep nesting
+            '{"entries": [{"n": 2048, "variant": "n2048_e8_b1_p4_r8.8.8.4"}',  # truncated
+            '{"arch": ""}',  # empty arch
+            '{"arch": ":sramecc+"}',
+            '{"arch": 950}',
+            '{"cus": 0}', '{"cus": -256}', '{"cus": 2.5}', '{"cus": "256"}',
+        ]
+        for text in docs:
+            bad.write_text(text)
+            with pytest.raises(sf.StockfftError) as e:
+                sf.fft_tune_load(str(bad))
+            assert e.value.name == "FFT_INVALID_ARGUMENT", text
+        good = "n2048_e16_b1_p4_r16.16.8"
+        entries = [
+            {"n": 2048, "batch_min": -5, "batch_max": 10, "variant": good},
+            {"n": 2048, "batch_min": 0, "batch_max": 10, "variant": good},
+            {"n": 2048, "batch_min": 1.5, "batch_max": 10, "variant": good},
+            {"n": 2048, "batch_min": 9, "batch_max": 3, "variant": good},
+            {"n": 2048.5, "batch_min": 1, "batch_max": 10, "variant": good},
+            {"n": -2048, "batch_min": 1, "batch_max": 10, "variant": good},
+            {"n": 2048, "batch_min": 1, "batch_max": -1e30, "variant": good},
+            {"n": 2048, "batch_min": "1", "batch_max": 10, "variant": good},
+        ]
+        p = tmp_path / "skip.json"
+        p.write_text(json.dumps({"arch": "gfx950:sramecc+:xnack-", "cus": 256, "entries": entries,
+                                 "filter_entries": entries, "fused_entries": entries,
+                                 "ragged": [{"n": 2048.5, "shape": "ragged_n2048_e16"}]}))
+        sf.fft_tune_load(str(p))  # loads, every entry skipped
+        assert sf.fft_tune_query(2048, 5) == base
+        # a huge batch_max saturates (the tuner's unbounded bucket is 2^62)
+        p.write_text(json.dumps({"entries": [
+            {"n": 2048, "batch_min": 1, "batch_max": 1e19, "variant": good}]}))
+        sf.fft_tune_load(str(p))
+        assert sf.fft_tune_query(2048, 5) == good
+        assert sf.fft_tune_query(2048, 2 ** 62) == good
+    finally:
+        sf.fft_tune_clear()
+        sf.fft_tune_clear_ragged()
