@@ -24,7 +24,7 @@ here are against numpy's FP64 FFT (an independent library routine); the
 parity tests against the oracle are the test suite's job.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-compare]
-                       [--skip-cpu] [--sweep]
+                       [--skip-cpu] [--sweep] [--timeline]
 """
 import argparse
 import hashlib
@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--sweep", action="store_true")
+    ap.add_argument("--timeline", action="store_true",
+                    help="only the per-wave phase timeline of the headline shape's variants")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -136,6 +138,10 @@ def main():
     T = Timer(torch, stream)
     props = torch.cuda.get_device_properties(dev)
     log(f"device {props.name} {props.gcnArchName} CUs={props.multi_processor_count}")
+
+    if args.timeline:
+        print(json.dumps({"timeline": run_timeline(torch, np, sf, dev, cs)}), flush=True)
+        return
 
     # ------------------------------------------------------------ headline
     n, b = N_HEAD, B_HEAD
@@ -199,18 +205,39 @@ def main():
                 "avg_launch_us": round(t_kernel * 1e6, 3)}
 
     # ----------------------------------------------------- reference kernels
+    # Hand-written HIP references (libstockref.so), launched through ctypes on
+    # the bench stream like the transform: an empty kernel in the headline's
+    # launch shape, a copy of the same bytes in that shape (one workgroup of
+    # 256 lanes per row, the transform's streaming 8-byte accesses), the same
+    # bytes in a wide grid (16-byte accesses), and a large copy for the
+    # device's practical HBM rate.
+    from paper_2603_27569_amd import reference as ref
     refs = {}
     cp_src = [xs[j] for j in range(K)]
     cp_dst = [ys[j] for j in range(K)]
-    t_copy = T.run(lambda i: cp_dst[i % K].copy_(cp_src[i % K]), args.steps, args.warmup) / args.steps
-    refs["device_copy_same_bytes"] = {"us": round(t_copy * 1e6, 3),
-                                      "GBs": round(bytes_launch / t_copy / 1e9, 1)}
-    # The same launch-bound shape as a plain device copy: how close the FFT
-    # comes to moving its bytes with no arithmetic at all.
+    t_empty = median_of(T, lambda i: ref.empty(b, 256, cs), args.steps, args.warmup)
+    t_copy = median_of(T, lambda i: ref.copy_rows(cp_src[i % K].data_ptr(), cp_dst[i % K].data_ptr(),
+                                                  n, b, 256, cs), args.steps, args.warmup)
+    t_wide = median_of(T, lambda i: ref.copy_wide(cp_src[i % K].data_ptr(), cp_dst[i % K].data_ptr(),
+                                                  slot_bytes, cs), args.steps, args.warmup)
+    refs["empty_kernel_same_grid_us"] = round(t_empty * 1e6, 3)
+    refs["copy_same_grid"] = {"us": round(t_copy * 1e6, 3),
+                              "GBs": round(bytes_launch / t_copy / 1e9, 1),
+                              "shape": f"{b} workgroups x 256 lanes, 8-byte streaming accesses"}
+    refs["copy_wide_grid_same_bytes"] = {"us": round(t_wide * 1e6, 3),
+                                         "GBs": round(bytes_launch / t_wide / 1e9, 1)}
+    big = 256 << 20
+    bsrc = torch.empty(big // 8, dtype=torch.complex64, device=dev)
+    bdst = torch.empty_like(bsrc)
+    t_big = median_of(T, lambda i: ref.copy_wide(bsrc.data_ptr(), bdst.data_ptr(), big, cs),
+                      max(20, args.steps // 10), 5)
+    refs["copy_wide_256MiB"] = {"us": round(t_big * 1e6, 3), "GBs": round(2 * big / t_big / 1e9, 1)}
+    del bsrc, bdst
+    # How close the transform comes to moving its bytes with no arithmetic in
+    # the same launch shape.
     roofline["frac_of_same_size_copy"] = round(t_copy / t_kernel, 4)
-    tiny = torch.zeros(1, device=dev)
-    t_min = T.run(lambda i: tiny.add_(1.0), args.steps, args.warmup) / args.steps
-    refs["minimal_kernel_us"] = round(t_min * 1e6, 3)
+    roofline["copy_same_grid_us"] = round(t_copy * 1e6, 3)
+    log("references", refs)
 
     # ------------------------------------------------------------ comparisons
     comps = {}
@@ -302,10 +329,9 @@ def compare(args, torch, np, sf, metrics, workloads, T, dev, cs):
     n, b = 4096, 512
     x_h, w_h = workloads.spectral_energy_inputs(n, b)
     K = ring_count(2 * n * b * 8)
+    from paper_2603_27569_amd import reference as ref
     x0 = torch.from_numpy(x_h).to(dev)
     w = torch.from_numpy(w_h).to(dev)
-    w2x2 = (2.0 * w * w).to(torch.complex64)
-    w2 = (w * w)
     xs = [x0] + [torch.randn(b, n, dtype=torch.complex64, device=dev) for _ in range(K - 1)]
     gs = [torch.empty_like(x0) for _ in range(K)]
     ys = [torch.empty_like(x0) for _ in range(K)]
@@ -319,11 +345,12 @@ def compare(args, torch, np, sf, metrics, workloads, T, dev, cs):
         sf.fft_exec_spectral_energy(pf.handle, xs[j].data_ptr(), w.data_ptr(), 0, gs[j].data_ptr(),
                                     rows.data_ptr(), total.data_ptr(), cs)
 
+    # The unfused chain: three HIP kernels (forward, the weight step with the
+    # row losses, adjoint); the fused call also writes the loss total.
     def chain(i):
         j = i % K
         pf.exec(xs[j].data_ptr(), ys[j].data_ptr(), cs)
-        total.copy_(torch.sum(w2 * (ys[j].real ** 2 + ys[j].imag ** 2)).reshape(1))
-        ys[j].mul_(w2x2)
+        ref.weight_energy(ys[j].data_ptr(), w.data_ptr(), rows.data_ptr(), n, b, cs)
         pb.exec(ys[j].data_ptr(), gs[j].data_ptr(), cs)
 
     def launches_only(i):
@@ -475,8 +502,8 @@ def compare_matched(torch, np, sf, metrics, workloads, T, dev, cs, iters, warm):
                                             for _ in range(K - 1)]
     ys = [torch.empty_like(xs[0]) for _ in range(K)]
     zs = [torch.empty_like(xs[0]) for _ in range(K)]
+    from paper_2603_27569_amd import reference as ref
     h = torch.from_numpy(h_h).to(dev)
-    hc_over_n = (h.conj() / n).resolve_conj()
     pf = sf.Plan(n, b, sf.FFT_FORWARD, sf.FFT_ALGO_SINGLE_PASS)
     pb = sf.Plan(n, b, sf.FFT_BACKWARD, sf.FFT_ALGO_SINGLE_PASS)
 
@@ -484,10 +511,12 @@ def compare_matched(torch, np, sf, metrics, workloads, T, dev, cs, iters, warm):
         j = i % K
         sf.fft_exec_matched_filter(pf.handle, xs[j].data_ptr(), h.data_ptr(), zs[j].data_ptr(), cs)
 
+    # The unfused chain: three HIP kernels (forward, multiply by conj(h) / n,
+    # backward).
     def chain(i):
         j = i % K
         pf.exec(xs[j].data_ptr(), ys[j].data_ptr(), cs)
-        ys[j].mul_(hc_over_n)
+        ref.filter_multiply(ys[j].data_ptr(), h.data_ptr(), n, b, cs)
         pb.exec(ys[j].data_ptr(), zs[j].data_ptr(), cs)
 
     def two(i):
@@ -590,6 +619,68 @@ def compare_ragged(args, torch, np, sf, metrics, workloads, T, dev, cs, iters, w
             "plain_graph_matches_eager": bool(graph_matches_eager),
             "speedup": round(t_p / t_r, 3), "speedup_vs_plain_graph": round(t_pg / t_r, 3), "persistent_GBs_algorithmic": round(16 * total / t_r / 1e9, 1),
             "persistent_gflops": round(flops / t_r / 1e9, 1), "worst_rel_rms": worst, "gates_pass": bool(ok)}
+
+
+def phase_names(passes):
+    names = ["input loads"]
+    for p in range(passes):
+        names.append(f"pass {p + 1}")
+        if p + 1 < passes:
+            names.append(f"exchange {p + 1}")
+    return names + ["stores issued", "stores completed"]
+
+
+def run_timeline(torch, np, sf, dev, cs, reps=20):
+    """Per-wave phase times of the single-pass transform at N=4096 x 256 for
+    each variant the reference library stamps (libstockref.so ref_timeline):
+    medians over every wave of `reps` launches on ring-rotated inputs.  Phase
+    durations come from the shader clock, scaled to microseconds by its
+    ratio to the 100 MHz real-time counter over each wave's life; the start
+    skew and the span are taken from the real-time counter (one clock for
+    the whole chip)."""
+    from paper_2603_27569_amd import reference as ref
+    n, b = N_HEAD, B_HEAD
+    K = ring_count(2 * n * b * 8)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(77)
+    xs = [torch.randn(b, n, dtype=torch.complex64, device=dev, generator=gen) for _ in range(K)]
+    ys = [torch.empty_like(xs[0]) for _ in range(K)]
+    out = {}
+    by_name = {v["name"]: i for i, v in enumerate(sf.variants())}
+    for name in ref.timeline_variants():
+        d = sf.fft_variant_describe(by_name[name])
+        waves = d["threads"] // 64
+        tw = torch.from_numpy(sf.fft_variant_twiddles(by_name[name])).to(dev)
+        st = torch.zeros(b * waves * 32, dtype=torch.int64, device=dev)
+        rows = []
+        for r in range(reps + 3):
+            j = r % K
+            ref.timeline(name, xs[j].data_ptr(), ys[j].data_ptr(), tw.data_ptr(), b, False,
+                         st.data_ptr(), cs)
+            torch.cuda.synchronize()
+            if r >= 3:  # the first launches warm the code and the tables
+                rows.append(st.view(b * waves, 32).cpu().numpy().copy())
+        a = np.concatenate(rows).astype(np.float64)
+        last = 2 * d["passes"] + 2
+        rt, ct = a[:, :last + 1], a[:, 16:16 + last + 1]
+        ratio = (ct[:, last] - ct[:, 0]) / ((rt[:, last] - rt[:, 0]) * 0.01)  # cycles per us
+        dur = np.diff(ct, axis=1) / ratio[:, None]
+        names = phase_names(d["passes"])
+        per_launch = np.split(rt, reps)
+        spans = [(x[:, last].max() - x[:, 0].min()) * 0.01 for x in per_launch]
+        skews = [(x[:, 0].max() - x[:, 0].min()) * 0.01 for x in per_launch]
+        life = (rt[:, last] - rt[:, 0]) * 0.01
+        out[name] = {
+            "waves_per_workgroup": waves,
+            "phase_us_median": {k: round(float(np.median(dur[:, i])), 3) for i, k in enumerate(names)},
+            "phase_us_p90": {k: round(float(np.percentile(dur[:, i], 90)), 3) for i, k in enumerate(names)},
+            "wave_life_us_median": round(float(np.median(life)), 3),
+            "start_skew_us_median": round(float(np.median(skews)), 3),
+            "first_start_to_last_end_us_median": round(float(np.median(spans)), 3),
+            "shader_clock_mhz_median": round(float(np.median(ratio)), 1),
+        }
+        log("timeline", name, out[name])
+    return out
 
 
 def run_sweep(args, torch, sf, metrics, T, dev, cs):

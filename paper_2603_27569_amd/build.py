@@ -1,8 +1,9 @@
-"""Build the HIP library libstockfft.so in-tree for gfx950.
+"""Build the HIP libraries in-tree for gfx950.
 
 Every translation unit under csrc/ is compiled with hipcc (in parallel) and
-linked into paper_2603_27569_amd/libstockfft.so.  Packed FP32 instructions
-are disabled for all device code.
+linked into paper_2603_27569_amd/libstockfft.so; refsrc/ (measurement
+references, not part of the transform path) into libstockref.so.  Packed
+FP32 instructions are disabled for all device code.
 """
 import concurrent.futures as cf
 import os
@@ -13,6 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libstockfft.so")
+REFSRC = os.path.join(HERE, "refsrc")
+REFLIB = os.path.join(HERE, "libstockref.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -35,7 +38,8 @@ def sources():
 
 
 def _compile(src):
-    obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+    sub = os.path.basename(os.path.dirname(src))
+    obj = os.path.join(BUILD_DIR, sub + "_" + os.path.basename(src) + ".o")
     lang = ["-x", "hip"] if src.endswith(".cpp") else []
     cmd = [HIPCC, *FLAGS, *EXTRA.get(os.path.basename(src), []), *lang, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -44,16 +48,24 @@ def _compile(src):
     return obj
 
 
-def build(jobs=None):
-    os.makedirs(BUILD_DIR, exist_ok=True)
-    srcs = sources()
-    jobs = jobs or min(len(srcs), max(1, min(8, os.cpu_count() or 1)))
-    with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
+def _link(objs, lib):
+    tmp = lib + ".tmp"
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
+
+
+def build(jobs=None):
+    """Compiles libstockfft.so (csrc/) and the measurement references
+    libstockref.so (refsrc/, which the transform library never loads)."""
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    srcs = sources()
+    refs = [os.path.join(REFSRC, f) for f in sorted(os.listdir(REFSRC)) if f.endswith(".hip")]
+    jobs = jobs or min(len(srcs) + len(refs), max(1, min(8, os.cpu_count() or 1)))
+    with cf.ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(_compile, srcs + refs))
+    _link(objs[:len(srcs)], LIB)
+    _link(objs[len(srcs):], REFLIB)
     return LIB
 
 

@@ -377,20 +377,31 @@ __device__ __forceinline__ void exchange(c32 (&a)[S::E], c32* lds, int t) {
     __syncthreads();  // all reads done before the next overwrite
 }
 
+// Phase marks of the pass pipeline.  The product kernels take NoProbe,
+// whose marks compile to nothing; a timeline probe records a clock reading
+// at each mark: mark 2p + 1 after pass p's arithmetic, 2p + 2 after the
+// exchange that follows it.
+struct NoProbe {
+  static constexpr bool on = false;
+  __device__ __forceinline__ void mark(int) {}
+};
+
 // Runs passes p..P-1.  On entry a[] holds the pass-p inputs in the register
 // convention (and, with prefetch, w[] the pass-p twiddles).  On exit a[]
 // holds the transform in natural order, a[m] at position t + m T.  The
 // exchange buffer must be free to overwrite on entry (the caller's barrier).
-template <class S, int p, bool INV>
+template <class S, int p, bool INV, class Pr>
 __device__ __forceinline__ void run_passes_from(c32 (&a)[S::E], c32 (&w)[S::TW_REGS], c32* lds,
-                                                const c32* tw, int t) {
+                                                const c32* tw, int t, Pr* pr) {
   pass_compute<S, p, INV>(a, w, tw, t);
+  if constexpr (Pr::on) pr->mark(2 * p + 1);
   if constexpr (p + 1 < S::P) {
     if constexpr (double_buffered<S>::value)
       exchange<S, p>(a, lds + (p & 1) * S::BUF, t);
     else
       exchange<S, p>(a, lds, t);
-    run_passes_from<S, p + 1, INV>(a, w, lds, tw, t);
+    if constexpr (Pr::on) pr->mark(2 * p + 2);
+    run_passes_from<S, p + 1, INV>(a, w, lds, tw, t, pr);
   }
 }
 
@@ -404,12 +415,12 @@ __device__ __forceinline__ void load_all_twiddles(c32 (&w)[S::TW_REGS], const c3
   }
 }
 
-template <class S, bool INV>
+template <class S, bool INV, class Pr = NoProbe>
 __device__ __forceinline__ void run_passes(c32 (&a)[S::E], c32* lds, const c32* tw,
-                                           int t) {
+                                           int t, Pr* pr = nullptr) {
   c32 w[S::TW_REGS];
   if constexpr (S::PF == 2) load_all_twiddles<S, 1>(w, tw, t);
-  run_passes_from<S, 0, INV>(a, w, lds, tw, t);
+  run_passes_from<S, 0, INV>(a, w, lds, tw, t, pr);
 }
 
 }  // namespace stockfft

@@ -434,3 +434,43 @@ def test_tune_file_malformed_documents_and_fields(tmp_path):
     finally:
         sf.fft_tune_clear()
         sf.fft_tune_clear_ragged()
+
+
+def test_reference_library_exports_its_header():
+    from paper_2603_27569_amd import reference
+    header = os.path.join(ROOT, "include", "stockref.h")
+    text = re.sub(r"/\*.*?\*/", "", open(header).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(ref_[a-z_]+)\s*\(", text)))
+    assert sorted(reference.SIGNATURES) == names
+    L = reference.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", reference.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    assert set(names) <= set(re.findall(r" T (ref_[a-z_]+)$", out, flags=re.M))
+    # the transform library does not carry the references
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True).stdout
+    assert not re.findall(r" T (ref_[a-z_]+)$", out, flags=re.M)
+    assert reference.timeline_variants()[0] == "n4096_e16_b1_px_r16.16.16_db"
+
+
+def test_reference_calls_reject_bad_arguments_before_any_device_call():
+    from paper_2603_27569_amd import reference as R
+    L = R.lib()
+    codes = _lib.CODES
+    vp = ctypes.c_void_p
+    assert L.ref_empty(0, 64, None) == codes["FFT_INVALID_ARGUMENT"]
+    assert L.ref_empty(1, 2048, None) == codes["FFT_INVALID_ARGUMENT"]
+    assert L.ref_copy_rows(None, vp(64), 4096, 1, 256, None) == codes["FFT_INVALID_POINTER"]
+    assert L.ref_copy_rows(vp(64), vp(1 << 30), 4096, 1, 128, None) == codes["FFT_INVALID_ARGUMENT"]
+    assert L.ref_copy_rows(vp(68), vp(1 << 30), 4096, 1, 256, None) == codes["FFT_MISALIGNED"]
+    assert L.ref_copy_rows(vp(64), vp(64 + 8), 4096, 1, 256, None) == codes["FFT_OVERLAP"]
+    assert L.ref_copy_wide(vp(64), vp(1 << 30), 24, None) == codes["FFT_INVALID_ARGUMENT"]
+    assert L.ref_copy_wide(vp(72), vp(1 << 30), 32, None) == codes["FFT_MISALIGNED"]
+    assert L.ref_weight_energy(vp(64), vp(64), vp(64), 300, 1, None) == codes["FFT_INVALID_ARGUMENT"]
+    assert L.ref_filter_multiply(vp(64), None, 256, 1, None) == codes["FFT_INVALID_POINTER"]
+    assert L.ref_timeline(b"nope", vp(64), vp(1 << 30), vp(64), 1, 0, vp(64), None) == \
+        codes["FFT_INVALID_ARGUMENT"]
+    assert L.ref_timeline(b"n4096_e16_b1_px_r16.16.16_db", vp(64), vp(1 << 30), vp(64), 1, 2,
+                          vp(64), None) == codes["FFT_INVALID_ARGUMENT"]
