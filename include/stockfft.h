@@ -180,6 +180,31 @@ int fft_exec_spectral_energy(fft_plan_t plan, const void *x, const float *w,
                              float *loss_total, void *stream);
 
 /*
+ * fft_exec_spectral_energy_noalloc -- fft_exec_spectral_energy for callers
+ * that cannot allocate device memory around the call (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the
+ * per-row losses and the arrival counters of the loss total live in a
+ * static device array of the library instead of a caller buffer and the
+ * plan's counters.  The array is 4 MiB + 4 KiB, one copy on each GPU the
+ * call runs on, held until the process ends; the first call on a GPU looks
+ * up its address and clears its counters with a small kernel on `stream`.
+ *   plan, x, w, grad_scale, grad_x, stream   as fft_exec_spectral_energy.
+ *   loss_total  device, one float32 receiving sum_b of the row losses
+ *               (required; the row losses themselves are not returned).
+ * The plan's batch must be at most 1048576 rows (FFT_INVALID_ARGUMENT).
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (two streams without ordering, two host threads) race, and the
+ * caller must order them.  Allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine); asynchronous.
+ * Errors: FFT_INVALID_PLAN, FFT_INVALID_POINTER, FFT_INVALID_ARGUMENT,
+ * FFT_MISALIGNED, FFT_OVERLAP, FFT_UNSUPPORTED (backward or four-step
+ * plan), FFT_HIP_ERROR.
+ */
+int fft_exec_spectral_energy_noalloc(fft_plan_t plan, const void *x, const float *w,
+                                     const float *grad_scale, void *grad_x, float *loss_total,
+                                     void *stream);
+
+/*
  * fft_exec_matched_filter -- fused range compression (the paper's future
  * work on SAR pipeline fusion, Section IX-A): out_b = F^{-1}(conj(h) .* F x_b)
  * with F^{-1} = backward / N, in one kernel.

@@ -31,7 +31,7 @@ __all__ = [
     "FFT_IO_BC16_MMA", "StockfftError", "STATUS",
     "CODES",
     "fft_plan", "fft_plan_config", "fft_exec", "fft_destroy",
-    "fft_exec_spectral_energy", "fft_exec_matched_filter",
+    "fft_exec_spectral_energy", "fft_exec_spectral_energy_noalloc", "fft_exec_matched_filter",
     "fft_exec_io", "fft_lowp",
     "fft_plan_ragged", "fft_exec_ragged", "fft_exec_ragged_direct", "fft_exec_ragged_plain",
     "fft_destroy_ragged",
@@ -78,6 +78,11 @@ def fft_exec_spectral_energy(plan, x, w, grad_scale, grad_x, row_loss, loss_tota
     return check("fft_exec_spectral_energy", lib().fft_exec_spectral_energy(
         _vp(plan), _vp(x), _vp(w), _vp(grad_scale), _vp(grad_x), _vp(row_loss),
         _vp(loss_total), _vp(stream)))
+
+
+def fft_exec_spectral_energy_noalloc(plan, x, w, grad_scale, grad_x, loss_total, stream=0):
+    return check("fft_exec_spectral_energy_noalloc", lib().fft_exec_spectral_energy_noalloc(
+        _vp(plan), _vp(x), _vp(w), _vp(grad_scale), _vp(grad_x), _vp(loss_total), _vp(stream)))
 
 
 def fft_exec_matched_filter(plan, x, h, out, stream=0):

@@ -42,6 +42,7 @@ SIGNATURES = {
     "fft_exec": (_int, [_vp, _vp, _vp, _vp]),
     "fft_destroy": (_int, [_vp]),
     "fft_exec_spectral_energy": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "fft_exec_spectral_energy_noalloc": (_int, [_vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "fft_exec_matched_filter": (_int, [_vp, _vp, _vp, _vp, _vp]),
     "fft_plan_ragged": (_int, [_pvp, ctypes.POINTER(_i64), _i64, _int]),
     "fft_exec_ragged": (_int, [_vp, _vp, _vp, _vp]),

@@ -744,6 +744,88 @@ extern "C" int fft_exec_spectral_energy(fft_plan_t plan, const void* x, const fl
   return e == hipSuccess ? FFT_SUCCESS : hip_fail(e);
 }
 
+// ------------------------------------------ allocation-free fused entry
+//
+// fft_exec_spectral_energy_noalloc keeps the per-row losses and the arrival
+// counters of the loss total in this array instead of a caller buffer and
+// the plan's counters: kNoAllocMaxRows floats, then the counters on their
+// own 256-byte lines.  One copy per GPU, held until the process ends.
+namespace {
+constexpr int64_t kNoAllocMaxRows = int64_t(1) << 20;
+constexpr size_t kNoAllocLossBytes = (size_t)kNoAllocMaxRows * sizeof(float);
+constexpr size_t kNoAllocCounterWords = (size_t)kTotalGroups * 64 + 1;
+constexpr size_t kNoAllocScratchBytes =
+    kNoAllocLossBytes + (kNoAllocCounterWords * sizeof(unsigned) + 255) / 256 * 256;
+constexpr int kMaxDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+namespace {
+
+// Zeroes n words (a fill kernel rather than a memset, so a caller may
+// capture it into a graph).
+__global__ void k_zero_words(unsigned* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];     // device address of `scratch` on each device
+bool g_scratch_cleared[kMaxDevices];  // counters zeroed by a launch on that device
+
+// The device address of `scratch` on the current device `dev`, looked up
+// once per device; on the first call the counters are cleared on `s` (they
+// come back to zero after every complete call).
+int scratch_for_device(int dev, hipStream_t s, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return FFT_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol);
+    g_scratch_ptr[dev] = ptr;
+  }
+  unsigned char* base = static_cast<unsigned char*>(g_scratch_ptr[dev]);
+  if (!g_scratch_cleared[dev]) {
+    k_zero_words<<<dim3((unsigned)((kNoAllocCounterWords + 255) / 256)), dim3(256), 0, s>>>(
+        reinterpret_cast<unsigned*>(base + kNoAllocLossBytes), (int)kNoAllocCounterWords);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e);
+    g_scratch_cleared[dev] = true;
+  }
+  *out = base;
+  return FFT_SUCCESS;
+}
+
+}  // namespace
+
+extern "C" int fft_exec_spectral_energy_noalloc(fft_plan_t plan, const void* x, const float* w,
+                                                const float* grad_scale, void* grad_x,
+                                                float* loss_total, void* stream) {
+  if (!plan || !live_handle(plan)) return FFT_INVALID_PLAN;
+  const SingleVariant* fv = plan->sv_fused;
+  if (plan->direction != FFT_FORWARD || plan->algorithm != FFT_ALGO_SINGLE_PASS || !fv)
+    return FFT_UNSUPPORTED;
+  if (!x || !w || !loss_total) return FFT_INVALID_POINTER;
+  if (plan->batch > kNoAllocMaxRows) return FFT_INVALID_ARGUMENT;
+  if (!aligned8(x) || (grad_x && !aligned8(grad_x)) || ((uintptr_t)w & 3u) ||
+      (grad_scale && ((uintptr_t)grad_scale & 3u)) || ((uintptr_t)loss_total & 3u))
+    return FFT_MISALIGNED;
+  const size_t bytes = (size_t)plan->n * (size_t)plan->batch * 8;
+  if (grad_x && ranges_partially_overlap(x, grad_x, bytes)) return FFT_OVERLAP;
+  DeviceGuard g(plan->device);
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char* base = nullptr;
+  const int rc = scratch_for_device(plan->device, s, &base);
+  if (rc) return rc;
+  float* row_loss = reinterpret_cast<float*>(base);
+  unsigned* counters = reinterpret_cast<unsigned*>(base + kNoAllocLossBytes);
+  const hipError_t e = fv->fused(x, w, grad_scale, grad_x, row_loss, loss_total, counters,
+                                 plan_table(plan, fv), plan->batch, s);
+  return e == hipSuccess ? FFT_SUCCESS : hip_fail(e);
+}
+
 extern "C" int fft_exec_matched_filter(fft_plan_t plan, const void* x, const void* h, void* out,
                                        void* stream) {
   if (!plan || !live_handle(plan)) return FFT_INVALID_PLAN;
