@@ -61,7 +61,7 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham(const c32* in, 
                                                          const c32* tw, int64_t rows) {
   __shared__ alignas(16) c32 lds_all[S::TPB * S::LDS_ELEMS];
   const int tid = threadIdx.x;
-  const int slot = tid / S::T;
+  const int slot = S::TPB == 1 ? 0 : tid / S::T;  // one transform: the row base is uniform
   const int t = tid - slot * S::T;
   const int64_t row = (int64_t)blockIdx.x * S::TPB + slot;
   const bool live = row < rows;
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham_io(const uint32
                                                                     int64_t rows) {
   __shared__ alignas(16) c32 lds_all[S::TPB * S::LDS_ELEMS];
   const int tid = threadIdx.x;
-  const int slot = tid / S::T;
+  const int slot = S::TPB == 1 ? 0 : tid / S::T;  // one transform: the row base is uniform
   const int t = tid - slot * S::T;
   const int64_t row = (int64_t)blockIdx.x * S::TPB + slot;
   const bool live = row < rows;
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_spectral_energy(
   __shared__ float red[(S::THREADS + 63) / 64];
   __shared__ int is_last;
   const int tid = threadIdx.x;
-  const int slot = tid / S::T;
+  const int slot = S::TPB == 1 ? 0 : tid / S::T;  // one transform: the row base is uniform
   const int t = tid - slot * S::T;
   const int64_t row = (int64_t)blockIdx.x * S::TPB + slot;
   const bool live = row < rows;
@@ -326,7 +326,7 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_matched_filter(const c32
                                                                int64_t rows) {
   __shared__ alignas(16) c32 lds_all[S::TPB * S::LDS_ELEMS];
   const int tid = threadIdx.x;
-  const int slot = tid / S::T;
+  const int slot = S::TPB == 1 ? 0 : tid / S::T;  // one transform: the row base is uniform
   const int t = tid - slot * S::T;
   const int64_t row = (int64_t)blockIdx.x * S::TPB + slot;
   const bool live = row < rows;

@@ -251,6 +251,55 @@ struct double_buffered : std::false_type {};
 template <class S>
 struct double_buffered<S, std::void_t<decltype(S::DB)>> : std::integral_constant<bool, S::DB> {};
 
+// Paired twiddle table: in every pass of radix R >= 4 the twiddles for
+// r = 2q + 1 and 2q + 2 sit side by side, entry [q][k] = (W^{k (2q + 1)},
+// W^{k (2q + 2)}) with W = W_{Ns R} (the last pair holds W^{k (R - 1)} and a
+// zero), so a lane fetches two twiddles with one 16-byte load: R/2 load
+// instructions per butterfly instead of R - 1.  For consecutive k the pairs
+// are consecutive, so a wave's load still covers whole cache lines.  Radix-2
+// passes keep the plain layout (one twiddle per butterfly).
+template <class Base>
+struct PairedTwiddles : Base {
+  static constexpr bool PT = true;
+  static constexpr int tw_pass_elems(int p) {
+    return p == 0 ? 0
+           : Base::radix(p) >= 4 ? (Base::radix(p) / 2) * 2 * Base::ns(p)
+                                 : (Base::radix(p) - 1) * Base::ns(p);
+  }
+  static constexpr int tw_off(int p) {
+    int o = 0;
+    for (int i = 1; i < p; ++i) o += tw_pass_elems(i);
+    return o;
+  }
+  static constexpr int TW_ELEMS = tw_off(Base::P);
+};
+
+template <class S, class = void>
+struct paired_twiddles : std::false_type {};
+template <class S>
+struct paired_twiddles<S, std::void_t<decltype(S::PT)>> : std::integral_constant<bool, S::PT> {};
+
+// The R - 1 twiddles of pass p for the butterfly with k = j mod Ns, from the
+// pass's table twp, into dst[off + 0 .. off + R - 2] (dst[off + r - 1] is the
+// twiddle of leg r; off is a constant once the caller's loops are unrolled).
+template <class S, int p, int CAP>
+__device__ __forceinline__ void fetch_twiddles(c32 (&dst)[CAP], int off, const c32* twp, int k) {
+  constexpr int R = S::radix(p);
+  constexpr int NS = S::ns(p);
+  static_assert(R - 1 <= CAP, "twiddle registers");
+  if constexpr (paired_twiddles<S>::value && R >= 4) {
+#pragma unroll
+    for (int q = 0; q < R / 2; ++q) {
+      const float4 v = *reinterpret_cast<const float4*>(twp + 2 * (q * NS + k));
+      dst[off + 2 * q] = c32{v.x, v.y};
+      if (2 * q + 1 < R - 1) dst[off + 2 * q + 1] = c32{v.z, v.w};
+    }
+  } else {
+#pragma unroll
+    for (int r = 1; r < R; ++r) dst[off + r - 1] = twp[(r - 1) * NS + k];
+  }
+}
+
 // The common case: whole-transform exchange buffer, twiddles one pass ahead.
 template <int N_, int E_, int TPB_, int PADLOG_, int... Rs>
 using Shape = ShapeX<1, true, 1, N_, E_, TPB_, PADLOG_, Rs...>;
@@ -270,8 +319,7 @@ __device__ __forceinline__ void load_twiddles(c32 (&w)[S::TW_REGS], const c32* t
 #pragma unroll
     for (int b = 0; b < BPT; ++b) {
       const int k = (t + b * S::T) & (NS - 1);
-#pragma unroll
-      for (int r = 1; r < R; ++r) w[S::tw_lane_off(p) + b * (R - 1) + (r - 1)] = twp[(r - 1) * NS + k];
+      fetch_twiddles<S, p>(w, S::tw_lane_off(p) + b * (R - 1), twp, k);
     }
     // Keep prefetched loads here: the scheduler would otherwise sink them to
     // their use, past the exchange barriers, and expose their latency.
@@ -297,10 +345,10 @@ __device__ __forceinline__ void pass_compute(c32 (&a)[S::E], c32 (&w)[S::TW_REGS
 #pragma unroll
       for (int r = 0; r < R; ++r) v[r] = a[b + r * BPT];
       if constexpr (p > 0) {
-        const c32* twp = tw + S::tw_off(p);
-        const int k = (t + b * S::T) & (NS - 1);
+        c32 wb[R - 1];
+        fetch_twiddles<S, p>(wb, 0, tw + S::tw_off(p), (t + b * S::T) & (NS - 1));
 #pragma unroll
-        for (int r = 1; r < R; ++r) v[r] = ctw<INV>(v[r], twp[(r - 1) * NS + k]);
+        for (int r = 1; r < R; ++r) v[r] = ctw<INV>(v[r], wb[r - 1]);
       }
       Dft<R, INV>::run(v);
 #pragma unroll

@@ -24,23 +24,42 @@ inline void root_f32(int64_t m, int64_t L, float* re, float* im) {
   *im = (float)std::sin(a);
 }
 
-// Per-pass tables of a Stockham plan with radices R_0 .. R_{npass-1}: for
-// pass p >= 1 with Ns = R_0 ... R_{p-1}, entry [r - 1][k] = W_{Ns R_p}^{k r},
-// r in [1, R_p), k in [0, Ns), appended pass after pass (interleaved re, im).
-inline void stockham_twiddles(const int* radix, int npass, std::vector<float>& out) {
+// Per-pass tables of a Stockham plan with radices R_0 .. R_{npass-1}, for
+// pass p >= 1 with Ns = R_0 ... R_{p-1} and W = W_{Ns R_p}, appended pass
+// after pass (interleaved re, im):
+//   plain   entry [r - 1][k] = W^{k r}, r in [1, R_p), k in [0, Ns);
+//   paired  for passes with R_p >= 4, entry [q][k][h] = W^{k (2q + 1 + h)},
+//           q in [0, R_p / 2), h in {0, 1}, k in [0, Ns), zero where
+//           2q + 1 + h = R_p; radix-2 passes as plain.
+inline void stockham_twiddles(const int* radix, int npass, bool paired, std::vector<float>& out) {
   out.clear();
   if (npass < 1) return;
   int64_t ns = radix[0];
+  auto put = [&](int64_t m, int64_t L) {
+    float re, im;
+    root_f32(m, L, &re, &im);
+    out.push_back(re);
+    out.push_back(im);
+  };
   for (int p = 1; p < npass; ++p) {
     const int R = radix[p];
     const int64_t L = ns * R;
-    for (int r = 1; r < R; ++r)
-      for (int64_t k = 0; k < ns; ++k) {
-        float re, im;
-        root_f32(k * r, L, &re, &im);
-        out.push_back(re);
-        out.push_back(im);
-      }
+    if (paired && R >= 4) {
+      for (int q = 0; q < R / 2; ++q)
+        for (int64_t k = 0; k < ns; ++k)
+          for (int h = 0; h < 2; ++h) {
+            const int r = 2 * q + 1 + h;
+            if (r < R) {
+              put(k * r, L);
+            } else {
+              out.push_back(0.0f);
+              out.push_back(0.0f);
+            }
+          }
+    } else {
+      for (int r = 1; r < R; ++r)
+        for (int64_t k = 0; k < ns; ++k) put(k * r, L);
+    }
     ns *= R;
   }
 }

@@ -18,6 +18,8 @@ SingleVariant make_variant(const char* name) {
   for (int i = 0; i < S::P; ++i) v.radix[i] = S::radix(i);
   v.chunks = S::C;
   v.double_buffered = double_buffered<S>::value;
+  v.twiddle_schedule = S::PF;
+  v.paired_twiddles = paired_twiddles<S>::value;
   v.threads = S::THREADS;
   v.lds_bytes = S::TPB * S::LDS_ELEMS * (int)sizeof(c32);
   v.tw_elems = S::TW_ELEMS;

@@ -45,6 +45,8 @@ struct SingleVariant {
   int radix[kMaxPasses];
   int chunks;  // exchange rounds per pass (the LDS holds N / chunks elements per transform)
   bool double_buffered;  // exchanges alternate between two LDS buffers
+  int twiddle_schedule;  // 0 at their pass, 1 one pass ahead, 2 all with the input
+  bool paired_twiddles;  // table layout: two twiddles per 16-byte entry (PairedTwiddles)
   int threads;
   int lds_bytes;
   int tw_elems;

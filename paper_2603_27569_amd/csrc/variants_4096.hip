@@ -3,6 +3,8 @@
 // larger register file, and the LDS-layout ablation (no pad / 1 in 16 / 1 in 32).
 #include "variant_maker.hpp"
 
+using stockfft::DoubleBuffered;
+using stockfft::PairedTwiddles;
 using stockfft::Shape;
 using stockfft::ShapeX;
 using stockfft::make_variant;
@@ -10,6 +12,7 @@ using stockfft::make_variant;
 STOCKFFT_VARIANT_GROUP(variants_4096,
   make_variant<Shape<4096, 4, 1, 4, 4, 4, 4, 4, 4, 4>>("n4096_e4_b1_p4_r4.4.4.4.4.4"),
   make_variant<Shape<4096, 8, 1, 4, 8, 8, 8, 8>>("n4096_e8_b1_p4_r8.8.8.8"),
+  make_variant<PairedTwiddles<Shape<4096, 8, 1, 4, 8, 8, 8, 8>>>("n4096_e8_b1_p4_r8.8.8.8_pt"),
   make_variant<Shape<4096, 16, 1, 4, 16, 16, 16>>("n4096_e16_b1_p4_r16.16.16"),
   make_variant<Shape<4096, 16, 1, 0, 16, 16, 16>>("n4096_e16_b1_p0_r16.16.16"),
   make_variant<Shape<4096, 16, 1, 5, 16, 16, 16>>("n4096_e16_b1_p5_r16.16.16"),
@@ -19,6 +22,12 @@ STOCKFFT_VARIANT_GROUP(variants_4096,
   make_variant<ShapeX<1, 2, 1, 4096, 16, 1, -1, 16, 16, 16>>("n4096_e16_b1_px_r16.16.16_tall"),
   make_variant<DoubleBuffered<Shape<4096, 16, 1, 5, 16, 16, 16>>>("n4096_e16_b1_p5_r16.16.16_db"),
   make_variant<DoubleBuffered<Shape<4096, 16, 1, -1, 16, 16, 16>>>("n4096_e16_b1_px_r16.16.16_db"),
+  // Paired twiddle tables (_pt): half the twiddle load instructions.
+  make_variant<DoubleBuffered<PairedTwiddles<Shape<4096, 16, 1, -1, 16, 16, 16>>>>("n4096_e16_b1_px_r16.16.16_db_pt"),
+  make_variant<PairedTwiddles<Shape<4096, 16, 1, -1, 16, 16, 16>>>("n4096_e16_b1_px_r16.16.16_pt"),
+  make_variant<PairedTwiddles<Shape<4096, 16, 1, 5, 16, 16, 16>>>("n4096_e16_b1_p5_r16.16.16_pt"),
+  make_variant<PairedTwiddles<Shape<4096, 32, 1, 4, 16, 16, 16>>>("n4096_e32_b1_p4_r16.16.16_pt"),
+  make_variant<PairedTwiddles<ShapeX<2, false, 4, 4096, 32, 1, 4, 16, 16, 16>>>("n4096_e32_c2_b1_p4_r16.16.16_pt"),
   make_variant<Shape<4096, 32, 1, 4, 16, 16, 16>>("n4096_e32_b1_p4_r16.16.16"),
   make_variant<Shape<4096, 32, 2, 4, 16, 16, 16>>("n4096_e32_b2_p4_r16.16.16"),
   // Two-round exchanges: half the LDS (17 KiB), so occupancy is set by the

@@ -172,6 +172,8 @@ hipError_t launch_timeline(const void* in, void* out, const void* tw, int64_t ba
 // The shapes of the N = 4096 variants of the library with one transform
 // per workgroup (names as fft_variant_describe gives them).
 const TimelineVariant kTimeline[] = {
+    {"n4096_e16_b1_px_r16.16.16_db_pt", 4096, 256,
+     &launch_timeline<DoubleBuffered<PairedTwiddles<Shape<4096, 16, 1, -1, 16, 16, 16>>>>},
     {"n4096_e16_b1_px_r16.16.16_db", 4096, 256,
      &launch_timeline<DoubleBuffered<Shape<4096, 16, 1, -1, 16, 16, 16>>>},
     {"n4096_e16_b1_px_r16.16.16", 4096, 256, &launch_timeline<Shape<4096, 16, 1, -1, 16, 16, 16>>},

@@ -39,18 +39,27 @@ static int twiddles() {
   long plans = 0;
   auto visit = [&](auto&& self, int64_t prod) -> void {
     if (!plan.empty()) {
-      stockham_twiddles(plan.data(), (int)plan.size(), out);
-      int64_t want = 0, ns = plan[0];
-      for (size_t p = 1; p < plan.size(); ++p) {
-        want += (plan[p] - 1) * ns;
-        ns *= plan[p];
+      for (int paired = 0; paired < 2; ++paired) {
+        stockham_twiddles(plan.data(), (int)plan.size(), paired == 1, out);
+        int64_t want = 0, ns = plan[0], pads = 0;
+        for (size_t p = 1; p < plan.size(); ++p) {
+          const bool pr = paired && plan[p] >= 4;
+          want += (pr ? plan[p] : plan[p] - 1) * ns;
+          pads += pr ? ns : 0;
+          ns *= plan[p];
+        }
+        if ((int64_t)out.size() != 2 * want) ++bad;
+        int64_t zeros = 0;
+        for (size_t i = 0; i + 1 < out.size(); i += 2) {
+          const double m = (double)out[i] * out[i] + (double)out[i + 1] * out[i + 1];
+          if (m == 0.0)
+            ++zeros;
+          else if (!(std::fabs(m - 1.0) < 1e-6))
+            ++bad;
+        }
+        if (zeros != pads) ++bad;
+        ++plans;
       }
-      if ((int64_t)out.size() != 2 * want) ++bad;
-      for (size_t i = 0; i + 1 < out.size(); i += 2) {
-        const double m = (double)out[i] * out[i] + (double)out[i + 1] * out[i + 1];
-        if (!(std::fabs(m - 1.0) < 1e-6)) ++bad;
-      }
-      ++plans;
     }
     if (plan.size() == 5) return;
     for (int r : radices) {

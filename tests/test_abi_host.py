@@ -292,26 +292,50 @@ def _ulp_err(tab, exact):
     return max(np.max(er / ur), np.max(ei / ui))
 
 
+def _stockham_expect(radices, paired):
+    """Exact table entries of a Stockham plan; None marks a pad (must be 0).
+    Plain layout [r - 1][k] = W^{k r}; paired layout (passes of radix >= 4)
+    [q][k][h] = W^{k (2q + 1 + h)}."""
+    expect = []
+    ns = radices[0]
+    for r_p in radices[1:]:
+        L = ns * r_p
+        if paired and r_p >= 4:
+            for q in range(r_p // 2):
+                for k in range(ns):
+                    for h in range(2):
+                        r = 2 * q + 1 + h
+                        expect.append(_exact_roots(k * r, L) if r < r_p else None)
+        else:
+            for r in range(1, r_p):
+                for k in range(ns):
+                    expect.append(_exact_roots(k * r, L))
+        ns *= r_p
+    return expect
+
+
 def test_twiddle_tables_rounded_once_from_fp64():
     """Every table entry is W_L^m rounded once to FP32: within half an ulp of
-    the exact root (plus FP64 evaluation slack)."""
+    the exact root (plus FP64 evaluation slack); pads of the paired layout are
+    exactly zero."""
     vs = _variants()
+    seen_paired = False
     for i, v in enumerate(vs):
         tab = sf.fft_variant_twiddles(i)
         if v["kind"] == "single":
             radices = v["radices"]
-            sub = None
+            paired = v["paired_twiddles"]
+            seen_paired |= paired
         else:
             sub = next(s for s in vs if s["name"] == v["sub_variant"])
             radices = sub["radices"]
-        expect = []
-        ns = radices[0]
-        for r_p in radices[1:]:
-            L = ns * r_p
-            for r in range(1, r_p):
-                for k in range(ns):
-                    expect.append(_exact_roots(k * r, L))
-            ns *= r_p
+            paired = sub["paired_twiddles"]
+        expect = _stockham_expect(radices, paired)
+        pads = np.array([e is None for e in expect] + [False] * (len(tab) - len(expect)))
+        if pads.shape == tab.shape and pads.any():
+            assert np.all(tab[pads] == 0), v["name"]
+            tab = tab[~pads]
+        expect = [e for e in expect if e is not None]
         if v["kind"] == "four_step" and not v["two_level_twiddles"]:
             N = v["n"]
             for n1 in range(1, v["n1"]):
@@ -326,16 +350,12 @@ def test_twiddle_tables_rounded_once_from_fp64():
             expect += [_exact_roots(j, v["n1"]) for j in range(v["n1"])]
             if v["sub2_variant"]:  # the second stage's own N1-point table
                 sub2 = next(s for s in vs if s["name"] == v["sub2_variant"])
-                assert sub2["n"] == v["n1"]
-                r2 = sub2["radices"]
-                ns = r2[0]
-                for r_p in r2[1:]:
-                    for r in range(1, r_p):
-                        expect += [_exact_roots(k * r, ns * r_p) for k in range(ns)]
-                    ns *= r_p
+                assert sub2["n"] == v["n1"] and not sub2["paired_twiddles"]
+                expect += _stockham_expect(sub2["radices"], False)
         expect = np.array(expect)
         assert tab.shape == expect.shape, v["name"]
         assert _ulp_err(tab, expect) <= 0.5 + 1e-6, v["name"]
+    assert seen_paired
 
 
 def test_tune_table_set_query_load(tmp_path):
@@ -452,7 +472,7 @@ def test_reference_library_exports_its_header():
     out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
                          text=True).stdout
     assert not re.findall(r" T (ref_[a-z_]+)$", out, flags=re.M)
-    assert reference.timeline_variants()[0] == "n4096_e16_b1_px_r16.16.16_db"
+    assert reference.timeline_variants()[0] == sf.fft_tune_query(4096, 256)  # the headline shape
 
 
 def test_reference_calls_reject_bad_arguments_before_any_device_call():
