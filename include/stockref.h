@@ -84,7 +84,8 @@ int ref_filter_multiply(void *y, const void *h, int64_t n, int64_t batch, void *
  *            For wave v of workgroup g, stamps[(g * waves + v) * 32 + i]
  *            holds for i < 16 the 100 MHz real-time counter and for
  *            i >= 16 the shader clock counter, at mark i mod 16:
- *            0 entry, 1 input loads landed, 2 .. 2P the pass marks (after
+ *            0 entry, 1 input loads (and the twiddle loads a shape issues
+ *            with them) landed, 2 .. 2P the pass marks (after
  *            pass p's arithmetic: 2p + 2; after the exchange that follows
  *            it: 2p + 3), 2P + 1 stores issued, 2P + 2 stores completed.
  *            Unused slots are 0.

@@ -176,69 +176,82 @@ struct BuiltinEntry {
   const char* name;
 };
 const BuiltinEntry kBuiltin[] = {
-    {256, 1, 64, "n256_e4_b4_p4_r4.4.4.4"},
-    {256, 65, 512, "n256_e8_b8_p4_r8.8.4"},
-    {256, 513, 1536, "n256_e4_b4_p4_r4.4.4.4_pt"},
-    {256, 1537, 4096, "n256_e8_b8_p4_r8.8.4_pt"},
-    {256, 4097, INT64_MAX, "n256_e16_b4_p4_r16.16_pt"},
-    {512, 1, 64, "n512_e8_b4_p4_r8.8.8"},
-    {512, 65, 512, "n512_e16_b2_p4_r16.16.2_pt"},
-    {512, 513, 1536, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
+    {256, 1, 64, "n256_e16_b4_p4_r16.16"},
+    {256, 65, 384, "n256_e4_b4_p4_r4.4.4.4_pt"},
+    {256, 385, 768, "n256_e8_b8_p4_r8.8.4"},
+    {256, 769, 1536, "n256_e4_b4_p4_r4.4.4.4_pt"},
+    {256, 1537, 4096, "n256_e16_b4_p4_r16.16_pt"},
+    {256, 4097, INT64_MAX, "n256_e4_b4_p4_r4.4.4.4_pt"},
+    {512, 1, 64, "n512_e4_b2_p4_r4.4.4.4.2"},
+    {512, 65, 384, "n512_e8_b4_p4_r8.8.8"},
+    {512, 385, 768, "n512_e8_b4_p4_r8.8.8"},
+    {512, 769, 1536, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
     {512, 1537, 4096, "n512_e8_b4_p4_r8.8.8_pt"},
     {512, 4097, INT64_MAX, "n512_e8_b4_p4_r8.8.8_pt"},
     {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4"},
-    {1024, 65, 512, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
-    {1024, 513, 1536, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
+    {1024, 65, 384, "n1024_e16_b1_p4_r16.16.4_pt"},
+    {1024, 385, 768, "n1024_e4_b1_p4_r4.4.4.4.4"},
+    {1024, 769, 1536, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
     {1024, 1537, 4096, "n1024_e16_b1_p4_r16.16.4_pt"},
     {1024, 4097, INT64_MAX, "n1024_e16_b4_p4_r16.16.4_pt"},
-    {2048, 1, 64, "n2048_e16_b1_p4_r16.16.8"},
-    {2048, 65, 512, "n2048_e8_b1_p4_r8.8.8.4_pt"},
-    {2048, 513, 1536, "n2048_e16_b1_p4_r16.16.8_pt"},
+    {2048, 1, 64, "n2048_e8_b1_p4_r8.8.8.4_pt"},
+    {2048, 65, 384, "n2048_e8_b1_p4_r8.8.8.4_pt"},
+    {2048, 385, 768, "n2048_e8_b1_p4_r8.8.8.4_pt"},
+    {2048, 769, 1536, "n2048_e16_b1_p4_r16.16.8_pt"},
     {2048, 1537, 4096, "n2048_e32_c2_b1_p4_r16.16.8_pt"},
-    {2048, 4097, INT64_MAX, "n2048_e32_c2_b1_p4_r16.16.8_pt"},
-    {4096, 1, 64, "n4096_e16_b1_px_r16.16.16_db_pt"},
-    {4096, 65, 512, "n4096_e16_b1_px_r16.16.16_db_pt"},
-    {4096, 513, 1536, "n4096_e32_b1_p4_r16.16.16"},
+    {2048, 4097, INT64_MAX, "n2048_e16_b2_p4_r16.16.8_pt"},
+    {4096, 1, 64, "n4096_e16_b1_px_r16.16.16_db_pt_tall"},
+    {4096, 65, 384, "n4096_e16_b1_px_r16.16.16_db_pt_tall"},
+    {4096, 385, 768, "n4096_e8_b1_p4_r8.8.8.8_pt"},
+    {4096, 769, 1536, "n4096_e32_b1_p4_r16.16.16"},
     {4096, 1537, 4096, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
     {4096, 4097, INT64_MAX, "n4096_e16_b1_px_r16.16.16_pt"},
     {8192, 1, 64, "fs8192_4x2048"},
-    {8192, 65, 512, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
-    {8192, 513, 1536, "n8192_e32_c4_b1_p4_r8.8.8.16"},
+    {8192, 65, 384, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
+    {8192, 385, 768, "n8192_e32_b1_p4_r16.16.16.2_pt"},
+    {8192, 769, 1536, "n8192_e32_c4_b1_p4_r8.8.8.16"},
     {8192, 1537, 4096, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
     {8192, 4097, INT64_MAX, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
     {16384, 1, 64, "fs16384_8x2048"},
-    {16384, 65, 512, "n16384_e16_b1_p4_r16.16.16.4_pt"},
-    {16384, 513, 1536, "n16384_e16_c2_b1_p4_r8.8.8.8.4_pt"},
+    {16384, 65, 384, "n16384_e16_b1_p4_r16.16.16.4_pt"},
+    {16384, 385, 768, "n16384_e16_c2_b1_p4_r8.8.8.8.4_pt"},
+    {16384, 769, 1536, "n16384_e16_c2_b1_p4_r8.8.8.8.4_pt"},
     {16384, 1537, 4096, "n16384_e16_c2_b1_p4_r8.8.8.8.4_pt"},
     {16384, 4097, INT64_MAX, "n16384_e32_c2_b1_p4_r16.16.16.4_pt"},
     {32768, 1, 64, "fs32768_2x16384"},
-    {32768, 65, 512, "fs32768_2x16384"},
-    {32768, 513, 1536, "fs32768_2x16384"},
+    {32768, 65, 384, "fs32768_2x16384"},
+    {32768, 385, 768, "fs32768_2x16384"},
+    {32768, 769, 1536, "fs32768_2x16384"},
     {32768, 1537, 4096, "fs32768_2x16384"},
     {32768, 4097, INT64_MAX, "fs32768_2x16384"},
     {65536, 1, 64, "fs65536_tile256x256"},
-    {65536, 65, 512, "fs65536_4x16384"},
-    {65536, 513, 1536, "fs65536_4x16384"},
+    {65536, 65, 384, "fs65536_4x16384"},
+    {65536, 385, 768, "fs65536_tile256x256"},
+    {65536, 769, 1536, "fs65536_4x16384"},
     {65536, 1537, 4096, "fs65536_4x16384"},
     {65536, 4097, INT64_MAX, "fs65536_4x16384"},
     {131072, 1, 64, "fs131072_tile256x512"},
-    {131072, 65, 512, "fs131072_tile256x512"},
-    {131072, 513, 1536, "fs131072_8x16384"},
+    {131072, 65, 384, "fs131072_tile256x512"},
+    {131072, 385, 768, "fs131072_tile256x512"},
+    {131072, 769, 1536, "fs131072_8x16384"},
     {131072, 1537, 4096, "fs131072_8x16384"},
     {131072, 4097, INT64_MAX, "fs131072_8x16384"},
     {262144, 1, 64, "fs262144_tile512x512"},
-    {262144, 65, 512, "fs262144_tile512x512_c2"},
-    {262144, 513, 1536, "fs262144_tile512x512"},
+    {262144, 65, 384, "fs262144_tile512x512_c2"},
+    {262144, 385, 768, "fs262144_tile512x512_c2"},
+    {262144, 769, 1536, "fs262144_tile512x512"},
     {262144, 1537, 4096, "fs262144_tile512x512"},
     {262144, 4097, INT64_MAX, "fs262144_tile512x512"},
     {524288, 1, 64, "fs524288_tile1024x512"},
-    {524288, 65, 512, "fs524288_tile1024x512"},
-    {524288, 513, 1536, "fs524288_tile1024x512"},
+    {524288, 65, 384, "fs524288_tile1024x512"},
+    {524288, 385, 768, "fs524288_tile1024x512"},
+    {524288, 769, 1536, "fs524288_tile1024x512"},
     {524288, 1537, 4096, "fs524288_tile1024x512"},
     {524288, 4097, INT64_MAX, "fs524288_tile1024x512"},
     {1048576, 1, 64, "fs1048576_tile1024x1024_c2"},
-    {1048576, 65, 512, "fs1048576_tile1024x1024_c2"},
-    {1048576, 513, 1536, "fs1048576_tile1024x1024_c2"},
+    {1048576, 65, 384, "fs1048576_tile1024x1024_c2"},
+    {1048576, 385, 768, "fs1048576_tile1024x1024_c2"},
+    {1048576, 769, 1536, "fs1048576_tile1024x1024_c2"},
     {1048576, 1537, 4096, "fs1048576_tile1024x1024_c2"},
     {1048576, 4097, INT64_MAX, "fs1048576_tile1024x1024_c2"},
 };
@@ -246,39 +259,46 @@ const BuiltinEntry kBuiltin[] = {
 // Built-in matched-filter choices: the autotuner's result on MI355X (the
 // "filter_entries" of the package's tune_gfx950.json).
 const BuiltinEntry kBuiltinFilter[] = {
-    {256, 1, 64, "n256_e16_b4_p4_r16.16_pt"},
-    {256, 65, 512, "n256_e16_b4_p4_r16.16"},
-    {256, 513, 1536, "n256_e4_b4_p4_r4.4.4.4_pt"},
+    {256, 1, 64, "n256_e4_b4_p4_r4.4.4.4_pt"},
+    {256, 65, 384, "n256_e16_b4_p4_r16.16"},
+    {256, 385, 768, "n256_e16_b4_p4_r16.16"},
+    {256, 769, 1536, "n256_e4_b4_p4_r4.4.4.4"},
     {256, 1537, 4096, "n256_e4_b4_p4_r4.4.4.4_pt"},
     {256, 4097, INT64_MAX, "n256_e16_b16_p4_r16.16_pt"},
-    {512, 1, 64, "n512_e8_b4_p4_r8.8.8_pt"},
-    {512, 65, 512, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
-    {512, 513, 1536, "n512_e8_b4_p4_r8.8.8_pt"},
+    {512, 1, 64, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
+    {512, 65, 384, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
+    {512, 385, 768, "n512_e4_b2_p4_r4.4.4.4.2"},
+    {512, 769, 1536, "n512_e8_b4_p4_r8.8.8_pt"},
     {512, 1537, 4096, "n512_e8_b4_p4_r8.8.8_pt"},
     {512, 4097, INT64_MAX, "n512_e8_b4_p4_r8.8.8_pt"},
-    {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
-    {1024, 65, 512, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
-    {1024, 513, 1536, "n1024_e8_b2_p4_r8.8.8.2_pt"},
+    {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4"},
+    {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
+    {1024, 385, 768, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
+    {1024, 769, 1536, "n1024_e8_b2_p4_r8.8.8.2_pt"},
     {1024, 1537, 4096, "n1024_e8_b2_p4_r8.8.8.2_pt"},
     {1024, 4097, INT64_MAX, "n1024_e16_b1_p4_r16.16.4_pt"},
     {2048, 1, 64, "n2048_e8_b1_p4_r8.8.8.4_pt"},
-    {2048, 65, 512, "n2048_e8_b1_p4_r8.8.8.4_pt"},
-    {2048, 513, 1536, "n2048_e8_b1_p4_r8.8.8.4_pt"},
+    {2048, 65, 384, "n2048_e8_b1_p4_r8.8.8.4_pt"},
+    {2048, 385, 768, "n2048_e8_b1_p4_r8.8.8.4_pt"},
+    {2048, 769, 1536, "n2048_e8_b1_p4_r8.8.8.4_pt"},
     {2048, 1537, 4096, "n2048_e8_b1_p4_r8.8.8.4_pt"},
     {2048, 4097, INT64_MAX, "n2048_e16_b1_p4_r16.16.8_pt"},
     {4096, 1, 64, "n4096_e8_b1_p4_r8.8.8.8_pt"},
-    {4096, 65, 512, "n4096_e16_b1_px_r16.16.16_db_pt"},
-    {4096, 513, 1536, "n4096_e16_b1_px_r16.16.16_pt"},
+    {4096, 65, 384, "n4096_e16_b1_px_r16.16.16_db_pt_tall"},
+    {4096, 385, 768, "n4096_e16_b1_px_r16.16.16_db_pt_tall"},
+    {4096, 769, 1536, "n4096_e16_b1_px_r16.16.16_pt"},
     {4096, 1537, 4096, "n4096_e16_b1_px_r16.16.16_pt"},
     {4096, 4097, INT64_MAX, "n4096_e16_b1_px_r16.16.16_pt"},
     {8192, 1, 64, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
-    {8192, 65, 512, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
-    {8192, 513, 1536, "n8192_e32_b1_p4_r16.16.16.2_pt"},
+    {8192, 65, 384, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
+    {8192, 385, 768, "n8192_e32_b1_p4_r16.16.16.2_pt"},
+    {8192, 769, 1536, "n8192_e32_b1_p4_r16.16.16.2_pt"},
     {8192, 1537, 4096, "n8192_e32_b1_p4_r16.16.16.2_pt"},
     {8192, 4097, INT64_MAX, "n8192_e32_b1_p4_r16.16.16.2_pt"},
     {16384, 1, 64, "n16384_e32_b1_p4_r16.16.16.4_pt"},
-    {16384, 65, 512, "n16384_e32_b1_p4_r16.16.16.4_pt"},
-    {16384, 513, 1536, "n16384_e32_b1_p4_r16.16.16.4_pt"},
+    {16384, 65, 384, "n16384_e32_b1_p4_r16.16.16.4_pt"},
+    {16384, 385, 768, "n16384_e16_c2_b1_p4_r8.8.8.8.4_pt"},
+    {16384, 769, 1536, "n16384_e32_b1_p4_r16.16.16.4_pt"},
     {16384, 1537, 4096, "n16384_e32_b1_p4_r16.16.16.4_pt"},
     {16384, 4097, INT64_MAX, "n16384_e16_c2_b1_p4_r8.8.8.8.4_pt"},
 };
@@ -286,39 +306,46 @@ const BuiltinEntry kBuiltinFilter[] = {
 // Built-in fused forward -> weight -> adjoint choices: the autotuner's result
 // on MI355X (the "fused_entries" of the package's tune_gfx950.json).
 const BuiltinEntry kBuiltinFused[] = {
-    {256, 1, 64, "n256_e8_b8_p4_r8.8.4_pt"},
-    {256, 65, 512, "n256_e4_b4_p4_r4.4.4.4_pt"},
-    {256, 513, 1536, "n256_e8_b8_p4_r8.8.4_pt"},
-    {256, 1537, 4096, "n256_e8_b8_p4_r8.8.4_pt"},
+    {256, 1, 64, "n256_e4_b4_p4_r4.4.4.4_pt"},
+    {256, 65, 384, "n256_e4_b4_p4_r4.4.4.4"},
+    {256, 385, 768, "n256_e4_b4_p4_r4.4.4.4"},
+    {256, 769, 1536, "n256_e4_b4_p4_r4.4.4.4_pt"},
+    {256, 1537, 4096, "n256_e8_b8_p4_r8.8.4"},
     {256, 4097, INT64_MAX, "n256_e16_b16_p4_r16.16_pt"},
-    {512, 1, 64, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
-    {512, 65, 512, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
-    {512, 513, 1536, "n512_e8_b4_p4_r8.8.8_pt"},
+    {512, 1, 64, "n512_e4_b2_p4_r4.4.4.4.2"},
+    {512, 65, 384, "n512_e4_b2_p4_r4.4.4.4.2"},
+    {512, 385, 768, "n512_e4_b2_p4_r4.4.4.4.2"},
+    {512, 769, 1536, "n512_e8_b4_p4_r8.8.8"},
     {512, 1537, 4096, "n512_e8_b4_p4_r8.8.8_pt"},
     {512, 4097, INT64_MAX, "n512_e8_b4_p4_r8.8.8_pt"},
     {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
-    {1024, 65, 512, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
-    {1024, 513, 1536, "n1024_e8_b2_p4_r8.8.8.2_pt"},
+    {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
+    {1024, 385, 768, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
+    {1024, 769, 1536, "n1024_e8_b2_p4_r8.8.8.2_pt"},
     {1024, 1537, 4096, "n1024_e8_b2_p4_r8.8.8.2_pt"},
     {1024, 4097, INT64_MAX, "n1024_e16_b4_p4_r16.16.4_pt"},
     {2048, 1, 64, "n2048_e8_b1_p4_r8.8.8.4_pt"},
-    {2048, 65, 512, "n2048_e8_b1_p4_r8.8.8.4_pt"},
-    {2048, 513, 1536, "n2048_e8_b1_p4_r8.8.8.4_pt"},
+    {2048, 65, 384, "n2048_e8_b1_p4_r8.8.8.4_pt"},
+    {2048, 385, 768, "n2048_e8_b1_p4_r8.8.8.4_pt"},
+    {2048, 769, 1536, "n2048_e8_b1_p4_r8.8.8.4_pt"},
     {2048, 1537, 4096, "n2048_e16_b2_p4_r16.16.8_pt"},
     {2048, 4097, INT64_MAX, "n2048_e16_b2_p4_r16.16.8_pt"},
-    {4096, 1, 64, "n4096_e8_b1_p4_r8.8.8.8_pt"},
-    {4096, 65, 512, "n4096_e8_b1_p4_r8.8.8.8_pt"},
-    {4096, 513, 1536, "n4096_e16_b1_p5_r16.16.16_pt"},
+    {4096, 1, 64, "n4096_e16_b1_px_r16.16.16_db_pt_tall"},
+    {4096, 65, 384, "n4096_e16_b1_px_r16.16.16_db_pt"},
+    {4096, 385, 768, "n4096_e16_b1_px_r16.16.16_db_pt"},
+    {4096, 769, 1536, "n4096_e16_b1_p5_r16.16.16_pt"},
     {4096, 1537, 4096, "n4096_e16_b1_p5_r16.16.16_pt"},
     {4096, 4097, INT64_MAX, "n4096_e16_b1_p5_r16.16.16_pt"},
-    {8192, 1, 64, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
-    {8192, 65, 512, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
-    {8192, 513, 1536, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
+    {8192, 1, 64, "n8192_e16_b1_p4_r16.16.16.2_pt"},
+    {8192, 65, 384, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
+    {8192, 385, 768, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
+    {8192, 769, 1536, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
     {8192, 1537, 4096, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
     {8192, 4097, INT64_MAX, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
     {16384, 1, 64, "n16384_e32_b1_p4_r16.16.16.4_pt"},
-    {16384, 65, 512, "n16384_e32_b1_p4_r16.16.16.4_pt"},
-    {16384, 513, 1536, "n16384_e32_b1_p4_r16.16.16.4_pt"},
+    {16384, 65, 384, "n16384_e32_b1_p4_r16.16.16.4_pt"},
+    {16384, 385, 768, "n16384_e32_b1_p4_r16.16.16.4_pt"},
+    {16384, 769, 1536, "n16384_e32_b1_p4_r16.16.16.4_pt"},
     {16384, 1537, 4096, "n16384_e32_b1_p4_r16.16.16.4_pt"},
     {16384, 4097, INT64_MAX, "n16384_e32_b1_p4_r16.16.16.4_pt"},
 };

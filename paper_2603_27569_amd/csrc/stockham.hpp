@@ -463,11 +463,26 @@ __device__ __forceinline__ void load_all_twiddles(c32 (&w)[S::TW_REGS], const c3
   }
 }
 
+// The twiddle loads a shape issues together with the input (PF = 2: all of
+// them); nothing for the other schedules.
+template <class S>
+__device__ __forceinline__ void preload_twiddles(c32 (&w)[S::TW_REGS], const c32* tw, int t) {
+  if constexpr (S::PF == 2) load_all_twiddles<S, 1>(w, tw, t);
+}
+
+// All passes, with w[] as preload_twiddles left it.
+template <class S, bool INV, class Pr = NoProbe>
+__device__ __forceinline__ void run_passes_preloaded(c32 (&a)[S::E], c32 (&w)[S::TW_REGS],
+                                                     c32* lds, const c32* tw, int t,
+                                                     Pr* pr = nullptr) {
+  run_passes_from<S, 0, INV>(a, w, lds, tw, t, pr);
+}
+
 template <class S, bool INV, class Pr = NoProbe>
 __device__ __forceinline__ void run_passes(c32 (&a)[S::E], c32* lds, const c32* tw,
                                            int t, Pr* pr = nullptr) {
   c32 w[S::TW_REGS];
-  if constexpr (S::PF == 2) load_all_twiddles<S, 1>(w, tw, t);
+  preload_twiddles<S>(w, tw, t);
   run_passes_from<S, 0, INV>(a, w, lds, tw, t, pr);
 }
 

@@ -131,10 +131,12 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham_timeline(const 
   const int t = threadIdx.x;
   const int64_t row = blockIdx.x;
   c32 a[S::E];
+  c32 w[S::TW_REGS];
   global_load_row<S>(a, in + row * S::N, t, true);
+  preload_twiddles<S>(w, tw, t);  // in flight with the input, as in the plain kernel
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   pr.read(1);
-  run_passes<S, INV, TimelineProbe>(a, lds, tw, t, &pr);
+  run_passes_preloaded<S, INV, TimelineProbe>(a, w, lds, tw, t, &pr);
   global_store_row<S>(a, out + row * S::N, t, true);
   pr.read(2 * S::P + 1);
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
@@ -172,6 +174,8 @@ hipError_t launch_timeline(const void* in, void* out, const void* tw, int64_t ba
 // The shapes of the N = 4096 variants of the library with one transform
 // per workgroup (names as fft_variant_describe gives them).
 const TimelineVariant kTimeline[] = {
+    {"n4096_e16_b1_px_r16.16.16_db_pt_tall", 4096, 256,
+     &launch_timeline<DoubleBuffered<PairedTwiddles<ShapeX<1, 2, 1, 4096, 16, 1, -1, 16, 16, 16>>>>},
     {"n4096_e16_b1_px_r16.16.16_db_pt", 4096, 256,
      &launch_timeline<DoubleBuffered<PairedTwiddles<Shape<4096, 16, 1, -1, 16, 16, 16>>>>},
     {"n4096_e16_b1_px_r16.16.16_db", 4096, 256,

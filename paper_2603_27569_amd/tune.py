@@ -19,7 +19,9 @@ ragged batch.  The result is a JSON file that
 
 Timing: back-to-back launches over a ring of independent buffers larger
 than the Infinity Cache, bracketed by HIP events on the launch stream; the
-median of a few repeats.  Every variant computes the same transform (the
+median of three repeats, each at least REPEAT_US of GPU time; candidates
+within 3% of the best are timed again with three times the launches before
+one is chosen.  Every variant computes the same transform (the
 parity tests check each one against the FP64 reference), so the search is
 on speed alone.
 
@@ -43,7 +45,14 @@ SIZES = (256, 512, 1024, 2048, 4096, 8192, 16384)
 # single-pass); the timed batch is capped by MAX_BYTES per buffer.
 SIZES_LARGE = tuple(1 << e for e in range(15, 21))
 # Batch buckets: (batch_min, batch_max, representative batch timed).
-BUCKETS = ((1, 64, 32), (65, 512, 256), (513, 1536, 1024), (1537, 4096, 2048), (4097, 2 ** 62, 16384))
+BUCKETS = ((1, 64, 32), (65, 384, 256), (385, 768, 512), (769, 1536, 1024), (1537, 4096, 2048),
+           (4097, 2 ** 62, 16384))
+# Each timed repeat covers at least this much GPU time (launch counts adapt to
+# the kernel's duration), and the candidates within CLOSE of the best are
+# timed once more with FINAL_FACTOR times the launches before one is chosen.
+REPEAT_US = 1500.0
+CLOSE = 1.03
+FINAL_FACTOR = 3
 RING_BYTES = 1 << 30
 MAX_BYTES = 2 << 30  # cap on one timed buffer
 
@@ -57,10 +66,23 @@ def _ring(torch, dev, n, batch):
 
 
 def _time(torch, stream, fn, iters, warmup=5, repeats=3):
+    """Median over `repeats` of the per-launch time of back-to-back launches
+    (microseconds).  `iters` is the least number of launches per repeat; it
+    grows so that a repeat covers REPEAT_US of GPU time."""
     with torch.cuda.stream(stream):
         for i in range(warmup):
             fn(i)
     torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(stream):
+        e0.record(stream)
+        for i in range(5):
+            fn(i)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    probe = max(e0.elapsed_time(e1) * 1e3 / 5, 1.0)
+    iters = max(iters, min(2000, int(REPEAT_US / probe)))
     res = []
     for _ in range(repeats):
         e0 = torch.cuda.Event(enable_timing=True)
@@ -73,6 +95,17 @@ def _time(torch, stream, fn, iters, warmup=5, repeats=3):
         torch.cuda.synchronize()
         res.append(e0.elapsed_time(e1) * 1e3 / iters)
     return statistics.median(res)
+
+
+def _pick(times, retime):
+    """The fastest candidate, after re-timing every candidate within CLOSE of
+    the first measurement's best (retime(name) returns a new time)."""
+    best = min(times.values())
+    close = [k for k, v in times.items() if v <= best * CLOSE]
+    if len(close) > 1:
+        for k in close:
+            times[k] = retime(k)
+    return min(times, key=times.get)
 
 
 def candidates(n):
@@ -95,13 +128,19 @@ def tune_plain(torch, dev, stream, sizes=SIZES, buckets=BUCKETS, iters=30, log=p
             k = len(xs)
             times = {}
             cs = stream.cuda_stream
-            for name, algo in candidates(n):
-                p = Plan(n, b, FFT_FORWARD, algo, name)
-                times[name] = _time(torch, stream,
-                                    lambda i: p.exec(xs[i % k].data_ptr(), ys[i % k].data_ptr(), cs),
-                                    iters)
+            algos = dict(candidates(n))
+
+            def timed(name, factor=1):
+                p = Plan(n, b, FFT_FORWARD, algos[name], name)
+                t = _time(torch, stream,
+                          lambda i: p.exec(xs[i % k].data_ptr(), ys[i % k].data_ptr(), cs),
+                          iters * factor)
                 p.close()
-            best = min(times, key=times.get)
+                return t
+
+            for name in algos:
+                times[name] = timed(name)
+            best = _pick(times, lambda name: timed(name, FINAL_FACTOR))
             log(f"tune n={n} batch={b} -> {best} {times[best]:.2f} us")
             entries.append({"n": n, "batch_min": bmin, "batch_max": bmax, "variant": best,
                             "timed_batch": b, "us": round(times[best], 3),
@@ -123,17 +162,20 @@ def tune_filter(torch, dev, stream, sizes=SIZES, buckets=BUCKETS, iters=30, log=
             k = len(xs)
             times = {}
             cs = stream.cuda_stream
-            for name, algo in candidates(n):
-                if algo != FFT_ALGO_SINGLE_PASS:
-                    continue
-                p = Plan(n, b, FFT_FORWARD, algo, name)
-                times[name] = _time(torch, stream,
-                                    lambda i: fft_exec_matched_filter(p.handle, xs[i % k].data_ptr(),
-                                                                      h.data_ptr(), ys[i % k].data_ptr(),
-                                                                      cs),
-                                    iters)
+            names = [nm for nm, algo in candidates(n) if algo == FFT_ALGO_SINGLE_PASS]
+
+            def timed(name, factor=1):
+                p = Plan(n, b, FFT_FORWARD, FFT_ALGO_SINGLE_PASS, name)
+                t = _time(torch, stream,
+                          lambda i: fft_exec_matched_filter(p.handle, xs[i % k].data_ptr(),
+                                                            h.data_ptr(), ys[i % k].data_ptr(), cs),
+                          iters * factor)
                 p.close()
-            best = min(times, key=times.get)
+                return t
+
+            for name in names:
+                times[name] = timed(name)
+            best = _pick(times, lambda name: timed(name, FINAL_FACTOR))
             log(f"tune filter n={n} batch={b} -> {best} {times[best]:.2f} us")
             entries.append({"n": n, "batch_min": bmin, "batch_max": bmax, "variant": best,
                             "timed_batch": b, "us": round(times[best], 3),
@@ -157,17 +199,21 @@ def tune_fused(torch, dev, stream, sizes=SIZES, buckets=BUCKETS, iters=30, log=p
             rows = torch.empty(b, dtype=torch.float32, device=dev)
             times = {}
             cs = stream.cuda_stream
-            for name, algo in candidates(n):
-                if algo != FFT_ALGO_SINGLE_PASS:
-                    continue
-                p = Plan(n, b, FFT_FORWARD, algo, name)
-                times[name] = _time(torch, stream,
-                                    lambda i: fft_exec_spectral_energy(
-                                        p.handle, xs[i % k].data_ptr(), w.data_ptr(), 0,
-                                        ys[i % k].data_ptr(), rows.data_ptr(), total.data_ptr(), cs),
-                                    iters)
+            names = [nm for nm, algo in candidates(n) if algo == FFT_ALGO_SINGLE_PASS]
+
+            def timed(name, factor=1):
+                p = Plan(n, b, FFT_FORWARD, FFT_ALGO_SINGLE_PASS, name)
+                t = _time(torch, stream,
+                          lambda i: fft_exec_spectral_energy(
+                              p.handle, xs[i % k].data_ptr(), w.data_ptr(), 0,
+                              ys[i % k].data_ptr(), rows.data_ptr(), total.data_ptr(), cs),
+                          iters * factor)
                 p.close()
-            best = min(times, key=times.get)
+                return t
+
+            for name in names:
+                times[name] = timed(name)
+            best = _pick(times, lambda name: timed(name, FINAL_FACTOR))
             log(f"tune fused n={n} batch={b} -> {best} {times[best]:.2f} us")
             entries.append({"n": n, "batch_min": bmin, "batch_max": bmax, "variant": best,
                             "timed_batch": b, "us": round(times[best], 3),
