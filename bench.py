@@ -82,17 +82,30 @@ def cpu_model():
 
 
 class Timer:
-    """HIP events recorded on one stream around a block of launches."""
+    """HIP events recorded on one stream around a block of launches.
+
+    The untimed warmup is `warmup` launches and at least WARM_S of wall
+    time: after host-side work (reference checks, buffer set-up) the GPU's
+    clocks have dropped, and a few dozen microsecond-scale launches do not
+    bring them back, so a short kernel timed right away reads up to 20% slow."""
+
+    WARM_S = 0.03
 
     def __init__(self, torch, stream):
         self.torch, self.stream = torch, stream
 
-    def run(self, fn, iters, warmup):
+    def run(self, fn, iters, warmup, exact_warmup=False):
+        """Seconds for `iters` launches; exact_warmup=True runs exactly
+        `warmup` untimed launches (the contract's W steps)."""
         torch = self.torch
-        with torch.cuda.stream(self.stream):
-            for i in range(warmup):
-                fn(i)
-        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < warmup or (not exact_warmup and time.perf_counter() - t0 < self.WARM_S):
+            with torch.cuda.stream(self.stream):
+                for i in range(max(warmup, 1)):
+                    fn(done + i)
+            done += max(warmup, 1)
+            torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         with torch.cuda.stream(self.stream):
@@ -165,7 +178,7 @@ def main():
         bwd.exec(ys[j].data_ptr(), zs[j].data_ptr(), cs)
 
     # The contract's figure: exactly K timed steps after W warmup steps.
-    t_step = T.run(step, args.steps, args.warmup) / args.steps
+    t_step = T.run(step, args.steps, args.warmup, exact_warmup=True) / args.steps
     # Per-launch figures for the roofline: median of 5 event-timed runs.
     t_fwd = median_of(T, lambda i: fwd.exec(xs[i % K].data_ptr(), ys[i % K].data_ptr(), cs),
                       args.steps, args.warmup)

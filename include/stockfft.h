@@ -126,7 +126,9 @@ int fft_exec(fft_plan_t plan, const void *in, void *out, void *stream);
  * binary16 overflows to infinity above 65504: a bin can reach sqrt(n) times
  * the input row's 2-norm, so inputs must be scaled for that; bfloat16 has
  * float32's range.  Single-pass plans only (n <= 16384).  Asynchronous; does
- * not allocate.  in == out allowed.
+ * not allocate.  in == out allowed.  The kernel shape is the plan's named
+ * variant, else the 16-bit transform's own tuned choice
+ * (fft_tune_query_storage16), which can differ from the FP32 one.
  * FFT_IO_C16_MMA / FFT_IO_BC16_MMA: the same storage for n = 16^P * RL
  * (512, 1024, 2048, 4096, 8192, 16384; any single-pass plan of those
  * lengths), with every 16-point DFT of the P radix-16 passes computed on the
@@ -327,6 +329,14 @@ int fft_tune_query_filter(int64_t n, int64_t batch, char *buf, int64_t cap);
  * tune file).  Host only.  Errors: as fft_tune_query_filter.
  */
 int fft_tune_query_fused(int64_t n, int64_t batch, char *buf, int64_t cap);
+
+/*
+ * fft_tune_query_storage16 -- the same for fft_exec_io's 16-bit storage
+ * formats FFT_IO_C16 and FFT_IO_BC16 ("storage16_entries" in a tune file),
+ * for plans of either direction.  Host only.  Errors: as
+ * fft_tune_query_filter.
+ */
+int fft_tune_query_storage16(int64_t n, int64_t batch, char *buf, int64_t cap);
 
 /*
  * fft_set_launch_limit -- largest grid (in workgroups) one kernel launch may

@@ -37,7 +37,7 @@ __all__ = [
     "fft_destroy_ragged",
     "fft_ragged_shapes", "fft_tune_set_ragged", "fft_tune_query_ragged", "fft_tune_clear_ragged",
     "fft_tune_load", "fft_tune_set", "fft_tune_clear", "fft_tune_query", "fft_tune_query_filter",
-    "fft_tune_query_fused",
+    "fft_tune_query_fused", "fft_tune_query_storage16",
     "fft_set_launch_limit",
     "fft_variant_count", "fft_variant_describe", "fft_variant_twiddles",
     "fft_plan_describe", "fft_status_string", "fft_last_hip_error", "fft_version",
@@ -171,6 +171,12 @@ def fft_tune_query_filter(n, batch):
 def fft_tune_query_fused(n, batch):
     buf = ctypes.create_string_buffer(128)
     check("fft_tune_query_fused", lib().fft_tune_query_fused(int(n), int(batch), buf, len(buf)))
+    return buf.value.decode()
+
+
+def fft_tune_query_storage16(n, batch):
+    buf = ctypes.create_string_buffer(128)
+    check("fft_tune_query_storage16", lib().fft_tune_query_storage16(int(n), int(batch), buf, len(buf)))
     return buf.value.decode()
 
 

@@ -55,6 +55,7 @@ SIGNATURES = {
     "fft_tune_query_ragged": (_int, [_i64, ctypes.c_char_p, _i64]),
     "fft_tune_query_filter": (_int, [_i64, _i64, ctypes.c_char_p, _i64]),
     "fft_tune_query_fused": (_int, [_i64, _i64, ctypes.c_char_p, _i64]),
+    "fft_tune_query_storage16": (_int, [_i64, _i64, ctypes.c_char_p, _i64]),
     "fft_tune_clear_ragged": (_int, []),
     "fft_tune_load": (_int, [ctypes.c_char_p]),
     "fft_tune_set": (_int, [_i64, _i64, _i64, ctypes.c_char_p]),

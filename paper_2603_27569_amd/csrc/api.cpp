@@ -163,8 +163,10 @@ std::mutex g_tune_mu;
 // multiply -> inverse kernel can prefer another shape than the plain
 // transform.  Tune-file entries ("filter_entries") take precedence.
 std::vector<TuneEntry> g_tune_filter;
-// The same for the fused forward -> weight -> adjoint kernel ("fused_entries").
+// The same for the fused forward -> weight -> adjoint kernel ("fused_entries")
+// and for the transform with 16-bit storage ("storage16_entries").
 std::vector<TuneEntry> g_tune_fused;
+std::vector<TuneEntry> g_tune_storage16;
 std::vector<TuneEntry> g_tune;
 bool g_env_tune_done = false;
 
@@ -176,48 +178,48 @@ struct BuiltinEntry {
   const char* name;
 };
 const BuiltinEntry kBuiltin[] = {
-    {256, 1, 64, "n256_e16_b4_p4_r16.16"},
-    {256, 65, 384, "n256_e4_b4_p4_r4.4.4.4_pt"},
-    {256, 385, 768, "n256_e8_b8_p4_r8.8.4"},
-    {256, 769, 1536, "n256_e4_b4_p4_r4.4.4.4_pt"},
+    {256, 1, 64, "n256_e16_b16_p4_r16.16"},
+    {256, 65, 384, "n256_e16_b16_p4_r16.16"},
+    {256, 385, 768, "n256_e8_b8_p4_r8.8.4_pt"},
+    {256, 769, 1536, "n256_e16_b16_p4_r16.16_pt"},
     {256, 1537, 4096, "n256_e16_b4_p4_r16.16_pt"},
-    {256, 4097, INT64_MAX, "n256_e4_b4_p4_r4.4.4.4_pt"},
-    {512, 1, 64, "n512_e4_b2_p4_r4.4.4.4.2"},
-    {512, 65, 384, "n512_e8_b4_p4_r8.8.8"},
-    {512, 385, 768, "n512_e8_b4_p4_r8.8.8"},
-    {512, 769, 1536, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
+    {256, 4097, INT64_MAX, "n256_e8_b8_p4_r8.8.4_pt"},
+    {512, 1, 64, "n512_e16_b2_p4_r16.16.2"},
+    {512, 65, 384, "n512_e16_b8_p4_r16.16.2"},
+    {512, 385, 768, "n512_e16_b2_p4_r16.16.2_pt"},
+    {512, 769, 1536, "n512_e8_b4_p4_r8.8.8"},
     {512, 1537, 4096, "n512_e8_b4_p4_r8.8.8_pt"},
     {512, 4097, INT64_MAX, "n512_e8_b4_p4_r8.8.8_pt"},
-    {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4"},
-    {1024, 65, 384, "n1024_e16_b1_p4_r16.16.4_pt"},
-    {1024, 385, 768, "n1024_e4_b1_p4_r4.4.4.4.4"},
+    {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
+    {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
+    {1024, 385, 768, "n1024_e8_b2_p4_r8.8.8.2"},
     {1024, 769, 1536, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
     {1024, 1537, 4096, "n1024_e16_b1_p4_r16.16.4_pt"},
     {1024, 4097, INT64_MAX, "n1024_e16_b4_p4_r16.16.4_pt"},
-    {2048, 1, 64, "n2048_e8_b1_p4_r8.8.8.4_pt"},
+    {2048, 1, 64, "n2048_e16_b1_p4_r16.16.8"},
     {2048, 65, 384, "n2048_e8_b1_p4_r8.8.8.4_pt"},
     {2048, 385, 768, "n2048_e8_b1_p4_r8.8.8.4_pt"},
     {2048, 769, 1536, "n2048_e16_b1_p4_r16.16.8_pt"},
     {2048, 1537, 4096, "n2048_e32_c2_b1_p4_r16.16.8_pt"},
     {2048, 4097, INT64_MAX, "n2048_e16_b2_p4_r16.16.8_pt"},
-    {4096, 1, 64, "n4096_e16_b1_px_r16.16.16_db_pt_tall"},
-    {4096, 65, 384, "n4096_e16_b1_px_r16.16.16_db_pt_tall"},
+    {4096, 1, 64, "n4096_e16_b1_px_r16.16.16_db_pt"},
+    {4096, 65, 384, "n4096_e8_b1_p4_r8.8.8.8_pt"},
     {4096, 385, 768, "n4096_e8_b1_p4_r8.8.8.8_pt"},
-    {4096, 769, 1536, "n4096_e32_b1_p4_r16.16.16"},
+    {4096, 769, 1536, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
     {4096, 1537, 4096, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
-    {4096, 4097, INT64_MAX, "n4096_e16_b1_px_r16.16.16_pt"},
-    {8192, 1, 64, "fs8192_4x2048"},
+    {4096, 4097, INT64_MAX, "n4096_e32_b1_p4_r16.16.16_pt_pl"},
+    {8192, 1, 64, "n8192_e16_b1_p4_r16.16.16.2_pt"},
     {8192, 65, 384, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
-    {8192, 385, 768, "n8192_e32_b1_p4_r16.16.16.2_pt"},
+    {8192, 385, 768, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
     {8192, 769, 1536, "n8192_e32_c4_b1_p4_r8.8.8.16"},
-    {8192, 1537, 4096, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
+    {8192, 1537, 4096, "n8192_e32_c4_b1_p4_r8.8.8.16"},
     {8192, 4097, INT64_MAX, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
     {16384, 1, 64, "fs16384_8x2048"},
     {16384, 65, 384, "n16384_e16_b1_p4_r16.16.16.4_pt"},
     {16384, 385, 768, "n16384_e16_c2_b1_p4_r8.8.8.8.4_pt"},
     {16384, 769, 1536, "n16384_e16_c2_b1_p4_r8.8.8.8.4_pt"},
     {16384, 1537, 4096, "n16384_e16_c2_b1_p4_r8.8.8.8.4_pt"},
-    {16384, 4097, INT64_MAX, "n16384_e32_c2_b1_p4_r16.16.16.4_pt"},
+    {16384, 4097, INT64_MAX, "n16384_e16_c2_b1_p4_r8.8.8.8.4_pt"},
     {32768, 1, 64, "fs32768_2x16384"},
     {32768, 65, 384, "fs32768_2x16384"},
     {32768, 385, 768, "fs32768_2x16384"},
@@ -236,9 +238,9 @@ const BuiltinEntry kBuiltin[] = {
     {131072, 769, 1536, "fs131072_8x16384"},
     {131072, 1537, 4096, "fs131072_8x16384"},
     {131072, 4097, INT64_MAX, "fs131072_8x16384"},
-    {262144, 1, 64, "fs262144_tile512x512"},
+    {262144, 1, 64, "fs262144_tile512x512_c2"},
     {262144, 65, 384, "fs262144_tile512x512_c2"},
-    {262144, 385, 768, "fs262144_tile512x512_c2"},
+    {262144, 385, 768, "fs262144_tile512x512"},
     {262144, 769, 1536, "fs262144_tile512x512"},
     {262144, 1537, 4096, "fs262144_tile512x512"},
     {262144, 4097, INT64_MAX, "fs262144_tile512x512"},
@@ -259,48 +261,97 @@ const BuiltinEntry kBuiltin[] = {
 // Built-in matched-filter choices: the autotuner's result on MI355X (the
 // "filter_entries" of the package's tune_gfx950.json).
 const BuiltinEntry kBuiltinFilter[] = {
-    {256, 1, 64, "n256_e4_b4_p4_r4.4.4.4_pt"},
-    {256, 65, 384, "n256_e16_b4_p4_r16.16"},
-    {256, 385, 768, "n256_e16_b4_p4_r16.16"},
-    {256, 769, 1536, "n256_e4_b4_p4_r4.4.4.4"},
+    {256, 1, 64, "n256_e16_b4_p4_r16.16"},
+    {256, 65, 384, "n256_e4_b4_p4_r4.4.4.4_pt"},
+    {256, 385, 768, "n256_e8_b8_p4_r8.8.4"},
+    {256, 769, 1536, "n256_e8_b8_p4_r8.8.4_pt"},
     {256, 1537, 4096, "n256_e4_b4_p4_r4.4.4.4_pt"},
-    {256, 4097, INT64_MAX, "n256_e16_b16_p4_r16.16_pt"},
+    {256, 4097, INT64_MAX, "n256_e16_b4_p4_r16.16_pt"},
     {512, 1, 64, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
-    {512, 65, 384, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
-    {512, 385, 768, "n512_e4_b2_p4_r4.4.4.4.2"},
+    {512, 65, 384, "n512_e8_b4_p4_r8.8.8_pt"},
+    {512, 385, 768, "n512_e8_b4_p4_r8.8.8_pt"},
     {512, 769, 1536, "n512_e8_b4_p4_r8.8.8_pt"},
     {512, 1537, 4096, "n512_e8_b4_p4_r8.8.8_pt"},
     {512, 4097, INT64_MAX, "n512_e8_b4_p4_r8.8.8_pt"},
-    {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4"},
-    {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
+    {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
+    {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4"},
     {1024, 385, 768, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
     {1024, 769, 1536, "n1024_e8_b2_p4_r8.8.8.2_pt"},
-    {1024, 1537, 4096, "n1024_e8_b2_p4_r8.8.8.2_pt"},
-    {1024, 4097, INT64_MAX, "n1024_e16_b1_p4_r16.16.4_pt"},
+    {1024, 1537, 4096, "n1024_e16_b1_p4_r16.16.4_pt"},
+    {1024, 4097, INT64_MAX, "n1024_e16_b4_p4_r16.16.4_pt"},
     {2048, 1, 64, "n2048_e8_b1_p4_r8.8.8.4_pt"},
     {2048, 65, 384, "n2048_e8_b1_p4_r8.8.8.4_pt"},
     {2048, 385, 768, "n2048_e8_b1_p4_r8.8.8.4_pt"},
-    {2048, 769, 1536, "n2048_e8_b1_p4_r8.8.8.4_pt"},
-    {2048, 1537, 4096, "n2048_e8_b1_p4_r8.8.8.4_pt"},
-    {2048, 4097, INT64_MAX, "n2048_e16_b1_p4_r16.16.8_pt"},
+    {2048, 769, 1536, "n2048_e16_b1_p4_r16.16.8_pt"},
+    {2048, 1537, 4096, "n2048_e16_b1_p4_r16.16.8_pt"},
+    {2048, 4097, INT64_MAX, "n2048_e16_b2_p4_r16.16.8_pt"},
     {4096, 1, 64, "n4096_e8_b1_p4_r8.8.8.8_pt"},
-    {4096, 65, 384, "n4096_e16_b1_px_r16.16.16_db_pt_tall"},
-    {4096, 385, 768, "n4096_e16_b1_px_r16.16.16_db_pt_tall"},
-    {4096, 769, 1536, "n4096_e16_b1_px_r16.16.16_pt"},
-    {4096, 1537, 4096, "n4096_e16_b1_px_r16.16.16_pt"},
-    {4096, 4097, INT64_MAX, "n4096_e16_b1_px_r16.16.16_pt"},
-    {8192, 1, 64, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
+    {4096, 65, 384, "n4096_e8_b1_p4_r8.8.8.8_pt"},
+    {4096, 385, 768, "n4096_e16_b1_p5_r16.16.16_pt"},
+    {4096, 769, 1536, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
+    {4096, 1537, 4096, "n4096_e32_c2_b1_p4_r16.16.16_pt_pl"},
+    {4096, 4097, INT64_MAX, "n4096_e32_b1_p4_r16.16.16_pt_pl"},
+    {8192, 1, 64, "n8192_e16_b1_p4_r16.16.16.2_pt"},
     {8192, 65, 384, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
     {8192, 385, 768, "n8192_e32_b1_p4_r16.16.16.2_pt"},
-    {8192, 769, 1536, "n8192_e32_b1_p4_r16.16.16.2_pt"},
-    {8192, 1537, 4096, "n8192_e32_b1_p4_r16.16.16.2_pt"},
-    {8192, 4097, INT64_MAX, "n8192_e32_b1_p4_r16.16.16.2_pt"},
-    {16384, 1, 64, "n16384_e32_b1_p4_r16.16.16.4_pt"},
-    {16384, 65, 384, "n16384_e32_b1_p4_r16.16.16.4_pt"},
+    {8192, 769, 1536, "n8192_e32_c4_b1_p4_r8.8.8.16"},
+    {8192, 1537, 4096, "n8192_e32_c4_b1_p4_r8.8.8.16"},
+    {8192, 4097, INT64_MAX, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
+    {16384, 1, 64, "n16384_e16_b1_p4_r16.16.16.4_pt"},
+    {16384, 65, 384, "n16384_e16_b1_p4_r16.16.16.4_pt"},
     {16384, 385, 768, "n16384_e16_c2_b1_p4_r8.8.8.8.4_pt"},
-    {16384, 769, 1536, "n16384_e32_b1_p4_r16.16.16.4_pt"},
-    {16384, 1537, 4096, "n16384_e32_b1_p4_r16.16.16.4_pt"},
-    {16384, 4097, INT64_MAX, "n16384_e16_c2_b1_p4_r8.8.8.8.4_pt"},
+    {16384, 769, 1536, "n16384_e32_c2_b1_p4_r16.16.16.4_pt"},
+    {16384, 1537, 4096, "n16384_e32_c2_b1_p4_r16.16.16.4_pt"},
+    {16384, 4097, INT64_MAX, "n16384_e32_c2_b1_p4_r16.16.16.4_pt"},
+};
+
+// Built-in 16-bit storage choices: the autotuner's result on MI355X (the
+// "storage16_entries" of the package's tune_gfx950.json).  Half the bytes
+// move, so the balance between memory and arithmetic, and with it the best
+// shape, differs from the FP32 transform's.
+const BuiltinEntry kBuiltinStorage16[] = {
+    {256, 1, 64, "n256_e16_b4_p4_r16.16"},
+    {256, 65, 384, "n256_e16_b16_p4_r16.16_pt"},
+    {256, 385, 768, "n256_e16_b16_p4_r16.16"},
+    {256, 769, 1536, "n256_e4_b4_p4_r4.4.4.4_pt"},
+    {256, 1537, 4096, "n256_e16_b4_p4_r16.16"},
+    {256, 4097, INT64_MAX, "n256_e16_b4_p4_r16.16_pt"},
+    {512, 1, 64, "n512_e16_b8_p4_r16.16.2"},
+    {512, 65, 384, "n512_e16_b2_p4_r16.16.2_pt"},
+    {512, 385, 768, "n512_e16_b2_p4_r16.16.2_pt"},
+    {512, 769, 1536, "n512_e8_b4_p4_r8.8.8"},
+    {512, 1537, 4096, "n512_e8_b4_p4_r8.8.8"},
+    {512, 4097, INT64_MAX, "n512_e8_b4_p4_r8.8.8_pt"},
+    {1024, 1, 64, "n1024_e8_b2_p4_r8.8.8.2"},
+    {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
+    {1024, 385, 768, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
+    {1024, 769, 1536, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
+    {1024, 1537, 4096, "n1024_e16_b1_p4_r16.16.4_pt"},
+    {1024, 4097, INT64_MAX, "n1024_e16_b1_p4_r16.16.4_pt"},
+    {2048, 1, 64, "n2048_e4_b1_p4_r4.4.4.4.4.2"},
+    {2048, 65, 384, "n2048_e16_b1_p4_r16.16.8"},
+    {2048, 385, 768, "n2048_e8_b1_p4_r8.8.8.4_pt"},
+    {2048, 769, 1536, "n2048_e16_b1_p4_r16.16.8_pt"},
+    {2048, 1537, 4096, "n2048_e16_b2_p4_r16.16.8_pt"},
+    {2048, 4097, INT64_MAX, "n2048_e32_c2_b1_p4_r16.16.8_pt"},
+    {4096, 1, 64, "n4096_e8_b1_p4_r8.8.8.8_pt"},
+    {4096, 65, 384, "n4096_e8_b1_p4_r8.8.8.8_pt_tall"},
+    {4096, 385, 768, "n4096_e16_b1_px_r16.16.16_pt"},
+    {4096, 769, 1536, "n4096_e32_b1_p4_r16.16.16_pt_pl"},
+    {4096, 1537, 4096, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
+    {4096, 4097, INT64_MAX, "n4096_e16_b1_p5_r16.16.16_pt"},
+    {8192, 1, 64, "n8192_e16_b1_p4_r16.16.16.2_pt"},
+    {8192, 65, 384, "n8192_e16_b1_p4_r16.16.16.2_pt"},
+    {8192, 385, 768, "n8192_e16_b1_p4_r16.16.16.2_pt"},
+    {8192, 769, 1536, "n8192_e32_c2_b1_p4_r16.16.16.2"},
+    {8192, 1537, 4096, "n8192_e32_c4_b1_p4_r8.8.8.16"},
+    {8192, 4097, INT64_MAX, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
+    {16384, 1, 64, "n16384_e16_b1_p4_r16.16.16.4_pt"},
+    {16384, 65, 384, "n16384_e32_b1_p4_r16.16.16.4_pt"},
+    {16384, 385, 768, "n16384_e32_c2_b1_p4_r16.16.16.4_pt"},
+    {16384, 769, 1536, "n16384_e32_c2_b1_p4_r16.16.16.4_pt"},
+    {16384, 1537, 4096, "n16384_e32_c2_b1_p4_r16.16.16.4_pt"},
+    {16384, 4097, INT64_MAX, "n16384_e32_c2_b1_p4_r16.16.16.4_pt"},
 };
 
 // Built-in fused forward -> weight -> adjoint choices: the autotuner's result
@@ -308,18 +359,18 @@ const BuiltinEntry kBuiltinFilter[] = {
 const BuiltinEntry kBuiltinFused[] = {
     {256, 1, 64, "n256_e4_b4_p4_r4.4.4.4_pt"},
     {256, 65, 384, "n256_e4_b4_p4_r4.4.4.4"},
-    {256, 385, 768, "n256_e4_b4_p4_r4.4.4.4"},
+    {256, 385, 768, "n256_e4_b4_p4_r4.4.4.4_pt"},
     {256, 769, 1536, "n256_e4_b4_p4_r4.4.4.4_pt"},
     {256, 1537, 4096, "n256_e8_b8_p4_r8.8.4"},
     {256, 4097, INT64_MAX, "n256_e16_b16_p4_r16.16_pt"},
-    {512, 1, 64, "n512_e4_b2_p4_r4.4.4.4.2"},
-    {512, 65, 384, "n512_e4_b2_p4_r4.4.4.4.2"},
-    {512, 385, 768, "n512_e4_b2_p4_r4.4.4.4.2"},
+    {512, 1, 64, "n512_e8_b4_p4_r8.8.8_pt"},
+    {512, 65, 384, "n512_e8_b4_p4_r8.8.8_pt"},
+    {512, 385, 768, "n512_e8_b4_p4_r8.8.8"},
     {512, 769, 1536, "n512_e8_b4_p4_r8.8.8"},
     {512, 1537, 4096, "n512_e8_b4_p4_r8.8.8_pt"},
     {512, 4097, INT64_MAX, "n512_e8_b4_p4_r8.8.8_pt"},
     {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
-    {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
+    {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4"},
     {1024, 385, 768, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
     {1024, 769, 1536, "n1024_e8_b2_p4_r8.8.8.2_pt"},
     {1024, 1537, 4096, "n1024_e8_b2_p4_r8.8.8.2_pt"},
@@ -327,27 +378,27 @@ const BuiltinEntry kBuiltinFused[] = {
     {2048, 1, 64, "n2048_e8_b1_p4_r8.8.8.4_pt"},
     {2048, 65, 384, "n2048_e8_b1_p4_r8.8.8.4_pt"},
     {2048, 385, 768, "n2048_e8_b1_p4_r8.8.8.4_pt"},
-    {2048, 769, 1536, "n2048_e8_b1_p4_r8.8.8.4_pt"},
+    {2048, 769, 1536, "n2048_e16_b2_p4_r16.16.8_pt"},
     {2048, 1537, 4096, "n2048_e16_b2_p4_r16.16.8_pt"},
     {2048, 4097, INT64_MAX, "n2048_e16_b2_p4_r16.16.8_pt"},
-    {4096, 1, 64, "n4096_e16_b1_px_r16.16.16_db_pt_tall"},
-    {4096, 65, 384, "n4096_e16_b1_px_r16.16.16_db_pt"},
+    {4096, 1, 64, "n4096_e8_b1_p4_r8.8.8.8_pt"},
+    {4096, 65, 384, "n4096_e8_b1_p4_r8.8.8.8_pt"},
     {4096, 385, 768, "n4096_e16_b1_px_r16.16.16_db_pt"},
-    {4096, 769, 1536, "n4096_e16_b1_p5_r16.16.16_pt"},
-    {4096, 1537, 4096, "n4096_e16_b1_p5_r16.16.16_pt"},
+    {4096, 769, 1536, "n4096_e16_b1_px_r16.16.16_pt"},
+    {4096, 1537, 4096, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
     {4096, 4097, INT64_MAX, "n4096_e16_b1_p5_r16.16.16_pt"},
-    {8192, 1, 64, "n8192_e16_b1_p4_r16.16.16.2_pt"},
+    {8192, 1, 64, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
     {8192, 65, 384, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
-    {8192, 385, 768, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
-    {8192, 769, 1536, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
-    {8192, 1537, 4096, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
-    {8192, 4097, INT64_MAX, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
-    {16384, 1, 64, "n16384_e32_b1_p4_r16.16.16.4_pt"},
-    {16384, 65, 384, "n16384_e32_b1_p4_r16.16.16.4_pt"},
-    {16384, 385, 768, "n16384_e32_b1_p4_r16.16.16.4_pt"},
-    {16384, 769, 1536, "n16384_e32_b1_p4_r16.16.16.4_pt"},
-    {16384, 1537, 4096, "n16384_e32_b1_p4_r16.16.16.4_pt"},
-    {16384, 4097, INT64_MAX, "n16384_e32_b1_p4_r16.16.16.4_pt"},
+    {8192, 385, 768, "n8192_e16_b1_p4_r16.16.16.2_pt"},
+    {8192, 769, 1536, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
+    {8192, 1537, 4096, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
+    {8192, 4097, INT64_MAX, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
+    {16384, 1, 64, "n16384_e16_b1_p4_r16.16.16.4_pt"},
+    {16384, 65, 384, "n16384_e16_b1_p4_r16.16.16.4_pt"},
+    {16384, 385, 768, "n16384_e32_c2_b1_p4_r16.16.16.4_pt"},
+    {16384, 769, 1536, "n16384_e32_c2_b1_p4_r16.16.16.4_pt"},
+    {16384, 1537, 4096, "n16384_e32_c2_b1_p4_r16.16.16.4_pt"},
+    {16384, 4097, INT64_MAX, "n16384_e32_c2_b1_p4_r16.16.16.4_pt"},
 };
 
 // Single-pass fallback when a four-step choice is not wanted.
@@ -419,6 +470,11 @@ const SingleVariant* tuned_filter_variant(int64_t n, int64_t batch) {
 // The fused forward -> weight -> adjoint kernel's variant for (n, batch).
 const SingleVariant* tuned_fused_variant(int64_t n, int64_t batch) {
   return tuned_table_variant(kBuiltinFused, g_tune_fused, n, batch);
+}
+
+// The 16-bit storage transform's variant for (n, batch).
+const SingleVariant* tuned_storage16_variant(int64_t n, int64_t batch) {
+  return tuned_table_variant(kBuiltinStorage16, g_tune_storage16, n, batch);
 }
 
 const SingleVariant* tuned_variant(int64_t n, int64_t batch) {
@@ -539,9 +595,10 @@ int load_tune_file_locked(const char* path) {
       out->push_back({n, bmin, bmax, v, nullptr});
     }
   };
-  std::vector<TuneEntry> add_filter, add_fused;
+  std::vector<TuneEntry> add_filter, add_fused, add_storage16;
   single_entries("filter_entries", &add_filter);
   single_entries("fused_entries", &add_fused);
+  single_entries("storage16_entries", &add_storage16);
   if (const json::Value* rs = doc.get("ragged"); rs && rs->kind == json::Value::Array) {
     for (const json::Value& e : rs->arr) {
       const std::string* shape = str(e, "shape");
@@ -556,6 +613,7 @@ int load_tune_file_locked(const char* path) {
   g_tune.insert(g_tune.end(), add.begin(), add.end());
   g_tune_filter.insert(g_tune_filter.end(), add_filter.begin(), add_filter.end());
   g_tune_fused.insert(g_tune_fused.end(), add_fused.begin(), add_fused.end());
+  g_tune_storage16.insert(g_tune_storage16.end(), add_storage16.begin(), add_storage16.end());
   return FFT_SUCCESS;
 }
 
@@ -608,12 +666,17 @@ struct stockfft_plan_s {
   void* d_tw_filter = nullptr;               // its twiddles when it differs from sv
   const SingleVariant* sv_fused = nullptr;   // fused forward/adjoint kernel shape
   void* d_tw_fused = nullptr;                // its twiddles when it differs from both
+  const SingleVariant* sv_storage16 = nullptr;  // 16-bit storage transform shape
+  void* d_tw_storage16 = nullptr;               // its twiddles when it differs from the rest
 };
 
 // Twiddle table of a single-pass shape held by the plan (its own or one of
 // the two-transform kernels').
 static const void* plan_table(const stockfft_plan_s* p, const SingleVariant* v) {
-  return v == p->sv ? p->d_tw : v == p->sv_filter ? p->d_tw_filter : p->d_tw_fused;
+  if (v == p->sv) return p->d_tw;
+  if (v == p->sv_filter) return p->d_tw_filter;
+  if (v == p->sv_fused) return p->d_tw_fused;
+  return p->d_tw_storage16;
 }
 
 static void free_plan(stockfft_plan_s* p) {
@@ -623,6 +686,7 @@ static void free_plan(stockfft_plan_s* p) {
   if (p->d_ws) (void)hipFree(p->d_ws);
   if (p->d_tw_filter) (void)hipFree(p->d_tw_filter);
   if (p->d_tw_fused) (void)hipFree(p->d_tw_fused);
+  if (p->d_tw_storage16) (void)hipFree(p->d_tw_storage16);
   if (p->d_counters) (void)hipFree(p->d_counters);
   if (p->d_tw_mma) (void)hipFree(p->d_tw_mma);
   delete p;
@@ -700,19 +764,34 @@ extern "C" int fft_plan_config(fft_plan_t* plan, int64_t n, int64_t batch, int d
     // forward -> weight -> adjoint): the named variant, else each kernel's
     // own tuned choice (timed on that kernel: its register pressure differs
     // from a single transform's), each with its twiddles.
-    p->sv_filter = variant ? sv : tuned_filter_variant(n, batch);
+    // (A named variant without the two-transform kernels -- a paired-lane
+    // shape whose output and input register orders differ -- takes the
+    // tuned choice for them.)
+    p->sv_filter = variant && sv->filter ? sv : tuned_filter_variant(n, batch);
     if (!p->sv_filter->filter) p->sv_filter = sv;
     if (p->sv_filter != sv) {
       std::vector<float> ftw;
       build_stockham_twiddles(*p->sv_filter, ftw);
       rc = upload(ftw, &p->d_tw_filter);
     }
-    const SingleVariant* fv = variant ? sv : tuned_fused_variant(n, batch);
+    const SingleVariant* fv = variant && sv->fused ? sv : tuned_fused_variant(n, batch);
     p->sv_fused = fv->fused ? fv : (sv->fused ? sv : nullptr);
     if (!rc && p->sv_fused && p->sv_fused != sv && p->sv_fused != p->sv_filter) {
       std::vector<float> utw;
       build_stockham_twiddles(*p->sv_fused, utw);
       rc = upload(utw, &p->d_tw_fused);
+    }
+  }
+  if (!rc && !fs) {
+    // The transform with 16-bit storage (either direction): the named
+    // variant, else its own tuned choice.
+    p->sv_storage16 = variant ? sv : tuned_storage16_variant(n, batch);
+    if (!p->sv_storage16->launch_f16) p->sv_storage16 = sv;
+    const SingleVariant* h = p->sv_storage16;
+    if (h != sv && h != p->sv_filter && h != p->sv_fused) {
+      std::vector<float> htw;
+      build_stockham_twiddles(*h, htw);
+      rc = upload(htw, &p->d_tw_storage16);
     }
   }
   if (!rc && p->sv_fused) {
@@ -794,7 +873,8 @@ extern "C" int fft_exec_io(fft_plan_t plan, const void* in, void* out, int io, v
   if (((uintptr_t)in & 3u) || ((uintptr_t)out & 3u)) return FFT_MISALIGNED;
   const size_t bytes = (size_t)plan->n * (size_t)plan->batch * 4;
   if (ranges_partially_overlap(in, out, bytes)) return FFT_OVERLAP;
-  const LaunchFn fn = io == FFT_IO_C16 ? plan->sv->launch_f16 : plan->sv->launch_bf16;
+  const SingleVariant* hv = plan->sv_storage16 ? plan->sv_storage16 : plan->sv;
+  const LaunchFn fn = io == FFT_IO_C16 ? hv->launch_f16 : hv->launch_bf16;
   if (!mma && !fn) return FFT_UNSUPPORTED;
   DeviceGuard g(plan->device);
   const bool inv = plan->direction == FFT_BACKWARD;
@@ -803,7 +883,7 @@ extern "C" int fft_exec_io(fft_plan_t plan, const void* in, void* out, int io, v
     e = (io == FFT_IO_C16_MMA ? launch_mma_f16 : launch_mma_bf16)(
         plan->n, in, out, plan->tw_mma, plan->batch, inv, (hipStream_t)stream);
   } else {
-    e = fn(in, out, plan->d_tw, plan->batch, inv, (hipStream_t)stream);
+    e = fn(in, out, plan_table(plan, hv), plan->batch, inv, (hipStream_t)stream);
   }
   return e == hipSuccess ? FFT_SUCCESS : hip_fail(e);
 }
@@ -993,6 +1073,15 @@ extern "C" int fft_tune_query_fused(int64_t n, int64_t batch, char* buf, int64_t
   return put_text(v->name, buf, cap);
 }
 
+extern "C" int fft_tune_query_storage16(int64_t n, int64_t batch, char* buf, int64_t cap) {
+  if (!buf) return FFT_INVALID_POINTER;
+  if (!valid_single_size(n)) return FFT_INVALID_SIZE;
+  if (batch < 1) return FFT_INVALID_BATCH;
+  const SingleVariant* v = tuned_storage16_variant(n, batch);
+  if (!v) return FFT_INVALID_SIZE;
+  return put_text(v->name, buf, cap);
+}
+
 extern "C" int fft_set_launch_limit(int64_t max_groups) {
   set_max_groups_per_launch(max_groups > 0 ? max_groups : kDefaultMaxGroupsPerLaunch);
   return FFT_SUCCESS;
@@ -1004,6 +1093,7 @@ extern "C" int fft_tune_clear(void) {
   g_tune.clear();
   g_tune_filter.clear();
   g_tune_fused.clear();
+  g_tune_storage16.clear();
   return FFT_SUCCESS;
 }
 
@@ -1035,12 +1125,14 @@ static std::string describe_single(const SingleVariant& v) {
                 "\"lds_layout\":\"%s\","
                 "\"passes\":%d,\"radices\":%s,\"exchange_rounds\":%d,\"threads\":%d,"
                 "\"lds_bytes\":%d,\"twiddle_entries\":%d,\"barriers\":%d,"
-                "\"double_buffered\":%s,\"twiddle_schedule\":%d,\"paired_twiddles\":%s}",
+                "\"double_buffered\":%s,\"twiddle_schedule\":%d,\"paired_twiddles\":%s,\"paired_lanes\":%s,"
+                "\"fused_kernels\":%s}",
                 v.name, v.n, v.e, v.t, v.tpb, v.padlog,
                 v.padlog > 0 ? "pad" : v.padlog < 0 ? "xor" : "none", v.npass, radices_json(v).c_str(),
                 v.chunks, v.threads, v.lds_bytes, v.tw_elems, barriers_of(v),
                 v.double_buffered ? "true" : "false", v.twiddle_schedule,
-                v.paired_twiddles ? "true" : "false");
+                v.paired_twiddles ? "true" : "false", v.paired_lanes ? "true" : "false",
+                v.fused && v.filter ? "true" : "false");
   return buf;
 }
 
@@ -1111,6 +1203,9 @@ extern "C" int fft_plan_describe(fft_plan_t plan, char* buf, int64_t cap) {
                                    : "") +
                   (plan->sv_fused ? ",\"fused_variant\":\"" + std::string(plan->sv_fused->name) + "\""
                                   : "") +
+                  (plan->sv_storage16
+                       ? ",\"storage16_variant\":\"" + std::string(plan->sv_storage16->name) + "\""
+                       : "") +
                   "}";
   return put_text(s, buf, cap);
 }

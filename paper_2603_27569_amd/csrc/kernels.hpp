@@ -29,26 +29,111 @@ __device__ __forceinline__ void store_stream(c32* p, c32 a) {
   __builtin_nontemporal_store(v, reinterpret_cast<f32x2*>(p));
 }
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// Row position of register slot m for the first pass's inputs (in_position)
+// and the last pass's outputs (out_position): t + m T, or the paired order.
 template <class S>
-__device__ __forceinline__ void global_load_row(c32 (&a)[S::E], const c32* src, int t, bool live) {
-  if (live) {
+__device__ __forceinline__ int in_position(int t, int m) { return read_position<S, 0>(t, m); }
+template <class S>
+__device__ __forceinline__ int out_position(int t, int m) { return read_position<S, S::P - 1>(t, m); }
+
+// Loads one row unconditionally: a slot past the last row is pointed at a
+// row that exists (its result is never stored), which costs nothing, where
+// zeroing its registers costs one instruction per register on every lane.
+template <class S>
+__device__ __forceinline__ void global_load_row(c32 (&a)[S::E], const c32* src, int t) {
+  if constexpr (paired_pass<S, 0>()) {
+    // slots m and m + 1 (m even) are adjacent elements: one 16-byte load
 #pragma unroll
-    for (int m = 0; m < S::E; ++m) a[m] = load_stream(src + t + m * S::T);
+    for (int m = 0; m < S::E; m += 2) {
+      const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(src + in_position<S>(t, m)));
+      a[m] = c32{v.x, v.y};
+      a[m + 1] = c32{v.z, v.w};
+    }
   } else {
 #pragma unroll
-    for (int m = 0; m < S::E; ++m) a[m] = c32{0.f, 0.f};
+    for (int m = 0; m < S::E; ++m) a[m] = load_stream(src + t + m * S::T);
   }
+}
+
+// The same through one buffer descriptor over the workgroup's rows: lane_row
+// is the lane's row offset from the descriptor's base in elements.  Both
+// orders of register slots are lane part + slot part (position(t, m) =
+// position(t, 0) + position(0, m)), the slot part a constant.
+template <class S>
+__device__ __forceinline__ void buffer_load_row(c32 (&a)[S::E], const Buf& b, int lane_row, int t) {
+  const int voff = 8 * (lane_row + in_position<S>(t, 0));
+  if constexpr (paired_pass<S, 0>()) {
+#pragma unroll
+    for (int m = 0; m < S::E; m += 2) {
+      const u32x4 v = b.ld128<kNT>(voff, 8 * in_position<S>(0, m));
+      a[m] = c32{__uint_as_float(v.x), __uint_as_float(v.y)};
+      a[m + 1] = c32{__uint_as_float(v.z), __uint_as_float(v.w)};
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < S::E; ++m) {
+      const u32x2 v = b.ld64<kNT>(voff, 8 * in_position<S>(0, m));
+      a[m] = c32{__uint_as_float(v.x), __uint_as_float(v.y)};
+    }
+  }
+}
+template <class S>
+__device__ __forceinline__ void buffer_store_row(const c32 (&a)[S::E], const Buf& b, int lane_row,
+                                                 int t, bool live) {
+  if (!live) return;
+  const int voff = 8 * (lane_row + out_position<S>(t, 0));
+  if constexpr (paired_pass<S, S::P - 1>()) {
+#pragma unroll
+    for (int m = 0; m < S::E; m += 2)
+      b.st128<kNT>(u32x4{__float_as_uint(a[m].x), __float_as_uint(a[m].y), __float_as_uint(a[m + 1].x),
+                         __float_as_uint(a[m + 1].y)},
+                   voff, 8 * out_position<S>(0, m));
+  } else {
+#pragma unroll
+    for (int m = 0; m < S::E; ++m)
+      b.st64<kNT>(u32x2{__float_as_uint(a[m].x), __float_as_uint(a[m].y)}, voff, 8 * out_position<S>(0, m));
+  }
+}
+
+// Every launcher gives a workgroup TPB consecutive rows from a grid of
+// ceil(rows / TPB) workgroups, so with one transform per workgroup every row
+// is live; only the last workgroup of a TPB > 1 shape can hold dead slots.
+// Those load the last row (row_src) and store nothing.
+template <class S>
+__device__ __forceinline__ bool row_live(int64_t row, int64_t rows) {
+  return S::TPB == 1 || row < rows;
+}
+template <class S>
+__device__ __forceinline__ int64_t row_src(int64_t row, int64_t rows) {
+  return row_live<S>(row, rows) ? row : rows - 1;
+}
+// The element offset of a slot's source row from its workgroup's first row
+// (below TPB N, so a 32-bit buffer offset).
+template <class S>
+__device__ __forceinline__ int slot_src(int slot, int64_t row, int64_t rows) {
+  return S::TPB == 1 ? 0 : (int)(row_src<S>(row, rows) - (row - slot)) * S::N;
 }
 
 template <class S, bool STREAM = true>
 __device__ __forceinline__ void global_store_row(const c32 (&a)[S::E], c32* dst, int t, bool live) {
   if (live) {
+    if constexpr (paired_pass<S, S::P - 1>()) {
+      static_assert(STREAM, "paired stores stream");
 #pragma unroll
-    for (int m = 0; m < S::E; ++m) {
-      if constexpr (STREAM)
-        store_stream(dst + t + m * S::T, a[m]);
-      else
-        dst[t + m * S::T] = a[m];
+      for (int m = 0; m < S::E; m += 2) {
+        const f32x4 v = {a[m].x, a[m].y, a[m + 1].x, a[m + 1].y};
+        __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(dst + out_position<S>(t, m)));
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < S::E; ++m) {
+        if constexpr (STREAM)
+          store_stream(dst + t + m * S::T, a[m]);
+        else
+          dst[t + m * S::T] = a[m];
+      }
     }
   }
 }
@@ -64,12 +149,13 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham(const c32* in, 
   const int slot = S::TPB == 1 ? 0 : tid / S::T;  // one transform: the row base is uniform
   const int t = tid - slot * S::T;
   const int64_t row = (int64_t)blockIdx.x * S::TPB + slot;
-  const bool live = row < rows;
+  const bool live = row_live<S>(row, rows);
+  const int64_t row0 = (int64_t)blockIdx.x * S::TPB;
   c32* lds = lds_all + slot * S::LDS_ELEMS;
   c32 a[S::E];
-  global_load_row<S>(a, in + row * S::N, t, live);
+  buffer_load_row<S>(a, Buf(in + row0 * S::N), slot_src<S>(slot, row, rows), t);
   run_passes<S, INV>(a, lds, tw, t);
-  global_store_row<S>(a, out + row * S::N, t, live);
+  buffer_store_row<S>(a, Buf(out + row0 * S::N), slot * S::N, t, live);
 }
 
 template <class S>
@@ -129,22 +215,39 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham_io(const uint32
   const int slot = S::TPB == 1 ? 0 : tid / S::T;  // one transform: the row base is uniform
   const int t = tid - slot * S::T;
   const int64_t row = (int64_t)blockIdx.x * S::TPB + slot;
-  const bool live = row < rows;
+  const bool live = row_live<S>(row, rows);
+  const int64_t row0 = (int64_t)blockIdx.x * S::TPB;
   c32* lds = lds_all + slot * S::LDS_ELEMS;
   c32 a[S::E];
-  if (live) {
-    const uint32_t* src = in + row * S::N;
+  {
+    // 4 bytes per value; lane part + constant slot part as in buffer_load_row
+    const Buf src(in + row0 * S::N);
+    const int voff = 4 * (slot_src<S>(slot, row, rows) + in_position<S>(t, 0));
+    if constexpr (paired_pass<S, 0>()) {
+      // slots m and m + 1 (m even) are adjacent values: one 8-byte load
 #pragma unroll
-    for (int m = 0; m < S::E; ++m) a[m] = IO::load(__builtin_nontemporal_load(src + t + m * S::T));
-  } else {
+      for (int m = 0; m < S::E; m += 2) {
+        const u32x2 v = src.ld64<kNT>(voff, 4 * in_position<S>(0, m));
+        a[m] = IO::load(v.x);
+        a[m + 1] = IO::load(v.y);
+      }
+    } else {
 #pragma unroll
-    for (int m = 0; m < S::E; ++m) a[m] = c32{0.f, 0.f};
+      for (int m = 0; m < S::E; ++m) a[m] = IO::load(src.ld32<kNT>(voff, 4 * in_position<S>(0, m)));
+    }
   }
   run_passes<S, INV>(a, lds, tw, t);
   if (live) {
-    uint32_t* dst = out + row * S::N;
+    const Buf dst(out + row0 * S::N);
+    const int voff = 4 * (slot * S::N + out_position<S>(t, 0));
+    if constexpr (paired_pass<S, S::P - 1>()) {
 #pragma unroll
-    for (int m = 0; m < S::E; ++m) __builtin_nontemporal_store(IO::store(a[m]), dst + t + m * S::T);
+      for (int m = 0; m < S::E; m += 2)
+        dst.st64<kNT>(u32x2{IO::store(a[m]), IO::store(a[m + 1])}, voff, 4 * out_position<S>(0, m));
+    } else {
+#pragma unroll
+      for (int m = 0; m < S::E; ++m) dst.st32<kNT>(IO::store(a[m]), voff, 4 * out_position<S>(0, m));
+    }
   }
 }
 
@@ -192,6 +295,7 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_spectral_energy(
     const c32* x, const float* __restrict__ w, const float* __restrict__ scale, c32* grad,
     float* row_loss, const c32* tw, int64_t rows, float* total_out, unsigned* counters,
     float* row_loss_all, int64_t rows_all, unsigned groups_all, unsigned gbase) {
+  static_assert(round_trip_layout<S>(), "the adjoint runs on the forward's output registers");
   __shared__ alignas(16) c32 lds_all[S::TPB * S::LDS_ELEMS];
   __shared__ float red[(S::THREADS + 63) / 64];
   __shared__ int is_last;
@@ -199,17 +303,20 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_spectral_energy(
   const int slot = S::TPB == 1 ? 0 : tid / S::T;  // one transform: the row base is uniform
   const int t = tid - slot * S::T;
   const int64_t row = (int64_t)blockIdx.x * S::TPB + slot;
-  const bool live = row < rows;
+  const bool live = row_live<S>(row, rows);
+  const int64_t row0 = (int64_t)blockIdx.x * S::TPB;
   c32* lds = lds_all + slot * S::LDS_ELEMS;
   c32 a[S::E];
-  global_load_row<S>(a, x + row * S::N, t, live);
+  buffer_load_row<S>(a, Buf(x + row0 * S::N), slot_src<S>(slot, row, rows), t);
   run_passes<S, false>(a, lds, tw, t);
 
   const float sc = scale ? 2.0f * scale[0] : 2.0f;
   float acc = 0.f;
+  const Buf wb(w);
+  const int wv = 4 * out_position<S>(t, 0);
 #pragma unroll
   for (int m = 0; m < S::E; ++m) {
-    const float wq = w[t + m * S::T];
+    const float wq = __uint_as_float(wb.ld32(wv, 4 * out_position<S>(0, m)));
     const float w2 = wq * wq;
     const c32 y = a[m];
     acc += w2 * (y.x * y.x + y.y * y.y);
@@ -236,7 +343,7 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_spectral_energy(
   }
   if (grad != nullptr) {  // uniform across the launch
     run_passes<S, true>(a, lds, tw, t);
-    global_store_row<S>(a, grad + row * S::N, t, live);
+    buffer_store_row<S>(a, Buf(grad + row0 * S::N), slot * S::N, t, live);
   }
   if (total_out != nullptr) {  // uniform across the launch
     // The loss total: the last workgroup to finish adds all rows in a fixed
@@ -324,26 +431,31 @@ template <class S>
 __global__ __launch_bounds__(S::THREADS, S::WPE) void k_matched_filter(const c32* x, const c32* __restrict__ h,
                                                                c32* out, const c32* tw,
                                                                int64_t rows) {
+  static_assert(round_trip_layout<S>(), "the inverse runs on the forward's output registers");
   __shared__ alignas(16) c32 lds_all[S::TPB * S::LDS_ELEMS];
   const int tid = threadIdx.x;
   const int slot = S::TPB == 1 ? 0 : tid / S::T;  // one transform: the row base is uniform
   const int t = tid - slot * S::T;
   const int64_t row = (int64_t)blockIdx.x * S::TPB + slot;
-  const bool live = row < rows;
+  const bool live = row_live<S>(row, rows);
+  const int64_t row0 = (int64_t)blockIdx.x * S::TPB;
   c32* lds = lds_all + slot * S::LDS_ELEMS;
   c32 a[S::E];
-  global_load_row<S>(a, x + row * S::N, t, live);
+  buffer_load_row<S>(a, Buf(x + row0 * S::N), slot_src<S>(slot, row, rows), t);
   run_passes<S, false>(a, lds, tw, t);
   constexpr float inv_n = 1.0f / float(S::N);  // a power of two: exact
+  const Buf hb(h);
+  const int hv = 8 * out_position<S>(t, 0);
 #pragma unroll
   for (int m = 0; m < S::E; ++m) {
-    const c32 hq = h[t + m * S::T];
+    const u32x2 hw = hb.ld64(hv, 8 * out_position<S>(0, m));
+    const c32 hq = c32{__uint_as_float(hw.x), __uint_as_float(hw.y)};
     const c32 y = cmulc(a[m], hq);
     a[m] = c32{y.x * inv_n, y.y * inv_n};
   }
   __syncthreads();
   run_passes<S, true>(a, lds, tw, t);
-  global_store_row<S>(a, out + row * S::N, t, live);
+  buffer_store_row<S>(a, Buf(out + row0 * S::N), slot * S::N, t, live);
 }
 
 template <class S>
@@ -378,6 +490,7 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_four_step_columns(const 
                                                                   const c32* tw,
                                                                   int64_t rows) {
   static_assert(S::TPB == 1, "four-step sub-transforms use one transform per workgroup");
+  static_assert(!paired_lanes<S>::value, "four-step sub-transforms use the plain lane order");
   __shared__ alignas(16) c32 lds[S::LDS_ELEMS];
   const int64_t i = blockIdx.x;
   const int64_t grp = i / (kXcds * N1);

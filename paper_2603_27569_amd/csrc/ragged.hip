@@ -133,7 +133,9 @@ __device__ __forceinline__ void run_class_serial(int pos, int end, const RaggedA
   for (;;) {
     const bool live = slot < tc.count;
     c32 a[S::E];
-    global_load_row<S>(a, A.in + off, t, live);
+    // A dead slot (off = 0) reads the buffer's first N elements, which exist:
+    // a length class has a task only if an item of that length does.
+    global_load_row<S>(a, A.in + off, t);
     const bool more = pos + 1 < end;
     Task tn = tc;
     int64_t off_n = 0;
@@ -189,7 +191,7 @@ int shape_index(const char* name) {
 
 // Built-in per-length shape: the autotuner's choice on MI355X (the package's
 // tune_gfx950.json).
-constexpr int kBuiltinShape[kClasses] = {0, 3, 4, 6, 8, 11, 13};
+constexpr int kBuiltinShape[kClasses] = {1, 2, 4, 6, 8, 11, 13};
 int builtin_shape(int64_t n) { return kBuiltinShape[ilog2(n) - 8]; }
 
 std::mutex g_rtune_mu;

@@ -28,6 +28,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "buffer.hpp"
+
 namespace stockfft {
 
 // ------------------------------------------------------------------ complex
@@ -231,6 +233,21 @@ struct ShapeX {
     else if constexpr (PADLOG < 0) return i ^ (((i >> 4) & 7) << 1);
     else return i;
   }
+  // pidx(l + c) for a lane part l >= 0 and a part c >= 0 that is a constant
+  // once the caller's loops are unrolled.  With padding, the pad count of
+  // l + c is that of l + (c mod 2^PADLOG) plus c / 2^PADLOG, so one shift of
+  // the lane part serves every c with the same low bits (all of them when
+  // the lane part's low bits are known zero), and the rest folds into the
+  // access's immediate offset instead of costing two vector instructions
+  // per access.
+  __device__ __forceinline__ static int pidx(int l, int c) {
+    if constexpr (PADLOG > 0) {
+      constexpr int M = (1 << PADLOG) - 1;
+      return l + c + ((l + (c & M)) >> PADLOG) + (c >> PADLOG);
+    } else {
+      return pidx(l + c);
+    }
+  }
 };
 
 // Double-buffered exchange: consecutive exchanges alternate between two LDS
@@ -274,6 +291,62 @@ struct PairedTwiddles : Base {
   static constexpr int TW_ELEMS = tw_off(Base::P);
 };
 
+// Paired lanes: in the first pass and in the last pass, where a lane does
+// BPT = E / R >= 2 butterflies, it takes BPT consecutive ones, j = BPT t + b,
+// instead of j = t + b T.  The legs it then reads from global memory (first
+// pass, legs j + r N/R) and writes to it (last pass, outputs j + k N/R) are
+// BPT adjacent elements: one 16-byte access carries two complex64 values (an
+// 8- or 16-byte access two or four 16-bit pairs) where the plain convention
+// needs one access per value.  The passes in between keep the plain
+// convention; only the first exchange's writes and the last exchange's reads
+// see the other butterfly order.  With exchange rounds (C > 1) the first
+// exchange's round h is written by the lanes t in [h T / C, (h + 1) T / C),
+// whole waves when T / C is a multiple of 64.
+template <class Base>
+struct PairedLanes : Base {
+  static constexpr bool PL = true;
+  static_assert(Base::E / Base::radix(0) >= 2 || Base::E / Base::radix(Base::P - 1) >= 2,
+                "paired lanes need two butterflies per lane in the first or the last pass");
+};
+
+template <class S, class = void>
+struct paired_lanes : std::false_type {};
+template <class S>
+struct paired_lanes<S, std::void_t<decltype(S::PL)>> : std::integral_constant<bool, S::PL> {};
+
+// Whether pass p runs a lane's butterflies in the paired order.
+template <class S, int p>
+constexpr bool paired_pass() {
+  if constexpr (!paired_lanes<S>::value) return false;
+  else return (p == 0 || p == S::P - 1) && S::E / S::radix(p) >= 2;
+}
+
+// Butterfly index of a lane's b-th butterfly in pass p.
+template <class S, int p>
+__device__ __forceinline__ int bfly_index(int t, int b) {
+  if constexpr (paired_pass<S, p>()) return (S::E / S::radix(p)) * t + b;
+  else return t + b * S::T;
+}
+
+// Buffer position that pass p reads into register slot m: leg m / BPT of
+// the lane's butterfly m mod BPT, at j + (m / BPT) N / R.
+template <class S, int p>
+__device__ __forceinline__ int read_position(int t, int m) {
+  constexpr int BPT = S::E / S::radix(p);
+  if constexpr (paired_pass<S, p>()) return BPT * t + (m % BPT) + (m / BPT) * (S::T * BPT);
+  else return t + m * S::T;
+}
+
+// Whether a transform's output register layout (the last pass's) is the
+// input layout of the first pass, so that a second transform can run on the
+// registers in place (the fused kernels).
+template <class S>
+constexpr bool round_trip_layout() {
+  if constexpr (!paired_lanes<S>::value) return true;
+  else return paired_pass<S, 0>() == paired_pass<S, S::P - 1>() &&
+              S::radix(0) == S::radix(S::P - 1);
+}
+
 template <class S, class = void>
 struct paired_twiddles : std::false_type {};
 template <class S>
@@ -287,16 +360,20 @@ __device__ __forceinline__ void fetch_twiddles(c32 (&dst)[CAP], int off, const c
   constexpr int R = S::radix(p);
   constexpr int NS = S::ns(p);
   static_assert(R - 1 <= CAP, "twiddle registers");
+  const Buf tb(twp);  // the lane part of every offset is k
   if constexpr (paired_twiddles<S>::value && R >= 4) {
 #pragma unroll
     for (int q = 0; q < R / 2; ++q) {
-      const float4 v = *reinterpret_cast<const float4*>(twp + 2 * (q * NS + k));
-      dst[off + 2 * q] = c32{v.x, v.y};
-      if (2 * q + 1 < R - 1) dst[off + 2 * q + 1] = c32{v.z, v.w};
+      const u32x4 v = tb.ld128(16 * k, 16 * q * NS);
+      dst[off + 2 * q] = c32{__uint_as_float(v.x), __uint_as_float(v.y)};
+      if (2 * q + 1 < R - 1) dst[off + 2 * q + 1] = c32{__uint_as_float(v.z), __uint_as_float(v.w)};
     }
   } else {
 #pragma unroll
-    for (int r = 1; r < R; ++r) dst[off + r - 1] = twp[(r - 1) * NS + k];
+    for (int r = 1; r < R; ++r) {
+      const u32x2 v = tb.ld64(8 * k, 8 * (r - 1) * NS);
+      dst[off + r - 1] = c32{__uint_as_float(v.x), __uint_as_float(v.y)};
+    }
   }
 }
 
@@ -318,7 +395,7 @@ __device__ __forceinline__ void load_twiddles(c32 (&w)[S::TW_REGS], const c32* t
     const c32* twp = tw + S::tw_off(p);
 #pragma unroll
     for (int b = 0; b < BPT; ++b) {
-      const int k = (t + b * S::T) & (NS - 1);
+      const int k = bfly_index<S, p>(t, b) & (NS - 1);
       fetch_twiddles<S, p>(w, S::tw_lane_off(p) + b * (R - 1), twp, k);
     }
     // Keep prefetched loads here: the scheduler would otherwise sink them to
@@ -346,7 +423,7 @@ __device__ __forceinline__ void pass_compute(c32 (&a)[S::E], c32 (&w)[S::TW_REGS
       for (int r = 0; r < R; ++r) v[r] = a[b + r * BPT];
       if constexpr (p > 0) {
         c32 wb[R - 1];
-        fetch_twiddles<S, p>(wb, 0, tw + S::tw_off(p), (t + b * S::T) & (NS - 1));
+        fetch_twiddles<S, p>(wb, 0, tw + S::tw_off(p), bfly_index<S, p>(t, b) & (NS - 1));
 #pragma unroll
         for (int r = 1; r < R; ++r) v[r] = ctw<INV>(v[r], wb[r - 1]);
       }
@@ -375,40 +452,71 @@ __device__ __forceinline__ void pass_compute(c32 (&a)[S::E], c32 (&w)[S::TW_REGS
   }
 }
 
-// Exchange after pass p: write the outputs to their Stockham positions and
-// read the next pass's inputs (positions t + m T), in C rounds of N/C
-// elements.  The buffer must be free on entry; it is free again on return
-// unless the next pass is the last (which reads nothing more from it).
+// Writes butterfly b's R outputs of pass p to their Stockham positions in
+// the exchange buffer (offset by the round's chunk start).
 template <class S, int p>
-__device__ __forceinline__ void exchange(c32 (&a)[S::E], c32* lds, int t) {
+__device__ __forceinline__ void exchange_write(const c32 (&a)[S::E], c32* lds, int t, int b,
+                                               int chunk0) {
   constexpr int R = S::radix(p);
   constexpr int NS = S::ns(p);
   constexpr int BPT = S::E / R;
+  // Leg 0's position (j / Ns) Ns R + j mod Ns is the lane part at b = 0
+  // plus the part of b (powers of two T and Ns: j = t + b T never carries
+  // across a multiple of Ns that t alone would not, and the paired order
+  // only writes in the first pass, where Ns = 1).
+  const auto wpos = [](int j) { return (j / NS) * NS * R + (j & (NS - 1)); };
+  const int l = wpos(bfly_index<S, p>(t, 0));
+  const int c = wpos(bfly_index<S, p>(0, b)) - chunk0;
+  if constexpr (S::PADLOG < 0 && NS == 1) {
+    // The swizzle keeps the pairs of this butterfly's consecutive outputs
+    // adjacent and 16-byte aligned: one 16-byte store per pair.
+#pragma unroll
+    for (int k = 0; k < R; k += 2) {
+      const c32 u = a[b + k * BPT], v = a[b + (k + 1) * BPT];
+      *reinterpret_cast<float4*>(lds + S::pidx(l + c + k)) = float4{u.x, u.y, v.x, v.y};
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < R; ++k) lds[S::pidx(l, c + k * NS)] = a[b + k * BPT];
+  }
+}
+
+// Exchange after pass p: write the outputs to their Stockham positions and
+// read the next pass's inputs (positions t + m T, or the paired order when the
+// next pass is a paired last pass), in C rounds of N/C elements.  The buffer
+// must be free on entry; it is free again on return unless the next pass is
+// the last (which reads nothing more from it).
+template <class S, int p>
+__device__ __forceinline__ void exchange(c32 (&a)[S::E], c32* lds, int t) {
+  constexpr int R = S::radix(p);
+  constexpr int BPT = S::E / R;
   constexpr int BPC = BPT / S::C;  // butterflies per chunk
   constexpr int MPC = S::E / S::C;  // read slots per chunk
+  constexpr bool PW = paired_pass<S, p>();      // paired writes (first pass)
+  constexpr bool PR = paired_pass<S, p + 1>();  // paired reads (for the last pass)
+  static_assert(!PW || p == 0, "only the first pass writes in the paired order");
+  static_assert(!PW || S::C == 1 || S::T % S::C == 0, "paired rounds split by lanes");
+  static_assert(!PR || S::C == 1 || S::radix(p + 1) % S::C == 0, "paired rounds split by legs");
   c32 nxt[S::E];
 #pragma unroll
   for (int h = 0; h < S::C; ++h) {
     if (h > 0) __syncthreads();  // the previous round's reads are done
+    if constexpr (PW) {
+      // Lane t's butterflies all fall in chunk t / (T / C).
+      if (S::C == 1 || t / (S::T / S::C) == h) {
 #pragma unroll
-    for (int b = h * BPC; b < (h + 1) * BPC; ++b) {
-      const int j = t + b * S::T;
-      const int base = (j / NS) * NS * R + (j & (NS - 1)) - h * S::CHUNK;
-      if constexpr (S::PADLOG < 0 && NS == 1) {
-        // The swizzle keeps the pairs of this butterfly's consecutive
-        // outputs adjacent and 16-byte aligned: one 16-byte store per pair.
-#pragma unroll
-        for (int k = 0; k < R; k += 2) {
-          const c32 u = a[b + k * BPT], v = a[b + (k + 1) * BPT];
-          *reinterpret_cast<float4*>(lds + S::pidx(base + k)) = float4{u.x, u.y, v.x, v.y};
-        }
-      } else {
-#pragma unroll
-        for (int k = 0; k < R; ++k) lds[S::pidx(base + k * NS)] = a[b + k * BPT];
+        for (int b = 0; b < BPT; ++b) exchange_write<S, p>(a, lds, t, b, h * S::CHUNK);
       }
+    } else {
+#pragma unroll
+      for (int b = h * BPC; b < (h + 1) * BPC; ++b) exchange_write<S, p>(a, lds, t, b, h * S::CHUNK);
     }
     __syncthreads();
-    if constexpr (S::PADLOG < 0 && S::T % 128 == 0 && S::CHUNK % 128 == 0) {
+    if constexpr (PR) {
+#pragma unroll
+      for (int m = h * MPC; m < (h + 1) * MPC; ++m)
+        nxt[m] = lds[S::pidx(read_position<S, p + 1>(t, 0), read_position<S, p + 1>(0, m) - h * S::CHUNK)];
+    } else if constexpr (S::PADLOG < 0 && S::T % 128 == 0 && S::CHUNK % 128 == 0) {
       // The swizzle leaves bits 7 and up alone, so the read positions
       // t + m T stay a constant stride apart after it.
       const int base = S::pidx(t);
@@ -416,7 +524,7 @@ __device__ __forceinline__ void exchange(c32 (&a)[S::E], c32* lds, int t) {
       for (int m = h * MPC; m < (h + 1) * MPC; ++m) nxt[m] = lds[base + m * S::T - h * S::CHUNK];
     } else {
 #pragma unroll
-      for (int m = h * MPC; m < (h + 1) * MPC; ++m) nxt[m] = lds[S::pidx(t + m * S::T - h * S::CHUNK)];
+      for (int m = h * MPC; m < (h + 1) * MPC; ++m) nxt[m] = lds[S::pidx(t, m * S::T - h * S::CHUNK)];
     }
   }
 #pragma unroll

@@ -47,6 +47,7 @@ template <class S, int N1, int TILE, bool INV>
 __global__ __launch_bounds__(TILE * S::T, S::WPE) void k_tile_columns(const c32* x, c32* y,
                                                                      const c32* tw, int64_t rows) {
   static_assert(S::TPB == 1 && N1 % 16 == 0 && 16 % TILE == 0, "tile shape");
+  static_assert(!paired_lanes<S>::value, "tiled stages use the plain lane order");
   constexpr int L = N1;
   constexpr int64_t N = (int64_t)N1 * S::N;
   constexpr int tiles = N1 / TILE;
@@ -84,6 +85,7 @@ __global__ __launch_bounds__(TILE * S::T, S::WPE) void k_tile_rows(const c32* y,
   constexpr int tiles = N2 / TILE;
   constexpr int SL = half_log2(N);
   static_assert(N2 % 16 == 0 && 16 % TILE == 0, "tile shape");
+  static_assert(!paired_lanes<S>::value, "tiled stages use the plain lane order");
   static_assert(S::C == 1, "the closing transpose holds whole transforms in LDS");
   __shared__ alignas(16) c32 lds[TILE * tile_stride<S>()];
   const int64_t g = tile_of_block<TILE>(blockIdx.x);

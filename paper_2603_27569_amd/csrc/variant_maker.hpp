@@ -20,12 +20,15 @@ SingleVariant make_variant(const char* name) {
   v.double_buffered = double_buffered<S>::value;
   v.twiddle_schedule = S::PF;
   v.paired_twiddles = paired_twiddles<S>::value;
+  v.paired_lanes = paired_lanes<S>::value;
   v.threads = S::THREADS;
   v.lds_bytes = S::TPB * S::LDS_ELEMS * (int)sizeof(c32);
   v.tw_elems = S::TW_ELEMS;
   v.launch = &launch_single<S>;
-  v.fused = &launch_spectral_energy<S>;
-  v.filter = &launch_matched_filter<S>;
+  if constexpr (round_trip_layout<S>()) {
+    v.fused = &launch_spectral_energy<S>;
+    v.filter = &launch_matched_filter<S>;
+  }
   v.launch_f16 = &launch_single_io<S, IoF16>;
   v.launch_bf16 = &launch_single_io<S, IoBF16>;
   return v;

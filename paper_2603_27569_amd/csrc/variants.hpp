@@ -47,6 +47,7 @@ struct SingleVariant {
   bool double_buffered;  // exchanges alternate between two LDS buffers
   int twiddle_schedule;  // 0 at their pass, 1 one pass ahead, 2 all with the input
   bool paired_twiddles;  // table layout: two twiddles per 16-byte entry (PairedTwiddles)
+  bool paired_lanes;     // first/last pass in the paired butterfly order (PairedLanes)
   int threads;
   int lds_bytes;
   int tw_elems;

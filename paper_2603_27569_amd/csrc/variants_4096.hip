@@ -4,6 +4,7 @@
 #include "variant_maker.hpp"
 
 using stockfft::DoubleBuffered;
+using stockfft::PairedLanes;
 using stockfft::PairedTwiddles;
 using stockfft::Shape;
 using stockfft::ShapeX;
@@ -31,7 +32,12 @@ STOCKFFT_VARIANT_GROUP(variants_4096,
   make_variant<PairedTwiddles<Shape<4096, 16, 1, -1, 16, 16, 16>>>("n4096_e16_b1_px_r16.16.16_pt"),
   make_variant<PairedTwiddles<Shape<4096, 16, 1, 5, 16, 16, 16>>>("n4096_e16_b1_p5_r16.16.16_pt"),
   make_variant<PairedTwiddles<Shape<4096, 32, 1, 4, 16, 16, 16>>>("n4096_e32_b1_p4_r16.16.16_pt"),
+  // Paired lanes: 16-byte (FP32) and 8-byte (16-bit) row accesses.  They
+  // tie the 4- and 8-byte forms here and lost at the other lengths measured
+  // (lane-strided accesses once a lane owns more than two butterflies).
+  make_variant<PairedLanes<PairedTwiddles<Shape<4096, 32, 1, 4, 16, 16, 16>>>>("n4096_e32_b1_p4_r16.16.16_pt_pl"),
   make_variant<PairedTwiddles<ShapeX<2, false, 4, 4096, 32, 1, 4, 16, 16, 16>>>("n4096_e32_c2_b1_p4_r16.16.16_pt"),
+  make_variant<PairedLanes<PairedTwiddles<ShapeX<2, false, 4, 4096, 32, 1, 4, 16, 16, 16>>>>("n4096_e32_c2_b1_p4_r16.16.16_pt_pl"),
   make_variant<Shape<4096, 32, 1, 4, 16, 16, 16>>("n4096_e32_b1_p4_r16.16.16"),
   make_variant<Shape<4096, 32, 2, 4, 16, 16, 16>>("n4096_e32_b2_p4_r16.16.16"),
   // Two-round exchanges: half the LDS (17 KiB), so occupancy is set by the

@@ -132,12 +132,12 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham_timeline(const 
   const int64_t row = blockIdx.x;
   c32 a[S::E];
   c32 w[S::TW_REGS];
-  global_load_row<S>(a, in + row * S::N, t, true);
+  buffer_load_row<S>(a, Buf(in + row * S::N), 0, t);
   preload_twiddles<S>(w, tw, t);  // in flight with the input, as in the plain kernel
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   pr.read(1);
   run_passes_preloaded<S, INV, TimelineProbe>(a, w, lds, tw, t, &pr);
-  global_store_row<S>(a, out + row * S::N, t, true);
+  buffer_store_row<S>(a, Buf(out + row * S::N), 0, t, true);
   pr.read(2 * S::P + 1);
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   pr.read(2 * S::P + 2);
@@ -174,6 +174,8 @@ hipError_t launch_timeline(const void* in, void* out, const void* tw, int64_t ba
 // The shapes of the N = 4096 variants of the library with one transform
 // per workgroup (names as fft_variant_describe gives them).
 const TimelineVariant kTimeline[] = {
+    {"n4096_e8_b1_p4_r8.8.8.8_pt", 4096, 512,
+     &launch_timeline<PairedTwiddles<Shape<4096, 8, 1, 4, 8, 8, 8, 8>>>},
     {"n4096_e16_b1_px_r16.16.16_db_pt_tall", 4096, 256,
      &launch_timeline<DoubleBuffered<PairedTwiddles<ShapeX<1, 2, 1, 4096, 16, 1, -1, 16, 16, 16>>>>},
     {"n4096_e16_b1_px_r16.16.16_db_pt", 4096, 256,

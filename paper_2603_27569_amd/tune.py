@@ -5,8 +5,8 @@ variant -- values per lane (hence the radix and lanes per transform),
 transforms per workgroup, LDS padding, and for N >= 8192 the four-step
 splits (for N > 16384 the only kind) -- through the C ABI, and keeps the
 fastest.  The two fused kernels (the matched filter, and the forward ->
-weight -> adjoint kernel with its loss total) are tuned the same way, each on
-its own.  For the ragged persistent kernel
+weight -> adjoint kernel with its loss total) and the transform with 16-bit
+storage are tuned the same way, each on its own.  For the ragged persistent kernel
 it picks one compiled shape per length by coordinate descent on a mixed
 ragged batch.  The result is a JSON file that
 ``fft_tune_load`` (or the STOCKFFT_TUNE_CACHE environment variable) applies:
@@ -14,7 +14,8 @@ ragged batch.  The result is a JSON file that
   {"arch": "gfx950", "cus": 256, "hip_runtime": ..., "entries": [
      {"n": 4096, "batch_min": 129, "batch_max": 1024,
       "variant": "n4096_e16_b1_p4_r16.16.16", "us": ..., "candidates": {...}}],
-   "filter_entries": [...], "fused_entries": [...],   (same form)
+   "filter_entries": [...], "fused_entries": [...],
+   "storage16_entries": [...],                          (same form)
    "ragged": [{"n": 4096, "shape": "ragged_n4096_e16", "batch_us": ...}]}
 
 Timing: back-to-back launches over a ring of independent buffers larger
@@ -36,8 +37,8 @@ import math
 import statistics
 import sys
 
-from . import (FFT_ALGO_FOUR_STEP, FFT_ALGO_SINGLE_PASS, FFT_FORWARD, Plan, RaggedPlan,
-               fft_exec_matched_filter, fft_exec_spectral_energy, fft_ragged_shapes,
+from . import (FFT_ALGO_FOUR_STEP, FFT_ALGO_SINGLE_PASS, FFT_FORWARD, FFT_IO_C16, Plan, RaggedPlan,
+               fft_exec_io, fft_exec_matched_filter, fft_exec_spectral_energy, fft_ragged_shapes,
                fft_tune_clear_ragged, fft_tune_set_ragged, variants)
 
 SIZES = (256, 512, 1024, 2048, 4096, 8192, 16384)
@@ -108,6 +109,12 @@ def _pick(times, retime):
     return min(times, key=times.get)
 
 
+def fused_candidates(n):
+    """Single-pass variants of length n that have the two fused kernels."""
+    return [v["name"] for v in variants()
+            if v["n"] == n and v["kind"] == "single" and v["fused_kernels"]]
+
+
 def candidates(n):
     out = []
     for v in variants():
@@ -162,7 +169,7 @@ def tune_filter(torch, dev, stream, sizes=SIZES, buckets=BUCKETS, iters=30, log=
             k = len(xs)
             times = {}
             cs = stream.cuda_stream
-            names = [nm for nm, algo in candidates(n) if algo == FFT_ALGO_SINGLE_PASS]
+            names = fused_candidates(n)
 
             def timed(name, factor=1):
                 p = Plan(n, b, FFT_FORWARD, FFT_ALGO_SINGLE_PASS, name)
@@ -199,7 +206,7 @@ def tune_fused(torch, dev, stream, sizes=SIZES, buckets=BUCKETS, iters=30, log=p
             rows = torch.empty(b, dtype=torch.float32, device=dev)
             times = {}
             cs = stream.cuda_stream
-            names = [nm for nm, algo in candidates(n) if algo == FFT_ALGO_SINGLE_PASS]
+            names = fused_candidates(n)
 
             def timed(name, factor=1):
                 p = Plan(n, b, FFT_FORWARD, FFT_ALGO_SINGLE_PASS, name)
@@ -215,6 +222,43 @@ def tune_fused(torch, dev, stream, sizes=SIZES, buckets=BUCKETS, iters=30, log=p
                 times[name] = timed(name)
             best = _pick(times, lambda name: timed(name, FINAL_FACTOR))
             log(f"tune fused n={n} batch={b} -> {best} {times[best]:.2f} us")
+            entries.append({"n": n, "batch_min": bmin, "batch_max": bmax, "variant": best,
+                            "timed_batch": b, "us": round(times[best], 3),
+                            "candidates": {k2: round(v, 3) for k2, v in times.items()}})
+            del xs, ys
+    return entries
+
+
+def tune_storage16(torch, dev, stream, sizes=SIZES, buckets=BUCKETS, iters=30, log=print):
+    """The transform with binary16 storage (fft_exec_io, FFT_IO_C16) per
+    length and batch bucket, over every single-pass variant.  The bfloat16
+    format runs the same kernels with another conversion, so it shares the
+    choice.  Half the bytes move, so the best shape can differ from FP32's."""
+    entries = []
+    for n in sizes:
+        for bmin, bmax, b in buckets:
+            while n * b * 4 > MAX_BYTES and b > 1:
+                b //= 2
+            k = max(2, math.ceil(RING_BYTES / (2 * n * b * 4)))
+            xs = [torch.randn(b, n, 2, device=dev).to(torch.float16) for _ in range(k)]
+            ys = [torch.empty_like(xs[0]) for _ in range(k)]
+            times = {}
+            cs = stream.cuda_stream
+            names = [nm for nm, algo in candidates(n) if algo == FFT_ALGO_SINGLE_PASS]
+
+            def timed(name, factor=1):
+                p = Plan(n, b, FFT_FORWARD, FFT_ALGO_SINGLE_PASS, name)
+                t = _time(torch, stream,
+                          lambda i: fft_exec_io(p.handle, xs[i % k].data_ptr(), ys[i % k].data_ptr(),
+                                                FFT_IO_C16, cs),
+                          iters * factor)
+                p.close()
+                return t
+
+            for name in names:
+                times[name] = timed(name)
+            best = _pick(times, lambda name: timed(name, FINAL_FACTOR))
+            log(f"tune storage16 n={n} batch={b} -> {best} {times[best]:.2f} us")
             entries.append({"n": n, "batch_min": bmin, "batch_max": bmax, "variant": best,
                             "timed_batch": b, "us": round(times[best], 3),
                             "candidates": {k2: round(v, 3) for k2, v in times.items()}})
@@ -285,11 +329,14 @@ def run(out_path, quick=False, log=print):
                          iters=10 if quick else 30, log=log)
     filters = tune_filter(torch, dev, stream, buckets=buckets, iters=10 if quick else 30, log=log)
     fused = tune_fused(torch, dev, stream, buckets=buckets, iters=10 if quick else 30, log=log)
+    storage16 = tune_storage16(torch, dev, stream, buckets=buckets, iters=10 if quick else 30,
+                               log=log)
     ragged = tune_ragged(torch, dev, stream, iters=5 if quick else 20, sweeps=1 if quick else 2,
                          log=log)
     doc = {"arch": props.gcnArchName.split(":")[0], "cus": props.multi_processor_count,
            "hip_runtime": getattr(torch.version, "hip", None), "entries": entries,
-           "filter_entries": filters, "fused_entries": fused, "ragged": ragged}
+           "filter_entries": filters, "fused_entries": fused, "storage16_entries": storage16,
+           "ragged": ragged}
     with open(out_path, "w") as f:
         json.dump(doc, f, indent=1)
     return doc

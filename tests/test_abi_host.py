@@ -21,7 +21,7 @@ GOLDEN = os.path.join(ROOT, "tests", "golden", "paper_tables.json")
 def _declared():
     text = open(HEADER).read()
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(fft_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(fft_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -34,7 +34,7 @@ def test_library_exports_every_declared_symbol():
     assert sorted(_lib.SIGNATURES) == names
     out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
                          text=True).stdout
-    exported = set(re.findall(r" T (fft_[a-z_]+)$", out, flags=re.M))
+    exported = set(re.findall(r" T (fft_[a-z0-9_]+)$", out, flags=re.M))
     assert set(names) <= exported
 
 
@@ -145,6 +145,10 @@ def test_builtin_table_is_the_shipped_tuner_output():
     for e in doc["fused_entries"]:
         for b in (e["batch_min"], e["timed_batch"], min(e["batch_max"], 10 ** 9)):
             assert sf.fft_tune_query_fused(e["n"], b) == e["variant"], (e["n"], b)
+    assert doc.get("storage16_entries")
+    for e in doc["storage16_entries"]:
+        for b in (e["batch_min"], e["timed_batch"], min(e["batch_max"], 10 ** 9)):
+            assert sf.fft_tune_query_storage16(e["n"], b) == e["variant"], (e["n"], b)
 
 
 def test_shipped_table_buckets_tile_every_batch():
@@ -154,7 +158,7 @@ def test_shipped_table_buckets_tile_every_batch():
     from paper_2603_27569_amd import tune
     doc = json.load(open(os.path.join(ROOT, "paper_2603_27569_amd", "tune_gfx950.json")))
     lows = [b[0] for b in tune.BUCKETS]
-    for key in ("entries", "filter_entries", "fused_entries"):
+    for key in ("entries", "filter_entries", "fused_entries", "storage16_entries"):
         by_n = {}
         for e in doc[key]:
             by_n.setdefault(e["n"], []).append(e)
@@ -377,9 +381,16 @@ def test_tune_table_set_query_load(tmp_path):
             {"n": 1024, "batch_min": 1, "batch_max": 10, "variant": "n2048_e8_b1_p4_r8.8.8.4"}],
             "fused_entries": [
             {"n": 512, "batch_min": 1, "batch_max": 10 ** 9, "variant": "n512_e4_b2_p4_r4.4.4.4.2"},
-            {"n": 512, "batch_min": 1, "batch_max": 10, "variant": "bogus"}]}))
+            {"n": 512, "batch_min": 1, "batch_max": 10, "variant": "bogus"}],
+            "storage16_entries": [
+            {"n": 512, "batch_min": 1, "batch_max": 10 ** 9, "variant": "n512_e16_b2_p4_r16.16.2"},
+            {"n": 512, "batch_min": 1, "batch_max": 10, "variant": "n1024_e4_b1_p4_r4.4.4.4.4"}]}))
         sf.fft_tune_load(str(p))
         assert sf.fft_tune_query_fused(512, 5) == "n512_e4_b2_p4_r4.4.4.4.2"
+        # the entry naming another length's variant is skipped
+        assert sf.fft_tune_query_storage16(512, 5) == "n512_e16_b2_p4_r16.16.2"
+        with pytest.raises(sf.StockfftError):
+            sf.fft_tune_query_storage16(32768, 5)
         with pytest.raises(sf.StockfftError):
             sf.fft_tune_query_fused(32768, 5)
         assert sf.fft_tune_query(2048, 5) == "n2048_e8_b1_p4_r8.8.8.4"
@@ -405,6 +416,7 @@ def test_tune_file_malformed_documents_and_fields(tmp_path):
     sf.fft_tune_clear()
     try:
         base = sf.fft_tune_query(2048, 5)
+        base16 = sf.fft_tune_query_storage16(2048, 5)
         bad = tmp_path / "bad.json"
         docs = [
             '{"entries": [{"n": 2048, "batch_min": NaN, "variant": "x"}]}',  # not JSON
@@ -442,9 +454,11 @@ def test_tune_file_malformed_documents_and_fields(tmp_path):
         p = tmp_path / "skip.json"
         p.write_text(json.dumps({"arch": "gfx950:sramecc+:xnack-", "cus": 256, "entries": entries,
                                  "filter_entries": entries, "fused_entries": entries,
+                                 "storage16_entries": entries,
                                  "ragged": [{"n": 2048.5, "shape": "ragged_n2048_e16"}]}))
         sf.fft_tune_load(str(p))  # loads, every entry skipped
         assert sf.fft_tune_query(2048, 5) == base
+        assert sf.fft_tune_query_storage16(2048, 5) == base16
         # a huge batch_max saturates (the tuner's unbounded bucket is 2^62)
         p.write_text(json.dumps({"entries": [
             {"n": 2048, "batch_min": 1, "batch_max": 1e19, "variant": good}]}))

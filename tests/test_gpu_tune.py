@@ -51,9 +51,49 @@ def test_fused_tuner_restricted_search():
                               iters=3, log=lambda *a: None)
     assert [e["n"] for e in entries] == [1024]
     e = entries[0]
-    names = {v["name"] for v in sf.variants() if v["kind"] == "single" and v["n"] == 1024}
+    names = {v["name"] for v in sf.variants()
+             if v["kind"] == "single" and v["n"] == 1024 and v["fused_kernels"]}
     assert set(e["candidates"]) == names
     assert e["variant"] in names and e["us"] == min(e["candidates"].values())
+
+
+def test_storage16_tuner_restricted_search_and_plan_choice(tmp_path):
+    dev = torch.device("cuda:0")
+    s = torch.cuda.Stream()
+    entries = tune.tune_storage16(torch, dev, s, sizes=(2048,), buckets=((1, 2 ** 62, 64),),
+                                  iters=3, log=lambda *a: None)
+    assert [e["n"] for e in entries] == [2048]
+    e = entries[0]
+    names = {v["name"] for v in sf.variants() if v["kind"] == "single" and v["n"] == 2048}
+    assert set(e["candidates"]) == names
+    assert e["variant"] in names and e["us"] == min(e["candidates"].values())
+    # A plan made without a variant runs the 16-bit transform with the
+    # 16-bit table's choice, which need not be the FP32 one.
+    other = next(nm for nm in sorted(names) if nm != sf.fft_tune_query(2048, 64))
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"arch": "gfx950", "storage16_entries": [
+        {"n": 2048, "batch_min": 1, "batch_max": 2 ** 62, "variant": other}]}))
+    sf.fft_tune_clear()
+    try:
+        sf.fft_tune_load(str(path))
+        assert sf.fft_tune_query_storage16(2048, 64) == other
+        for direction in (sf.FFT_FORWARD, sf.FFT_BACKWARD):
+            p = sf.Plan(2048, 64, direction)
+            d = p.describe()
+            assert d["storage16_variant"] == other and d["variant"]["name"] != other
+            x = workloads.complex_normal((64, 2048), seed=5)
+            stored, xv = workloads.to_storage(x, "f16")
+            xin = torch.from_numpy(np.ascontiguousarray(stored)).to(dev)
+            y = torch.empty_like(xin)
+            sf.fft_exec_io(p.handle, xin.data_ptr(), y.data_ptr(), sf.FFT_IO_C16, 0)
+            torch.cuda.synchronize()
+            yh = y.cpu().numpy().astype(np.float64)
+            ref = oracle.fft(xv, inverse=direction == sf.FFT_BACKWARD)
+            ok, worst, _, _ = metrics.gate_storage(yh[..., 0] + 1j * yh[..., 1], ref, xv, "f16")
+            assert ok, worst
+            p.close()
+    finally:
+        sf.fft_tune_clear()
 
 
 def test_ragged_shape_tuner():
