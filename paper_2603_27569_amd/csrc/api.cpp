@@ -37,6 +37,26 @@ namespace {
 std::atomic<int64_t> g_max_groups{kDefaultMaxGroupsPerLaunch};
 }
 int64_t max_groups_per_launch() { return g_max_groups.load(std::memory_order_relaxed); }
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::atomic<int> g_cus[kMaxDevices];  // 0 = not queried yet
+}  // namespace
+
+int device_cus() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 1;
+  if (dev < kMaxDevices) {
+    const int c = g_cus[dev].load(std::memory_order_relaxed);
+    if (c > 0) return c;
+  }
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      cus < 1)
+    cus = 1;
+  if (dev < kMaxDevices) g_cus[dev].store(cus, std::memory_order_relaxed);
+  return cus;
+}
 void set_max_groups_per_launch(int64_t g) { g_max_groups.store(g, std::memory_order_relaxed); }
 
 int hip_fail(hipError_t e) {
@@ -178,37 +198,37 @@ struct BuiltinEntry {
   const char* name;
 };
 const BuiltinEntry kBuiltin[] = {
-    {256, 1, 64, "n256_e16_b16_p4_r16.16"},
-    {256, 65, 384, "n256_e16_b16_p4_r16.16"},
-    {256, 385, 768, "n256_e8_b8_p4_r8.8.4_pt"},
-    {256, 769, 1536, "n256_e16_b16_p4_r16.16_pt"},
-    {256, 1537, 4096, "n256_e16_b4_p4_r16.16_pt"},
+    {256, 1, 64, "n256_e16_b4_p4_r16.16_pt"},
+    {256, 65, 384, "n256_e16_b4_p4_r16.16_pt"},
+    {256, 385, 768, "n256_e16_b16_p4_r16.16_pt"},
+    {256, 769, 1536, "n256_e4_b4_p4_r4.4.4.4_pt"},
+    {256, 1537, 4096, "n256_e4_b4_p4_r4.4.4.4_pt"},
     {256, 4097, INT64_MAX, "n256_e8_b8_p4_r8.8.4_pt"},
-    {512, 1, 64, "n512_e16_b2_p4_r16.16.2"},
-    {512, 65, 384, "n512_e16_b8_p4_r16.16.2"},
+    {512, 1, 64, "n512_e16_b2_p4_r16.16.2_pt"},
+    {512, 65, 384, "n512_e16_b2_p4_r16.16.2"},
     {512, 385, 768, "n512_e16_b2_p4_r16.16.2_pt"},
-    {512, 769, 1536, "n512_e8_b4_p4_r8.8.8"},
+    {512, 769, 1536, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
     {512, 1537, 4096, "n512_e8_b4_p4_r8.8.8_pt"},
     {512, 4097, INT64_MAX, "n512_e8_b4_p4_r8.8.8_pt"},
-    {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
+    {1024, 1, 64, "n1024_e16_b1_p4_r16.16.4"},
     {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
-    {1024, 385, 768, "n1024_e8_b2_p4_r8.8.8.2"},
+    {1024, 385, 768, "n1024_e16_b1_p4_r16.16.4_pt"},
     {1024, 769, 1536, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
     {1024, 1537, 4096, "n1024_e16_b1_p4_r16.16.4_pt"},
-    {1024, 4097, INT64_MAX, "n1024_e16_b4_p4_r16.16.4_pt"},
-    {2048, 1, 64, "n2048_e16_b1_p4_r16.16.8"},
+    {1024, 4097, INT64_MAX, "n1024_e8_b2_p4_r8.8.8.2_pt"},
+    {2048, 1, 64, "n2048_e8_b1_p4_r8.8.8.4_pt"},
     {2048, 65, 384, "n2048_e8_b1_p4_r8.8.8.4_pt"},
     {2048, 385, 768, "n2048_e8_b1_p4_r8.8.8.4_pt"},
     {2048, 769, 1536, "n2048_e16_b1_p4_r16.16.8_pt"},
     {2048, 1537, 4096, "n2048_e32_c2_b1_p4_r16.16.8_pt"},
     {2048, 4097, INT64_MAX, "n2048_e16_b2_p4_r16.16.8_pt"},
-    {4096, 1, 64, "n4096_e16_b1_px_r16.16.16_db_pt"},
+    {4096, 1, 64, "n4096_e16_b1_px_r16.16.16_db_pt_tall"},
     {4096, 65, 384, "n4096_e8_b1_p4_r8.8.8.8_pt"},
-    {4096, 385, 768, "n4096_e8_b1_p4_r8.8.8.8_pt"},
+    {4096, 385, 768, "n4096_e16_b1_px_r16.16.16_pt"},
     {4096, 769, 1536, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
     {4096, 1537, 4096, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
-    {4096, 4097, INT64_MAX, "n4096_e32_b1_p4_r16.16.16_pt_pl"},
-    {8192, 1, 64, "n8192_e16_b1_p4_r16.16.16.2_pt"},
+    {4096, 4097, INT64_MAX, "n4096_e8_b1_p4_r8.8.8.8_pt_tall_st1d3"},
+    {8192, 1, 64, "fs8192_4x2048"},
     {8192, 65, 384, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
     {8192, 385, 768, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
     {8192, 769, 1536, "n8192_e32_c4_b1_p4_r8.8.8.16"},
@@ -262,19 +282,19 @@ const BuiltinEntry kBuiltin[] = {
 // "filter_entries" of the package's tune_gfx950.json).
 const BuiltinEntry kBuiltinFilter[] = {
     {256, 1, 64, "n256_e16_b4_p4_r16.16"},
-    {256, 65, 384, "n256_e4_b4_p4_r4.4.4.4_pt"},
-    {256, 385, 768, "n256_e8_b8_p4_r8.8.4"},
-    {256, 769, 1536, "n256_e8_b8_p4_r8.8.4_pt"},
-    {256, 1537, 4096, "n256_e4_b4_p4_r4.4.4.4_pt"},
+    {256, 65, 384, "n256_e4_b4_p4_r4.4.4.4"},
+    {256, 385, 768, "n256_e4_b4_p4_r4.4.4.4"},
+    {256, 769, 1536, "n256_e16_b4_p4_r16.16_pt"},
+    {256, 1537, 4096, "n256_e8_b8_p4_r8.8.4_pt"},
     {256, 4097, INT64_MAX, "n256_e16_b4_p4_r16.16_pt"},
     {512, 1, 64, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
-    {512, 65, 384, "n512_e8_b4_p4_r8.8.8_pt"},
-    {512, 385, 768, "n512_e8_b4_p4_r8.8.8_pt"},
+    {512, 65, 384, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
+    {512, 385, 768, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
     {512, 769, 1536, "n512_e8_b4_p4_r8.8.8_pt"},
     {512, 1537, 4096, "n512_e8_b4_p4_r8.8.8_pt"},
     {512, 4097, INT64_MAX, "n512_e8_b4_p4_r8.8.8_pt"},
-    {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
-    {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4"},
+    {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4"},
+    {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
     {1024, 385, 768, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
     {1024, 769, 1536, "n1024_e8_b2_p4_r8.8.8.2_pt"},
     {1024, 1537, 4096, "n1024_e16_b1_p4_r16.16.4_pt"},
@@ -289,12 +309,12 @@ const BuiltinEntry kBuiltinFilter[] = {
     {4096, 65, 384, "n4096_e8_b1_p4_r8.8.8.8_pt"},
     {4096, 385, 768, "n4096_e16_b1_p5_r16.16.16_pt"},
     {4096, 769, 1536, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
-    {4096, 1537, 4096, "n4096_e32_c2_b1_p4_r16.16.16_pt_pl"},
+    {4096, 1537, 4096, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
     {4096, 4097, INT64_MAX, "n4096_e32_b1_p4_r16.16.16_pt_pl"},
     {8192, 1, 64, "n8192_e16_b1_p4_r16.16.16.2_pt"},
     {8192, 65, 384, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
     {8192, 385, 768, "n8192_e32_b1_p4_r16.16.16.2_pt"},
-    {8192, 769, 1536, "n8192_e32_c4_b1_p4_r8.8.8.16"},
+    {8192, 769, 1536, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
     {8192, 1537, 4096, "n8192_e32_c4_b1_p4_r8.8.8.16"},
     {8192, 4097, INT64_MAX, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
     {16384, 1, 64, "n16384_e16_b1_p4_r16.16.16.4_pt"},
@@ -310,41 +330,41 @@ const BuiltinEntry kBuiltinFilter[] = {
 // move, so the balance between memory and arithmetic, and with it the best
 // shape, differs from the FP32 transform's.
 const BuiltinEntry kBuiltinStorage16[] = {
-    {256, 1, 64, "n256_e16_b4_p4_r16.16"},
-    {256, 65, 384, "n256_e16_b16_p4_r16.16_pt"},
-    {256, 385, 768, "n256_e16_b16_p4_r16.16"},
-    {256, 769, 1536, "n256_e4_b4_p4_r4.4.4.4_pt"},
+    {256, 1, 64, "n256_e16_b16_p4_r16.16"},
+    {256, 65, 384, "n256_e8_b8_p4_r8.8.4"},
+    {256, 385, 768, "n256_e16_b4_p4_r16.16_pt"},
+    {256, 769, 1536, "n256_e16_b16_p4_r16.16"},
     {256, 1537, 4096, "n256_e16_b4_p4_r16.16"},
-    {256, 4097, INT64_MAX, "n256_e16_b4_p4_r16.16_pt"},
-    {512, 1, 64, "n512_e16_b8_p4_r16.16.2"},
-    {512, 65, 384, "n512_e16_b2_p4_r16.16.2_pt"},
-    {512, 385, 768, "n512_e16_b2_p4_r16.16.2_pt"},
-    {512, 769, 1536, "n512_e8_b4_p4_r8.8.8"},
-    {512, 1537, 4096, "n512_e8_b4_p4_r8.8.8"},
+    {256, 4097, INT64_MAX, "n256_e8_b8_p4_r8.8.4_pt"},
+    {512, 1, 64, "n512_e16_b2_p4_r16.16.2"},
+    {512, 65, 384, "n512_e4_b2_p4_r4.4.4.4.2"},
+    {512, 385, 768, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
+    {512, 769, 1536, "n512_e16_b2_p4_r16.16.2"},
+    {512, 1537, 4096, "n512_e8_b4_p4_r8.8.8_pt"},
     {512, 4097, INT64_MAX, "n512_e8_b4_p4_r8.8.8_pt"},
-    {1024, 1, 64, "n1024_e8_b2_p4_r8.8.8.2"},
-    {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
-    {1024, 385, 768, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
-    {1024, 769, 1536, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
+    {1024, 1, 64, "n1024_e8_b2_p4_r8.8.8.2_pt"},
+    {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4"},
+    {1024, 385, 768, "n1024_e16_b1_p4_r16.16.4_pt"},
+    {1024, 769, 1536, "n1024_e8_b2_p4_r8.8.8.2_pt"},
     {1024, 1537, 4096, "n1024_e16_b1_p4_r16.16.4_pt"},
-    {1024, 4097, INT64_MAX, "n1024_e16_b1_p4_r16.16.4_pt"},
-    {2048, 1, 64, "n2048_e4_b1_p4_r4.4.4.4.4.2"},
-    {2048, 65, 384, "n2048_e16_b1_p4_r16.16.8"},
+    {1024, 4097, INT64_MAX, "n1024_e16_b4_p4_r16.16.4_pt"},
+    {2048, 1, 64, "n2048_e16_b1_p4_r16.16.8_pt"},
+    {2048, 65, 384, "n2048_e16_b1_p4_r16.16.8_pt"},
     {2048, 385, 768, "n2048_e8_b1_p4_r8.8.8.4_pt"},
     {2048, 769, 1536, "n2048_e16_b1_p4_r16.16.8_pt"},
     {2048, 1537, 4096, "n2048_e16_b2_p4_r16.16.8_pt"},
     {2048, 4097, INT64_MAX, "n2048_e32_c2_b1_p4_r16.16.8_pt"},
-    {4096, 1, 64, "n4096_e8_b1_p4_r8.8.8.8_pt"},
+    {4096, 1, 64, "n4096_e16_b1_px_r16.16.16_db_pt"},
     {4096, 65, 384, "n4096_e8_b1_p4_r8.8.8.8_pt_tall"},
-    {4096, 385, 768, "n4096_e16_b1_px_r16.16.16_pt"},
-    {4096, 769, 1536, "n4096_e32_b1_p4_r16.16.16_pt_pl"},
-    {4096, 1537, 4096, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
-    {4096, 4097, INT64_MAX, "n4096_e16_b1_p5_r16.16.16_pt"},
+    {4096, 385, 768, "n4096_e16_b1_p5_r16.16.16_pt"},
+    {4096, 769, 1536, "n4096_e32_b1_p4_r16.16.16_pt"},
+    {4096, 1537, 4096, "n4096_e32_c2_b1_p4_r16.16.16_pt_pl"},
+    {4096, 4097, INT64_MAX, "n4096_e16_b1_px_r16.16.16_db_pt_tall_st2d2"},
     {8192, 1, 64, "n8192_e16_b1_p4_r16.16.16.2_pt"},
     {8192, 65, 384, "n8192_e16_b1_p4_r16.16.16.2_pt"},
     {8192, 385, 768, "n8192_e16_b1_p4_r16.16.16.2_pt"},
     {8192, 769, 1536, "n8192_e32_c2_b1_p4_r16.16.16.2"},
-    {8192, 1537, 4096, "n8192_e32_c4_b1_p4_r8.8.8.16"},
+    {8192, 1537, 4096, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
     {8192, 4097, INT64_MAX, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
     {16384, 1, 64, "n16384_e16_b1_p4_r16.16.16.4_pt"},
     {16384, 65, 384, "n16384_e32_b1_p4_r16.16.16.4_pt"},
@@ -358,19 +378,19 @@ const BuiltinEntry kBuiltinStorage16[] = {
 // on MI355X (the "fused_entries" of the package's tune_gfx950.json).
 const BuiltinEntry kBuiltinFused[] = {
     {256, 1, 64, "n256_e4_b4_p4_r4.4.4.4_pt"},
-    {256, 65, 384, "n256_e4_b4_p4_r4.4.4.4"},
-    {256, 385, 768, "n256_e4_b4_p4_r4.4.4.4_pt"},
+    {256, 65, 384, "n256_e4_b4_p4_r4.4.4.4_pt"},
+    {256, 385, 768, "n256_e4_b4_p4_r4.4.4.4"},
     {256, 769, 1536, "n256_e4_b4_p4_r4.4.4.4_pt"},
-    {256, 1537, 4096, "n256_e8_b8_p4_r8.8.4"},
+    {256, 1537, 4096, "n256_e8_b8_p4_r8.8.4_pt"},
     {256, 4097, INT64_MAX, "n256_e16_b16_p4_r16.16_pt"},
-    {512, 1, 64, "n512_e8_b4_p4_r8.8.8_pt"},
-    {512, 65, 384, "n512_e8_b4_p4_r8.8.8_pt"},
+    {512, 1, 64, "n512_e4_b2_p4_r4.4.4.4.2"},
+    {512, 65, 384, "n512_e4_b2_p4_r4.4.4.4.2"},
     {512, 385, 768, "n512_e8_b4_p4_r8.8.8"},
     {512, 769, 1536, "n512_e8_b4_p4_r8.8.8"},
     {512, 1537, 4096, "n512_e8_b4_p4_r8.8.8_pt"},
     {512, 4097, INT64_MAX, "n512_e8_b4_p4_r8.8.8_pt"},
     {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
-    {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4"},
+    {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
     {1024, 385, 768, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
     {1024, 769, 1536, "n1024_e8_b2_p4_r8.8.8.2_pt"},
     {1024, 1537, 4096, "n1024_e8_b2_p4_r8.8.8.2_pt"},
@@ -383,11 +403,11 @@ const BuiltinEntry kBuiltinFused[] = {
     {2048, 4097, INT64_MAX, "n2048_e16_b2_p4_r16.16.8_pt"},
     {4096, 1, 64, "n4096_e8_b1_p4_r8.8.8.8_pt"},
     {4096, 65, 384, "n4096_e8_b1_p4_r8.8.8.8_pt"},
-    {4096, 385, 768, "n4096_e16_b1_px_r16.16.16_db_pt"},
+    {4096, 385, 768, "n4096_e16_b1_p5_r16.16.16_pt"},
     {4096, 769, 1536, "n4096_e16_b1_px_r16.16.16_pt"},
     {4096, 1537, 4096, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
     {4096, 4097, INT64_MAX, "n4096_e16_b1_p5_r16.16.16_pt"},
-    {8192, 1, 64, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
+    {8192, 1, 64, "n8192_e16_b1_p4_r16.16.16.2_pt"},
     {8192, 65, 384, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
     {8192, 385, 768, "n8192_e16_b1_p4_r16.16.16.2_pt"},
     {8192, 769, 1536, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
@@ -1126,13 +1146,13 @@ static std::string describe_single(const SingleVariant& v) {
                 "\"passes\":%d,\"radices\":%s,\"exchange_rounds\":%d,\"threads\":%d,"
                 "\"lds_bytes\":%d,\"twiddle_entries\":%d,\"barriers\":%d,"
                 "\"double_buffered\":%s,\"twiddle_schedule\":%d,\"paired_twiddles\":%s,\"paired_lanes\":%s,"
-                "\"fused_kernels\":%s}",
+                "\"fused_kernels\":%s,\"streamed\":%d}",
                 v.name, v.n, v.e, v.t, v.tpb, v.padlog,
                 v.padlog > 0 ? "pad" : v.padlog < 0 ? "xor" : "none", v.npass, radices_json(v).c_str(),
                 v.chunks, v.threads, v.lds_bytes, v.tw_elems, barriers_of(v),
                 v.double_buffered ? "true" : "false", v.twiddle_schedule,
                 v.paired_twiddles ? "true" : "false", v.paired_lanes ? "true" : "false",
-                v.fused && v.filter ? "true" : "false");
+                v.fused && v.filter ? "true" : "false", v.streamed);
   return buf;
 }
 

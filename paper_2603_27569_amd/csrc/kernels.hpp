@@ -270,6 +270,123 @@ hipError_t launch_single_io(const void* in, void* out, const void* tw, int64_t b
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------ streaming
+// Persistent form of the single-pass transform for large batches.  With one
+// short-lived workgroup per row, every workgroup of a launch first waits for
+// its whole row, then computes, then stores, so a batch that fills the chip
+// once runs its loads, its arithmetic and its stores one after the other.
+// Here G = k x CUs workgroups loop over the rows (row = blockIdx.x + i G):
+// each loads its twiddles once and keeps them in registers, and issues the
+// next row's loads before the current row's passes, so one row's loads
+// overlap the previous row's arithmetic and its stores the next row's.
+// The vector-memory counter lets the row's stores stay in flight while the
+// next loop waits for the prefetched row, and the exchange barriers wait
+// only for LDS traffic.
+
+struct IoF32 {  // complex64 storage, for the streaming form's FP32 launch
+  __device__ __forceinline__ static c32 load(u32x2 v) {
+    return c32{__uint_as_float(v.x), __uint_as_float(v.y)};
+  }
+  __device__ __forceinline__ static u32x2 store(c32 a) {
+    return u32x2{__float_as_uint(a.x), __float_as_uint(a.y)};
+  }
+};
+template <class IO>
+using io_raw = std::conditional_t<std::is_same_v<IO, IoF32>, u32x2, uint32_t>;
+
+template <class Base, int WPC, int DEPTH = 1>
+struct Streamed : Base {
+  static_assert(Base::TPB == 1 && Base::PF == 2, "streamed shapes hold every twiddle in registers");
+  static_assert(!paired_lanes<Base>::value, "streamed shapes use the t + m T order");
+  static constexpr int STREAM_WPC = WPC;
+  static constexpr int STREAM_DEPTH = DEPTH;
+  // Waves per SIMD that WPC resident workgroups need (the register budget).
+  static constexpr int WPE = WPC * Base::THREADS / 256 > 1 ? WPC * Base::THREADS / 256 : 1;
+};
+template <class S, class = void>
+struct streamed : std::integral_constant<int, 0> {};
+template <class S>
+struct streamed<S, std::void_t<decltype(S::STREAM_WPC)>> : std::integral_constant<int, S::STREAM_WPC> {};
+
+// One row of raw values: slot m at t + m T.
+template <class S, class IO>
+__device__ __forceinline__ void stream_load(io_raw<IO> (&r)[S::E], const Buf& b, int t) {
+  constexpr int B = (int)sizeof(io_raw<IO>);
+#pragma unroll
+  for (int m = 0; m < S::E; ++m) {
+    if constexpr (B == 8)
+      r[m] = b.ld64<kNT>(B * t, B * m * S::T);
+    else
+      r[m] = b.ld32<kNT>(B * t, B * m * S::T);
+  }
+}
+
+template <class S, bool INV, class IO>
+__global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham_stream(const void* in, void* out,
+                                                                 const c32* tw, int64_t rows,
+                                                                 int64_t stride) {
+  using R = io_raw<IO>;
+  constexpr int B = (int)sizeof(R);
+  constexpr int D = S::STREAM_DEPTH;  // rows in flight ahead of the one computed
+  constexpr int NB = D + 1;           // register buffers, used round-robin
+  static_assert(D * S::E + S::E <= 63, "in-flight accesses exceed the wave's memory counter");
+  __shared__ alignas(16) c32 lds[S::LDS_ELEMS];
+  const int t = threadIdx.x;
+  const char* src = static_cast<const char*>(in);
+  char* dst = static_cast<char*>(out);
+  R buf[NB][S::E];
+  int64_t row = blockIdx.x;  // the grid never exceeds rows
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+    if (row + j * stride < rows) stream_load<S, IO>(buf[j], Buf(src + (row + j * stride) * (S::N * B)), t);
+  c32 w[S::TW_REGS];
+  preload_twiddles<S>(w, tw, t);
+  // Wait for the twiddles here (the rows loaded before them are then in too):
+  // otherwise the loop's wait counts must allow for their loads still being
+  // in flight, and in later rows they would wait for the prefetches.
+#pragma unroll
+  for (int i = 0; i < S::TW_REGS; ++i) asm volatile("" ::"v"(w[i].x), "v"(w[i].y));
+  for (;;) {
+    // Unrolled NB times, so every buffer index is a constant and no loaded
+    // register is copied (a copy would wait for its load).
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+      const int64_t r = row + s * stride;
+      if (r >= rows) return;  // uniform
+      const int64_t ahead = r + D * stride;
+      // buffer (s + D) mod NB held the row computed in the previous step
+      if (ahead < rows) stream_load<S, IO>(buf[(s + D) % NB], Buf(src + ahead * (S::N * B)), t);
+      c32 a[S::E];
+#pragma unroll
+      for (int m = 0; m < S::E; ++m) a[m] = IO::load(buf[s][m]);
+      run_passes_preloaded<S, INV>(a, w, lds, tw, t);
+      const Buf o(dst + r * (S::N * B));
+#pragma unroll
+      for (int m = 0; m < S::E; ++m) {
+        if constexpr (B == 8)
+          o.st64<kNT>(IO::store(a[m]), B * t, B * m * S::T);
+        else
+          o.st32<kNT>(IO::store(a[m]), B * t, B * m * S::T);
+      }
+      __syncthreads();  // this row's last exchange reads are done before the next row's writes
+    }
+    row += NB * stride;
+  }
+}
+
+template <class S, class IO>
+hipError_t launch_stream(const void* in, void* out, const void* tw, int64_t batch, bool inverse,
+                         hipStream_t s) {
+  int64_t g = (int64_t)device_cus() * streamed<S>::value;
+  if (g > batch) g = batch;
+  const c32* twp = static_cast<const c32*>(tw);
+  if (inverse)
+    k_stockham_stream<S, true, IO><<<dim3((unsigned)g), dim3(S::THREADS), 0, s>>>(in, out, twp, batch, g);
+  else
+    k_stockham_stream<S, false, IO><<<dim3((unsigned)g), dim3(S::THREADS), 0, s>>>(in, out, twp, batch, g);
+  return hipGetLastError();
+}
+
 // Sum v over the lanes of one wave that own the same transform (all 64 lanes
 // when a transform spans several waves).  Every one of those lanes returns
 // the wave's sum; a transform wider than a wave adds its waves' sums

@@ -5,7 +5,7 @@
 // 68 KiB exchange tile each) work through a list of tasks; a task is as many
 // transforms of one length as the workgroup holds under the shape chosen for
 // that length (values per lane, exchange rounds, radix order; picked by the
-// autotuner): 16384 or 8192 elements, so tasks cost about the same.  The plan
+// autotuner): 4096 to 16384 elements, costed by their measured durations.  The plan
 // deals the tasks out on the host with Graham's longest-processing-time list
 // schedule, costing each task by its shape's measured duration, and stores
 // every workgroup's tasks contiguously, longest length first, with the start
@@ -39,10 +39,12 @@ constexpr int kClasses = 7;  // lengths 256 << c, c = 0..6
 
 // Two candidate shapes per length, all 512 lanes, at most 128 VGPRs (two
 // workgroups per CU) and at most an 8192-element (+ pad) exchange tile.
-// A: 32 values per lane, two-round exchanges, 16384 elements per task.
+// A: 32 values per lane, two-round exchanges, 16384 elements per task (for
+// 256: 8 values per lane, radix 8 8 4, 4096 elements per task -- 64 tasks of
+// 8 lanes at 32 values needed more than 128 VGPRs and spilled).
 // B: 16 values per lane, whole-tile exchanges, 8192 elements per task (for
 // 16384, B is the radix-16 order of the A shape).
-using A256 = ShapeX<2, false, 4, 256, 32, 64, 4, 16, 16>;
+using A256 = ShapeX<1, false, 4, 256, 8, 16, 4, 8, 8, 4>;
 using A512 = ShapeX<2, false, 4, 512, 32, 32, 4, 16, 16, 2>;
 using A1024 = ShapeX<2, false, 4, 1024, 32, 16, 4, 16, 16, 4>;
 using A2048 = ShapeX<2, false, 4, 2048, 32, 8, 4, 16, 16, 8>;
@@ -74,7 +76,7 @@ constexpr ShapeInfo info(const char* name) {
 }
 
 const ShapeInfo kShapes[kNumShapes] = {
-    info<A256>("ragged_n256_e32c2"),       info<B256>("ragged_n256_e16"),
+    info<A256>("ragged_n256_e8"),          info<B256>("ragged_n256_e16"),
     info<A512>("ragged_n512_e32c2"),       info<B512>("ragged_n512_e16"),
     info<A1024>("ragged_n1024_e32c2"),     info<B1024>("ragged_n1024_e16"),
     info<A2048>("ragged_n2048_e32c2"),     info<B2048>("ragged_n2048_e16"),
@@ -88,7 +90,7 @@ const ShapeInfo kShapes[kNumShapes] = {
 // CU, every CU busy), kernel time x 512 / 4096.  The list schedule uses them
 // as task costs; only their ratios matter to it.
 constexpr float kShapeTaskUs[kNumShapes] = {
-    29.22f, 13.76f,  // 256
+    7.38f, 13.76f,   // 256
     29.60f, 14.43f,  // 512
     29.07f, 14.09f,  // 1024
     28.39f, 14.41f,  // 2048
@@ -191,7 +193,7 @@ int shape_index(const char* name) {
 
 // Built-in per-length shape: the autotuner's choice on MI355X (the package's
 // tune_gfx950.json).
-constexpr int kBuiltinShape[kClasses] = {1, 2, 4, 6, 8, 11, 13};
+constexpr int kBuiltinShape[kClasses] = {0, 2, 4, 6, 8, 11, 13};
 int builtin_shape(int64_t n) { return kBuiltinShape[ilog2(n) - 8]; }
 
 std::mutex g_rtune_mu;

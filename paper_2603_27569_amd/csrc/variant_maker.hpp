@@ -21,16 +21,25 @@ SingleVariant make_variant(const char* name) {
   v.twiddle_schedule = S::PF;
   v.paired_twiddles = paired_twiddles<S>::value;
   v.paired_lanes = paired_lanes<S>::value;
+  v.streamed = streamed<S>::value;
   v.threads = S::THREADS;
   v.lds_bytes = S::TPB * S::LDS_ELEMS * (int)sizeof(c32);
   v.tw_elems = S::TW_ELEMS;
-  v.launch = &launch_single<S>;
-  if constexpr (round_trip_layout<S>()) {
-    v.fused = &launch_spectral_energy<S>;
-    v.filter = &launch_matched_filter<S>;
+  if constexpr (streamed<S>::value > 0) {
+    // Persistent shapes run the plain transform only (either storage).
+    v.launch = &launch_stream<S, IoF32>;
+    v.launch_f16 = &launch_stream<S, IoF16>;
+    v.launch_bf16 = &launch_stream<S, IoBF16>;
+    return v;
+  } else {
+    v.launch = &launch_single<S>;
+    if constexpr (round_trip_layout<S>()) {
+      v.fused = &launch_spectral_energy<S>;
+      v.filter = &launch_matched_filter<S>;
+    }
+    v.launch_f16 = &launch_single_io<S, IoF16>;
+    v.launch_bf16 = &launch_single_io<S, IoBF16>;
   }
-  v.launch_f16 = &launch_single_io<S, IoF16>;
-  v.launch_bf16 = &launch_single_io<S, IoBF16>;
   return v;
 }
 

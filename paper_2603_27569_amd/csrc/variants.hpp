@@ -21,6 +21,8 @@ constexpr int64_t kMaxSinglePassN = 16384;
 constexpr int64_t kMaxN = int64_t(1) << 20;
 int64_t max_groups_per_launch();
 void set_max_groups_per_launch(int64_t groups);
+// Compute units of the current device (cached per device).
+int device_cus();
 
 using LaunchFn = hipError_t (*)(const void* in, void* out, const void* tw, int64_t batch,
                                 bool inverse, hipStream_t s);
@@ -48,6 +50,7 @@ struct SingleVariant {
   int twiddle_schedule;  // 0 at their pass, 1 one pass ahead, 2 all with the input
   bool paired_twiddles;  // table layout: two twiddles per 16-byte entry (PairedTwiddles)
   bool paired_lanes;     // first/last pass in the paired butterfly order (PairedLanes)
+  int streamed;          // 0: a workgroup per transform; k: k persistent workgroups per CU (Streamed)
   int threads;
   int lds_bytes;
   int tw_elems;

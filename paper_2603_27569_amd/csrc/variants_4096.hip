@@ -8,6 +8,7 @@ using stockfft::PairedLanes;
 using stockfft::PairedTwiddles;
 using stockfft::Shape;
 using stockfft::ShapeX;
+using stockfft::Streamed;
 using stockfft::make_variant;
 
 STOCKFFT_VARIANT_GROUP(variants_4096,
@@ -42,4 +43,16 @@ STOCKFFT_VARIANT_GROUP(variants_4096,
   make_variant<Shape<4096, 32, 2, 4, 16, 16, 16>>("n4096_e32_b2_p4_r16.16.16"),
   // Two-round exchanges: half the LDS (17 KiB), so occupancy is set by the
   // registers (at most 128: four waves per SIMD) rather than by the LDS.
-  make_variant<ShapeX<2, false, 4, 4096, 32, 1, 4, 16, 16, 16>>("n4096_e32_c2_b1_p4_r16.16.16"))
+  make_variant<ShapeX<2, false, 4, 4096, 32, 1, 4, 16, 16, 16>>("n4096_e32_c2_b1_p4_r16.16.16"),
+  // Persistent streaming forms (k workgroups per CU loop over the rows, the
+  // next row's loads in flight during the current row's passes), for
+  // batches of several rows per CU.
+  // Names end in _st<workgroups per CU>d<rows in flight ahead>.
+  make_variant<Streamed<DoubleBuffered<PairedTwiddles<ShapeX<1, 2, 1, 4096, 16, 1, -1, 16, 16, 16>>>, 2, 1>>(
+      "n4096_e16_b1_px_r16.16.16_db_pt_tall_st2d1"),
+  make_variant<Streamed<DoubleBuffered<PairedTwiddles<ShapeX<1, 2, 1, 4096, 16, 1, -1, 16, 16, 16>>>, 2, 2>>(
+      "n4096_e16_b1_px_r16.16.16_db_pt_tall_st2d2"),
+  make_variant<Streamed<PairedTwiddles<ShapeX<1, 2, 1, 4096, 8, 1, 4, 8, 8, 8, 8>>, 1, 3>>(
+      "n4096_e8_b1_p4_r8.8.8.8_pt_tall_st1d3"),
+  make_variant<Streamed<PairedTwiddles<ShapeX<1, 2, 1, 4096, 8, 1, 4, 8, 8, 8, 8>>, 2, 2>>(
+      "n4096_e8_b1_p4_r8.8.8.8_pt_tall_st2d2"))

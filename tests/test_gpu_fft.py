@@ -50,6 +50,29 @@ def test_single_pass_variant_parity(v, inverse):
     assert worst < 2e-6  # a healthy FP32 Stockham sits near 1e-7
 
 
+STREAMED = [v for v in SINGLE if v["streamed"]]
+
+
+@pytest.mark.parametrize("v", STREAMED, ids=[v["name"] for v in STREAMED])
+@pytest.mark.parametrize("inverse", [False, True], ids=["fwd", "bwd"])
+def test_streamed_variant_many_rows_per_workgroup(v, inverse):
+    """A persistent shape's workgroups loop over the rows (row = id + i G with
+    G = streamed x CUs): two full rounds and a ragged third, out of place and
+    in place (a row is read before it is written, and the prefetched row is
+    another one)."""
+    n = v["n"]
+    g = torch.cuda.get_device_properties(0).multi_processor_count * v["streamed"]
+    batch = 2 * g + 37
+    x = workloads.plain_uniform(n, batch, seed=n + batch + 11)
+    ref = oracle.fft(x, inverse=inverse)
+    y = sf.fft(_gpu(x), inverse=inverse, algorithm=sf.FFT_ALGO_SINGLE_PASS, variant=v["name"])
+    assert _check(_host(y), x, inverse, ref=ref) < 2e-6
+    xt = _gpu(x)
+    sf.fft(xt, inverse=inverse, out=xt, algorithm=sf.FFT_ALGO_SINGLE_PASS, variant=v["name"])
+    assert _check(_host(xt), x, inverse, ref=ref) < 2e-6
+    assert not v["fused_kernels"]
+
+
 @pytest.mark.parametrize("v", FOUR, ids=[v["name"] for v in FOUR])
 @pytest.mark.parametrize("inverse", [False, True], ids=["fwd", "bwd"])
 def test_four_step_variant_parity(v, inverse):

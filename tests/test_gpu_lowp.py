@@ -52,6 +52,33 @@ def test_every_variant_with_16bit_storage(v, fmt):
         assert ok, (inverse, worst, ab)
 
 
+STREAMED = [v for v in SINGLE if v["streamed"]]
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
+@pytest.mark.parametrize("v", STREAMED, ids=[v["name"] for v in STREAMED])
+def test_streamed_16bit_many_rows_per_workgroup(v, fmt):
+    """16-bit storage through a persistent shape: several rows per
+    workgroup, a ragged last round, both directions."""
+    n = v["n"]
+    g = torch.cuda.get_device_properties(0).multi_processor_count * v["streamed"]
+    batch = 2 * g + 21
+    x = workloads.plain_normal(n, batch, seed=n + 91)
+    stored, xv = workloads.to_storage(x, fmt)
+    for inverse in (False, True):
+        p = sf.Plan(n, batch, sf.FFT_BACKWARD if inverse else sf.FFT_FORWARD,
+                    sf.FFT_ALGO_SINGLE_PASS, v["name"])
+        xt = _device(stored, fmt)
+        yt = torch.empty_like(xt)
+        sf.fft_exec_io(p.handle, xt.data_ptr(), yt.data_ptr(),
+                       sf.FFT_IO_C16 if fmt == "f16" else sf.FFT_IO_BC16,
+                       torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+        p.close()
+        ok, worst, _, ab = metrics.gate_storage(_host(yt, fmt), oracle.fft(xv, inverse=inverse), xv, fmt)
+        assert ok, (inverse, worst, ab)
+
+
 @pytest.mark.parametrize("fmt", ["f16", "bf16"])
 def test_lowp_auto_plan_in_place_and_repeatable(fmt):
     n, b = 4096, 64
