@@ -198,33 +198,33 @@ struct BuiltinEntry {
   const char* name;
 };
 const BuiltinEntry kBuiltin[] = {
-    {256, 1, 64, "n256_e16_b4_p4_r16.16_pt"},
+    {256, 1, 64, "n256_e16_b4_p4_r16.16"},
     {256, 65, 384, "n256_e16_b4_p4_r16.16_pt"},
-    {256, 385, 768, "n256_e16_b16_p4_r16.16_pt"},
+    {256, 385, 768, "n256_e8_b8_p4_r8.8.4"},
     {256, 769, 1536, "n256_e4_b4_p4_r4.4.4.4_pt"},
-    {256, 1537, 4096, "n256_e4_b4_p4_r4.4.4.4_pt"},
+    {256, 1537, 4096, "n256_e8_b8_p4_r8.8.4"},
     {256, 4097, INT64_MAX, "n256_e8_b8_p4_r8.8.4_pt"},
-    {512, 1, 64, "n512_e16_b2_p4_r16.16.2_pt"},
+    {512, 1, 64, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
     {512, 65, 384, "n512_e16_b2_p4_r16.16.2"},
-    {512, 385, 768, "n512_e16_b2_p4_r16.16.2_pt"},
-    {512, 769, 1536, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
+    {512, 385, 768, "n512_e8_b4_p4_r8.8.8_pt"},
+    {512, 769, 1536, "n512_e16_b2_p4_r16.16.2_pt"},
     {512, 1537, 4096, "n512_e8_b4_p4_r8.8.8_pt"},
     {512, 4097, INT64_MAX, "n512_e8_b4_p4_r8.8.8_pt"},
-    {1024, 1, 64, "n1024_e16_b1_p4_r16.16.4"},
-    {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
-    {1024, 385, 768, "n1024_e16_b1_p4_r16.16.4_pt"},
+    {1024, 1, 64, "n1024_e8_b2_p4_r8.8.8.2"},
+    {1024, 65, 384, "n1024_e16_b1_p4_r16.16.4_pt"},
+    {1024, 385, 768, "n1024_e16_b1_p4_r16.16.4"},
     {1024, 769, 1536, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
     {1024, 1537, 4096, "n1024_e16_b1_p4_r16.16.4_pt"},
-    {1024, 4097, INT64_MAX, "n1024_e8_b2_p4_r8.8.8.2_pt"},
+    {1024, 4097, INT64_MAX, "n1024_e16_b4_p4_r16.16.4_pt"},
     {2048, 1, 64, "n2048_e8_b1_p4_r8.8.8.4_pt"},
-    {2048, 65, 384, "n2048_e8_b1_p4_r8.8.8.4_pt"},
+    {2048, 65, 384, "n2048_e8_b1_p4_r8.8.8.4"},
     {2048, 385, 768, "n2048_e8_b1_p4_r8.8.8.4_pt"},
     {2048, 769, 1536, "n2048_e16_b1_p4_r16.16.8_pt"},
     {2048, 1537, 4096, "n2048_e32_c2_b1_p4_r16.16.8_pt"},
     {2048, 4097, INT64_MAX, "n2048_e16_b2_p4_r16.16.8_pt"},
-    {4096, 1, 64, "n4096_e16_b1_px_r16.16.16_db_pt_tall"},
+    {4096, 1, 64, "n4096_e16_b1_p5_r16.16.16_pt"},
     {4096, 65, 384, "n4096_e8_b1_p4_r8.8.8.8_pt"},
-    {4096, 385, 768, "n4096_e16_b1_px_r16.16.16_pt"},
+    {4096, 385, 768, "n4096_e8_b1_p4_r8.8.8.8_pt"},
     {4096, 769, 1536, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
     {4096, 1537, 4096, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
     {4096, 4097, INT64_MAX, "n4096_e8_b1_p4_r8.8.8.8_pt_tall_st1d3"},
@@ -282,19 +282,19 @@ const BuiltinEntry kBuiltin[] = {
 // "filter_entries" of the package's tune_gfx950.json).
 const BuiltinEntry kBuiltinFilter[] = {
     {256, 1, 64, "n256_e16_b4_p4_r16.16"},
-    {256, 65, 384, "n256_e4_b4_p4_r4.4.4.4"},
-    {256, 385, 768, "n256_e4_b4_p4_r4.4.4.4"},
-    {256, 769, 1536, "n256_e16_b4_p4_r16.16_pt"},
-    {256, 1537, 4096, "n256_e8_b8_p4_r8.8.4_pt"},
+    {256, 65, 384, "n256_e16_b4_p4_r16.16_pt"},
+    {256, 385, 768, "n256_e16_b4_p4_r16.16_pt"},
+    {256, 769, 1536, "n256_e4_b4_p4_r4.4.4.4_pt"},
+    {256, 1537, 4096, "n256_e4_b4_p4_r4.4.4.4_pt"},
     {256, 4097, INT64_MAX, "n256_e16_b4_p4_r16.16_pt"},
     {512, 1, 64, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
     {512, 65, 384, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
-    {512, 385, 768, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
+    {512, 385, 768, "n512_e4_b2_p4_r4.4.4.4.2"},
     {512, 769, 1536, "n512_e8_b4_p4_r8.8.8_pt"},
     {512, 1537, 4096, "n512_e8_b4_p4_r8.8.8_pt"},
     {512, 4097, INT64_MAX, "n512_e8_b4_p4_r8.8.8_pt"},
-    {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4"},
-    {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
+    {1024, 1, 64, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
+    {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4"},
     {1024, 385, 768, "n1024_e4_b1_p4_r4.4.4.4.4_pt"},
     {1024, 769, 1536, "n1024_e8_b2_p4_r8.8.8.2_pt"},
     {1024, 1537, 4096, "n1024_e16_b1_p4_r16.16.4_pt"},
@@ -309,13 +309,13 @@ const BuiltinEntry kBuiltinFilter[] = {
     {4096, 65, 384, "n4096_e8_b1_p4_r8.8.8.8_pt"},
     {4096, 385, 768, "n4096_e16_b1_p5_r16.16.16_pt"},
     {4096, 769, 1536, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
-    {4096, 1537, 4096, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
+    {4096, 1537, 4096, "n4096_e32_c2_b1_p4_r16.16.16_pt_pl"},
     {4096, 4097, INT64_MAX, "n4096_e32_b1_p4_r16.16.16_pt_pl"},
     {8192, 1, 64, "n8192_e16_b1_p4_r16.16.16.2_pt"},
     {8192, 65, 384, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
     {8192, 385, 768, "n8192_e32_b1_p4_r16.16.16.2_pt"},
-    {8192, 769, 1536, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
-    {8192, 1537, 4096, "n8192_e32_c4_b1_p4_r8.8.8.16"},
+    {8192, 769, 1536, "n8192_e32_c4_b1_p4_r8.8.8.16"},
+    {8192, 1537, 4096, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
     {8192, 4097, INT64_MAX, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
     {16384, 1, 64, "n16384_e16_b1_p4_r16.16.16.4_pt"},
     {16384, 65, 384, "n16384_e16_b1_p4_r16.16.16.4_pt"},
@@ -330,41 +330,41 @@ const BuiltinEntry kBuiltinFilter[] = {
 // move, so the balance between memory and arithmetic, and with it the best
 // shape, differs from the FP32 transform's.
 const BuiltinEntry kBuiltinStorage16[] = {
-    {256, 1, 64, "n256_e16_b16_p4_r16.16"},
+    {256, 1, 64, "n256_e16_b4_p4_r16.16"},
     {256, 65, 384, "n256_e8_b8_p4_r8.8.4"},
-    {256, 385, 768, "n256_e16_b4_p4_r16.16_pt"},
-    {256, 769, 1536, "n256_e16_b16_p4_r16.16"},
-    {256, 1537, 4096, "n256_e16_b4_p4_r16.16"},
+    {256, 385, 768, "n256_e16_b4_p4_r16.16"},
+    {256, 769, 1536, "n256_e16_b4_p4_r16.16_pt"},
+    {256, 1537, 4096, "n256_e8_b8_p4_r8.8.4_pt"},
     {256, 4097, INT64_MAX, "n256_e8_b8_p4_r8.8.4_pt"},
-    {512, 1, 64, "n512_e16_b2_p4_r16.16.2"},
-    {512, 65, 384, "n512_e4_b2_p4_r4.4.4.4.2"},
-    {512, 385, 768, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
-    {512, 769, 1536, "n512_e16_b2_p4_r16.16.2"},
-    {512, 1537, 4096, "n512_e8_b4_p4_r8.8.8_pt"},
+    {512, 1, 64, "n512_e4_b2_p4_r4.4.4.4.2_pt"},
+    {512, 65, 384, "n512_e16_b2_p4_r16.16.2"},
+    {512, 385, 768, "n512_e16_b2_p4_r16.16.2"},
+    {512, 769, 1536, "n512_e8_b4_p4_r8.8.8_pt"},
+    {512, 1537, 4096, "n512_e8_b4_p4_r8.8.8"},
     {512, 4097, INT64_MAX, "n512_e8_b4_p4_r8.8.8_pt"},
     {1024, 1, 64, "n1024_e8_b2_p4_r8.8.8.2_pt"},
-    {1024, 65, 384, "n1024_e4_b1_p4_r4.4.4.4.4"},
-    {1024, 385, 768, "n1024_e16_b1_p4_r16.16.4_pt"},
-    {1024, 769, 1536, "n1024_e8_b2_p4_r8.8.8.2_pt"},
+    {1024, 65, 384, "n1024_e16_b4_p4_r16.16.4"},
+    {1024, 385, 768, "n1024_e8_b2_p4_r8.8.8.2"},
+    {1024, 769, 1536, "n1024_e16_b1_p4_r16.16.4_pt"},
     {1024, 1537, 4096, "n1024_e16_b1_p4_r16.16.4_pt"},
-    {1024, 4097, INT64_MAX, "n1024_e16_b4_p4_r16.16.4_pt"},
-    {2048, 1, 64, "n2048_e16_b1_p4_r16.16.8_pt"},
-    {2048, 65, 384, "n2048_e16_b1_p4_r16.16.8_pt"},
-    {2048, 385, 768, "n2048_e8_b1_p4_r8.8.8.4_pt"},
+    {1024, 4097, INT64_MAX, "n1024_e16_b1_p4_r16.16.4_pt"},
+    {2048, 1, 64, "n2048_e8_b1_p4_r8.8.8.4_pt"},
+    {2048, 65, 384, "n2048_e16_b1_p4_r16.16.8"},
+    {2048, 385, 768, "n2048_e8_b1_p4_r8.8.8.4"},
     {2048, 769, 1536, "n2048_e16_b1_p4_r16.16.8_pt"},
     {2048, 1537, 4096, "n2048_e16_b2_p4_r16.16.8_pt"},
     {2048, 4097, INT64_MAX, "n2048_e32_c2_b1_p4_r16.16.8_pt"},
-    {4096, 1, 64, "n4096_e16_b1_px_r16.16.16_db_pt"},
+    {4096, 1, 64, "n4096_e8_b1_p4_r8.8.8.8"},
     {4096, 65, 384, "n4096_e8_b1_p4_r8.8.8.8_pt_tall"},
-    {4096, 385, 768, "n4096_e16_b1_p5_r16.16.16_pt"},
+    {4096, 385, 768, "n4096_e8_b1_px_r8.8.8.8_pt"},
     {4096, 769, 1536, "n4096_e32_b1_p4_r16.16.16_pt"},
     {4096, 1537, 4096, "n4096_e32_c2_b1_p4_r16.16.16_pt_pl"},
-    {4096, 4097, INT64_MAX, "n4096_e16_b1_px_r16.16.16_db_pt_tall_st2d2"},
+    {4096, 4097, INT64_MAX, "n4096_e16_b1_px_r16.16.16_db_pt_tall_st2d1"},
     {8192, 1, 64, "n8192_e16_b1_p4_r16.16.16.2_pt"},
     {8192, 65, 384, "n8192_e16_b1_p4_r16.16.16.2_pt"},
     {8192, 385, 768, "n8192_e16_b1_p4_r16.16.16.2_pt"},
-    {8192, 769, 1536, "n8192_e32_c2_b1_p4_r16.16.16.2"},
-    {8192, 1537, 4096, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
+    {8192, 769, 1536, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
+    {8192, 1537, 4096, "n8192_e16_b1_p4_r16.16.16.2_pt"},
     {8192, 4097, INT64_MAX, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},
     {16384, 1, 64, "n16384_e16_b1_p4_r16.16.16.4_pt"},
     {16384, 65, 384, "n16384_e32_b1_p4_r16.16.16.4_pt"},
@@ -379,11 +379,11 @@ const BuiltinEntry kBuiltinStorage16[] = {
 const BuiltinEntry kBuiltinFused[] = {
     {256, 1, 64, "n256_e4_b4_p4_r4.4.4.4_pt"},
     {256, 65, 384, "n256_e4_b4_p4_r4.4.4.4_pt"},
-    {256, 385, 768, "n256_e4_b4_p4_r4.4.4.4"},
+    {256, 385, 768, "n256_e4_b4_p4_r4.4.4.4_pt"},
     {256, 769, 1536, "n256_e4_b4_p4_r4.4.4.4_pt"},
     {256, 1537, 4096, "n256_e8_b8_p4_r8.8.4_pt"},
     {256, 4097, INT64_MAX, "n256_e16_b16_p4_r16.16_pt"},
-    {512, 1, 64, "n512_e4_b2_p4_r4.4.4.4.2"},
+    {512, 1, 64, "n512_e8_b4_p4_r8.8.8"},
     {512, 65, 384, "n512_e4_b2_p4_r4.4.4.4.2"},
     {512, 385, 768, "n512_e8_b4_p4_r8.8.8"},
     {512, 769, 1536, "n512_e8_b4_p4_r8.8.8"},
@@ -398,16 +398,16 @@ const BuiltinEntry kBuiltinFused[] = {
     {2048, 1, 64, "n2048_e8_b1_p4_r8.8.8.4_pt"},
     {2048, 65, 384, "n2048_e8_b1_p4_r8.8.8.4_pt"},
     {2048, 385, 768, "n2048_e8_b1_p4_r8.8.8.4_pt"},
-    {2048, 769, 1536, "n2048_e16_b2_p4_r16.16.8_pt"},
+    {2048, 769, 1536, "n2048_e8_b1_p4_r8.8.8.4_pt"},
     {2048, 1537, 4096, "n2048_e16_b2_p4_r16.16.8_pt"},
     {2048, 4097, INT64_MAX, "n2048_e16_b2_p4_r16.16.8_pt"},
-    {4096, 1, 64, "n4096_e8_b1_p4_r8.8.8.8_pt"},
-    {4096, 65, 384, "n4096_e8_b1_p4_r8.8.8.8_pt"},
+    {4096, 1, 64, "n4096_e8_b1_px_r8.8.8.8_pt"},
+    {4096, 65, 384, "n4096_e8_b1_px_r8.8.8.8_pt"},
     {4096, 385, 768, "n4096_e16_b1_p5_r16.16.16_pt"},
     {4096, 769, 1536, "n4096_e16_b1_px_r16.16.16_pt"},
     {4096, 1537, 4096, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
     {4096, 4097, INT64_MAX, "n4096_e16_b1_p5_r16.16.16_pt"},
-    {8192, 1, 64, "n8192_e16_b1_p4_r16.16.16.2_pt"},
+    {8192, 1, 64, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
     {8192, 65, 384, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
     {8192, 385, 768, "n8192_e16_b1_p4_r16.16.16.2_pt"},
     {8192, 769, 1536, "n8192_e32_c2_b1_p4_r16.16.16.2_pt"},

@@ -193,7 +193,7 @@ int shape_index(const char* name) {
 
 // Built-in per-length shape: the autotuner's choice on MI355X (the package's
 // tune_gfx950.json).
-constexpr int kBuiltinShape[kClasses] = {0, 2, 4, 6, 8, 11, 13};
+constexpr int kBuiltinShape[kClasses] = {1, 2, 4, 6, 8, 11, 13};
 int builtin_shape(int64_t n) { return kBuiltinShape[ilog2(n) - 8]; }
 
 std::mutex g_rtune_mu;
