@@ -246,6 +246,21 @@ def main():
                       max(20, args.steps // 10), 5)
     refs["copy_wide_256MiB"] = {"us": round(t_big * 1e6, 3), "GBs": round(2 * big / t_big / 1e9, 1)}
     del bsrc, bdst
+    # The LDS roof of the exchange (the secondary roof): 32 KiB written and
+    # read back per round per workgroup, barrier after each half, 256 lanes.
+    # One workgroup per CU (the headline's occupancy) gives the time of one
+    # exchange; four per CU give the LDS's aggregate rate.
+    rounds = 256
+    lds = {}
+    for per_cu in (1, 4):
+        g = 256 * per_cu
+        lout = torch.empty(g * 256, dtype=torch.float32, device=dev)
+        t_l = median_of(T, lambda i: ref.lds_exchange(g, rounds, lout.data_ptr(), cs),
+                        max(10, args.steps // 50), 3)
+        lds[f"{per_cu}_per_cu"] = {"us_per_exchange": round(t_l / rounds * 1e6, 4),
+                                   "TBs_aggregate": round(g * rounds * 65536 / t_l / 1e12, 2)}
+        del lout
+    refs["lds_exchange_32KiB"] = lds
     # How close the transform comes to moving its bytes with no arithmetic in
     # the same launch shape.
     roofline["frac_of_same_size_copy"] = round(t_copy / t_kernel, 4)

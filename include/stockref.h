@@ -74,6 +74,20 @@ int ref_weight_energy(void *y, const float *w, float *row_loss, int64_t n, int64
 int ref_filter_multiply(void *y, const void *h, int64_t n, int64_t batch, void *stream);
 
 /*
+ * ref_lds_exchange -- the LDS roof of the transform's exchange: `groups`
+ * workgroups of 256 lanes (1 <= groups <= 2^31 - 1), each doing `rounds`
+ * (>= 0) exchanges of 32 KiB -- every lane writes 16 values of 8 bytes to
+ * LDS, a barrier, every lane reads 16 values another lane wrote, a barrier
+ * -- and nothing else.  Bank-conflict free.  Each round moves 64 KiB of LDS
+ * traffic per workgroup (32 KiB written, 32 KiB read).  out: device,
+ * groups * 256 float32 (4-byte aligned), caller-owned; out[g * 256 + t] =
+ * 16 ((t + rounds) mod 256) + 120, the sum of the real parts lane t holds at
+ * the end (lane t starts with t + m, m < 16, and every round passes each
+ * lane's values to lane t - 1).
+ */
+int ref_lds_exchange(int64_t groups, int rounds, float *out, void *stream);
+
+/*
  * ref_timeline -- run the single-pass transform of variant `variant` (one
  * of the names ref_timeline_variants lists) on `batch` rows, as fft_exec
  * would, with clock readings taken at the phase boundaries of every wave.

@@ -22,6 +22,7 @@ SIGNATURES = {
     "ref_empty": (_int, [_i64, _int, _vp]),
     "ref_copy_rows": (_int, [_vp, _vp, _i64, _i64, _int, _vp]),
     "ref_copy_wide": (_int, [_vp, _vp, _i64, _vp]),
+    "ref_lds_exchange": (_int, [_i64, ctypes.c_int, _vp, _vp]),
     "ref_weight_energy": (_int, [_vp, _vp, _vp, _i64, _i64, _vp]),
     "ref_filter_multiply": (_int, [_vp, _vp, _i64, _i64, _vp]),
     "ref_timeline": (_int, [ctypes.c_char_p, _vp, _vp, _vp, _i64, _int, _vp, _vp]),
@@ -68,6 +69,10 @@ def copy_rows(src, dst, n, batch, lanes, stream=0):
 
 def copy_wide(src, dst, nbytes, stream=0):
     _check("ref_copy_wide", lib().ref_copy_wide(_p(src), _p(dst), int(nbytes), _p(stream)))
+
+
+def lds_exchange(groups, rounds, out, stream=0):
+    _check("ref_lds_exchange", lib().ref_lds_exchange(int(groups), int(rounds), _p(out), _p(stream)))
 
 
 def weight_energy(y, w, row_loss, n, batch, stream=0):

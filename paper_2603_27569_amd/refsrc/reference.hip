@@ -87,6 +87,35 @@ __global__ __launch_bounds__(256) void k_weight_energy(c32* y, const float* __re
   if (t == 0) row_loss[blockIdx.x] = (part[0] + part[1]) + (part[2] + part[3]);
 }
 
+// The LDS exchange alone, in the radix-16 headline shape's size and access
+// width: 256 lanes, 16 values of 8 bytes each, so every round writes and reads
+// back 32 KiB per workgroup, with a barrier after the writes and one after the
+// reads and nothing else in between.  Lane t writes slot t + 256 m and reads
+// slot ((t + 1) mod 256) + 256 m: consecutive lanes on consecutive 8-byte
+// slots (no bank conflicts), and every value moves to another lane, so after
+// r rounds lane t holds lane ((t + r) mod 256)'s values.  out[g 256 + t] is
+// the sum of lane t's final values (the caller can check it).
+__global__ __launch_bounds__(256) void k_lds_exchange(int rounds, float* out) {
+  __shared__ alignas(16) c32 buf[16 * 256];
+  const int t = threadIdx.x;
+  c32 a[16];
+#pragma unroll
+  for (int m = 0; m < 16; ++m) a[m] = c32{(float)(t + m), (float)m};
+  const int u = (t + 1) & 255;
+  for (int r = 0; r < rounds; ++r) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) buf[t + 256 * m] = a[m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 16; ++m) a[m] = buf[u + 256 * m];
+    __syncthreads();
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int m = 0; m < 16; ++m) s += a[m].x;
+  out[(int64_t)blockIdx.x * 256 + t] = s;
+}
+
 // y <- conj(h) y / n over every element (n a power of two: 1/n is exact).
 __global__ __launch_bounds__(256) void k_filter_multiply(c32* y, const c32* __restrict__ h,
                                                          int logn, int64_t total) {
@@ -229,6 +258,14 @@ extern "C" int ref_copy_wide(const void* in, void* out, int64_t bytes, void* str
   if (groups > 0x7fffffff) return FFT_INVALID_ARGUMENT;
   k_copy_wide<<<dim3((unsigned)groups), dim3(256), 0, (hipStream_t)stream>>>(
       static_cast<const f32x4*>(in), static_cast<f32x4*>(out), count);
+  return launched();
+}
+
+extern "C" int ref_lds_exchange(int64_t groups, int rounds, float* out, void* stream) {
+  if (!out) return FFT_INVALID_POINTER;
+  if (groups < 1 || groups > 0x7fffffff || rounds < 0) return FFT_INVALID_ARGUMENT;
+  if ((uintptr_t)out & 3u) return FFT_MISALIGNED;
+  k_lds_exchange<<<dim3((unsigned)groups), dim3(256), 0, (hipStream_t)stream>>>(rounds, out);
   return launched();
 }
 

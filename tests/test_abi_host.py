@@ -504,6 +504,10 @@ def test_reference_calls_reject_bad_arguments_before_any_device_call():
     assert L.ref_copy_wide(vp(72), vp(1 << 30), 32, None) == codes["FFT_MISALIGNED"]
     assert L.ref_weight_energy(vp(64), vp(64), vp(64), 300, 1, None) == codes["FFT_INVALID_ARGUMENT"]
     assert L.ref_filter_multiply(vp(64), None, 256, 1, None) == codes["FFT_INVALID_POINTER"]
+    assert L.ref_lds_exchange(0, 1, vp(64), None) == codes["FFT_INVALID_ARGUMENT"]
+    assert L.ref_lds_exchange(1, -1, vp(64), None) == codes["FFT_INVALID_ARGUMENT"]
+    assert L.ref_lds_exchange(1, 1, None, None) == codes["FFT_INVALID_POINTER"]
+    assert L.ref_lds_exchange(1, 1, vp(66), None) == codes["FFT_MISALIGNED"]
     assert L.ref_timeline(b"nope", vp(64), vp(1 << 30), vp(64), 1, 0, vp(64), None) == \
         codes["FFT_INVALID_ARGUMENT"]
     assert L.ref_timeline(b"n4096_e16_b1_px_r16.16.16_db", vp(64), vp(1 << 30), vp(64), 1, 2,

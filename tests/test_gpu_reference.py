@@ -28,6 +28,16 @@ def test_copy_rows_exact(n, lanes, batch):
     assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("groups,rounds", [(1, 0), (3, 1), (256, 7), (40, 300)])
+def test_lds_exchange_moves_every_value(groups, rounds):
+    out = torch.full((groups * 256,), -1.0, dtype=torch.float32, device=DEV)
+    ref.lds_exchange(groups, rounds, out.data_ptr(), _cs())
+    torch.cuda.synchronize()
+    t = np.arange(256)
+    want = np.tile(16 * ((t + rounds) % 256) + 120, groups).astype(np.float32)
+    assert np.array_equal(out.cpu().numpy(), want)
+
+
 @pytest.mark.parametrize("nbytes", [16, 4096 * 16, 4096 * 16 * 3 + 48])
 def test_copy_wide_exact_and_bounded(nbytes):
     src = torch.randint(0, 255, (nbytes + 64,), dtype=torch.uint8, device=DEV)
