@@ -347,7 +347,7 @@ int fft_tune_query_storage16(int64_t n, int64_t batch, char *buf, int64_t cap);
 int fft_set_launch_limit(int64_t max_groups);
 
 /*
- * Introspection (host only; no device needed).
+ * Introspection (host only; the variant calls need no device).
  * fft_variant_count: number of compiled kernel variants.
  * fft_variant_describe: JSON text for variant `index` into buf (cap bytes,
  *   NUL-terminated); returns FFT_INVALID_ARGUMENT for a bad index or a
@@ -356,7 +356,12 @@ int fft_set_launch_limit(int64_t max_groups);
  *   for the device (interleaved re, im; forward direction), written into
  *   out[0 .. 2*count); *count receives the number of complex entries.
  *   With out == NULL only *count is set.
- * fft_plan_describe: JSON text describing a plan.
+ * fft_plan_describe: JSON text describing a plan: its variant, and for a
+ *   single-pass variant "variant_resources" (VGPRs, scratch bytes per lane,
+ *   static LDS bytes and the largest workgroup of its forward FP32 kernel,
+ *   as the HIP runtime reports them for the plan's device), the matched-
+ *   filter, fused and 16-bit storage shapes.  Errors: FFT_INVALID_PLAN, or
+ *   FFT_INVALID_ARGUMENT for a buffer that is too small.
  */
 int fft_variant_count(void);
 int fft_variant_describe(int index, char *buf, int64_t cap);

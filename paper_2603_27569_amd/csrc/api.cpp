@@ -1209,6 +1209,19 @@ extern "C" int fft_variant_twiddles(int index, float* out, int64_t cap_complex, 
   return FFT_SUCCESS;
 }
 
+// The compiled resources of a variant's forward FP32 kernel on the plan's
+// device: registers, scratch and static LDS per the HIP runtime.
+static std::string kernel_resources(const stockfft_plan_s* plan, const SingleVariant& v) {
+  if (!v.kernel) return "";
+  DeviceGuard g(plan->device);
+  hipFuncAttributes a{};
+  if (hipFuncGetAttributes(&a, v.kernel) != hipSuccess) return "";
+  return ",\"variant_resources\":{\"vgprs\":" + std::to_string(a.numRegs) +
+         ",\"scratch_bytes_per_lane\":" + std::to_string(a.localSizeBytes) +
+         ",\"lds_bytes\":" + std::to_string(a.sharedSizeBytes) +
+         ",\"max_threads\":" + std::to_string(a.maxThreadsPerBlock) + "}";
+}
+
 extern "C" int fft_plan_describe(fft_plan_t plan, char* buf, int64_t cap) {
   if (!plan || !live_handle(plan)) return FFT_INVALID_PLAN;
   std::string s = "{\"n\":" + std::to_string(plan->n) + ",\"batch\":" +
@@ -1217,7 +1230,7 @@ extern "C" int fft_plan_describe(fft_plan_t plan, char* buf, int64_t cap) {
                   ",\"algorithm\":\"" +
                   (plan->algorithm == FFT_ALGO_FOUR_STEP ? "four_step" : "single_pass") + "\"" +
                   ",\"workspace_bytes\":" + std::to_string(plan->ws_bytes) +
-                  ",\"variant\":" + describe_single(*plan->sv) +
+                  ",\"variant\":" + describe_single(*plan->sv) + kernel_resources(plan, *plan->sv) +
                   (plan->fs ? ",\"four_step\":" + describe_four_step(*plan->fs) : "") +
                   (plan->sv_filter ? ",\"filter_variant\":\"" + std::string(plan->sv_filter->name) + "\""
                                    : "") +

@@ -30,6 +30,7 @@ SingleVariant make_variant(const char* name) {
     v.launch = &launch_stream<S, IoF32>;
     v.launch_f16 = &launch_stream<S, IoF16>;
     v.launch_bf16 = &launch_stream<S, IoBF16>;
+    v.kernel = reinterpret_cast<const void*>(&k_stockham_stream<S, false, IoF32>);
     return v;
   } else {
     v.launch = &launch_single<S>;
@@ -39,6 +40,7 @@ SingleVariant make_variant(const char* name) {
     }
     v.launch_f16 = &launch_single_io<S, IoF16>;
     v.launch_bf16 = &launch_single_io<S, IoBF16>;
+    v.kernel = reinterpret_cast<const void*>(&k_stockham<S, false>);
   }
   return v;
 }

@@ -61,6 +61,8 @@ struct SingleVariant {
   // in HBM as IEEE half pairs (launch_f16) or bfloat16 pairs (launch_bf16).
   LaunchFn launch_f16;
   LaunchFn launch_bf16;
+  // The forward FP32 kernel itself, for resource queries (hipFuncGetAttributes).
+  const void* kernel;
 };
 
 extern const SingleVariant kSingleVariants[];

@@ -18,6 +18,10 @@ ragged batch.  The result is a JSON file that
    "storage16_entries": [...],                          (same form)
    "ragged": [{"n": 4096, "shape": "ragged_n4096_e16", "batch_us": ...}]}
 
+Each plain entry also records, per single-pass candidate, the registers,
+scratch and LDS of its compiled kernel as the runtime reports them
+("resources"), so a choice can be read against its occupancy and spills.
+
 Timing: back-to-back launches over a ring of independent buffers larger
 than the Infinity Cache, bracketed by HIP events on the launch stream; the
 median of three repeats, each at least REPEAT_US of GPU time; candidates
@@ -134,11 +138,16 @@ def tune_plain(torch, dev, stream, sizes=SIZES, buckets=BUCKETS, iters=30, log=p
             xs, ys = _ring(torch, dev, n, b)
             k = len(xs)
             times = {}
+            res = {}
             cs = stream.cuda_stream
             algos = dict(candidates(n))
 
             def timed(name, factor=1):
                 p = Plan(n, b, FFT_FORWARD, algos[name], name)
+                if algos[name] == FFT_ALGO_SINGLE_PASS and name not in res:
+                    r = p.describe().get("variant_resources")
+                    if r:
+                        res[name] = r
                 t = _time(torch, stream,
                           lambda i: p.exec(xs[i % k].data_ptr(), ys[i % k].data_ptr(), cs),
                           iters * factor)
@@ -151,7 +160,8 @@ def tune_plain(torch, dev, stream, sizes=SIZES, buckets=BUCKETS, iters=30, log=p
             log(f"tune n={n} batch={b} -> {best} {times[best]:.2f} us")
             entries.append({"n": n, "batch_min": bmin, "batch_max": bmax, "variant": best,
                             "timed_batch": b, "us": round(times[best], 3),
-                            "candidates": {k2: round(v, 3) for k2, v in times.items()}})
+                            "candidates": {k2: round(v, 3) for k2, v in times.items()},
+                            "resources": res})
             del xs, ys
     return entries
 

@@ -145,6 +145,12 @@ def test_builtin_table_is_the_shipped_tuner_output():
     for e in doc["fused_entries"]:
         for b in (e["batch_min"], e["timed_batch"], min(e["batch_max"], 10 ** 9)):
             assert sf.fft_tune_query_fused(e["n"], b) == e["variant"], (e["n"], b)
+    # every shipped single-pass choice was recorded with its kernel's
+    # resources, and none of them spills
+    for e in doc["entries"]:
+        if e["n"] <= 16384 and not e["variant"].startswith("fs"):
+            r = e["resources"][e["variant"]]
+            assert r["scratch_bytes_per_lane"] == 0 and 0 < r["vgprs"] <= 512, e["variant"]
     assert doc.get("storage16_entries")
     for e in doc["storage16_entries"]:
         for b in (e["batch_min"], e["timed_batch"], min(e["batch_max"], 10 ** 9)):

@@ -218,6 +218,13 @@ def test_plan_describe_and_alloc_failure(monkeypatch):
     assert d["algorithm"] == "four_step" and d["workspace_bytes"] == 16384 * 3 * 8
     assert d["four_step"]["n1"] * d["four_step"]["n2"] == 16384
     p.close()
+    # the compiled kernel's resources as the runtime reports them (the
+    # headline shape: no scratch, its static LDS as the variant states)
+    p = sf.Plan(4096, 256, variant="n4096_e8_b1_p4_r8.8.8.8_pt")
+    r = p.describe()["variant_resources"]
+    assert 0 < r["vgprs"] <= 128 and r["scratch_bytes_per_lane"] == 0
+    assert r["lds_bytes"] == p.describe()["variant"]["lds_bytes"] and r["max_threads"] >= 512
+    p.close()
     monkeypatch.setenv("STOCKFFT_FAIL_ALLOC", "1")
     with pytest.raises(sf.StockfftError) as e:
         sf.Plan(4096, 3)

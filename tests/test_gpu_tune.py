@@ -21,6 +21,10 @@ def test_tuner_restricted_search_and_load(tmp_path):
     for e in entries:
         assert e["variant"] in e["candidates"]
         assert e["us"] == min(e["candidates"].values())
+        singles = {v["name"] for v in sf.variants() if v["kind"] == "single" and v["n"] == e["n"]}
+        assert set(e["resources"]) == singles
+        for r in e["resources"].values():
+            assert 0 < r["vgprs"] <= 512 and r["scratch_bytes_per_lane"] >= 0 and r["lds_bytes"] > 0
     path = tmp_path / "tune.json"
     path.write_text(json.dumps({"arch": "gfx950", "entries": entries, "ragged": []}))
     sf.fft_tune_clear()
