@@ -98,6 +98,29 @@ def test_lowp_auto_plan_in_place_and_repeatable(fmt):
 
 
 @pytest.mark.parametrize("fmt", ["f16", "bf16"])
+@pytest.mark.parametrize("batch", [256, 2048, 16384])
+def test_lowp_tuned_plans_at_bench_sizes_sampled_rows(fmt, batch):
+    """The tuned 16-bit shapes at the batches the bench times (4096 x 256,
+    2048, 16384; a persistent shape at 16384), both directions: rows sampled
+    across the batch against the oracle on the stored values."""
+    n = 4096
+    g = torch.Generator(device=DEV)
+    g.manual_seed(batch + 3)
+    dt = torch.float16 if fmt == "f16" else torch.bfloat16
+    xt = (torch.randn(batch, n, 2, device=DEV, generator=g)).to(dt)
+    rows = sorted({0, 1, batch // 3, batch // 2 + 7, batch - 2, batch - 1})
+    xv = _host(xt[rows], fmt)
+    for inverse in (False, True):
+        y = sf.fft_lowp(xt, inverse=inverse)
+        ok, worst, _, ab = metrics.gate_storage(_host(y[rows], fmt), oracle.fft(xv, inverse=inverse),
+                                                xv, fmt)
+        assert ok, (inverse, worst, ab)
+        del y
+    del xt
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("fmt", ["f16", "bf16"])
 def test_lowp_output_is_the_fp32_result_rounded_once(fmt):
     # The same plan in FP32 on the widened input gives the values before the
     # final rounding; the 16-bit result must be those, rounded to nearest
