@@ -462,6 +462,13 @@ def compare(args, torch, np, sf, metrics, workloads, T, dev, cs):
         p.close()
         del xs, ys
 
+    # Exchange tiers at N = 4096 on one radix plan (8 8 8 8) and one twiddle
+    # table: every exchange through the LDS (padded) against the exchanges
+    # after passes 0 and 2 as in-wave transposes (one or two groups per lane).
+    comps["exchange_tiers_n4096"] = compare_exchange_tiers(torch, np, sf, metrics, workloads, T,
+                                                           dev, cs, iters, warm)
+    log("exchange tiers", comps["exchange_tiers_n4096"])
+
     # Ragged persistent launch vs per-size plain launches.
     try:
         comps["ragged_2000"] = compare_ragged(args, torch, np, sf, metrics, workloads, T, dev, cs, iters, warm)
@@ -469,6 +476,37 @@ def compare(args, torch, np, sf, metrics, workloads, T, dev, cs):
     except sf.StockfftError as e:
         comps["ragged_2000"] = {"error": str(e)}
     return comps
+
+
+EXCHANGE_TIERS = (("lds", "n4096_e8_b1_p4_r8.8.8.8_pt"),
+                  ("in_wave_one_group_per_lane", "n4096_e8_b1_px_r8.8.8.8_pt_wx1"),
+                  ("in_wave_two_groups_per_lane", "n4096_e16_b1_px_r8.8.8.8_pt_wx2"))
+
+
+def compare_exchange_tiers(torch, np, sf, metrics, workloads, T, dev, cs, iters, warm):
+    n = 4096
+    out = {}
+    for b in (32, 256, 2048):
+        x_h = workloads.plain_normal(n, b, seed=4242 + b)
+        K = ring_count(2 * n * b * 8)
+        xs = [torch.from_numpy(x_h).to(dev)] + [torch.randn(b, n, dtype=torch.complex64, device=dev)
+                                                for _ in range(K - 1)]
+        ys = [torch.empty_like(xs[0]) for _ in range(K)]
+        want = ref_fft(np, x_h)
+        rec = {}
+        for label, name in EXCHANGE_TIERS:
+            p = sf.Plan(n, b, sf.FFT_FORWARD, sf.FFT_ALGO_SINGLE_PASS, name)
+            t = T.run(lambda i: p.exec(xs[i % K].data_ptr(), ys[i % K].data_ptr(), cs), iters, warm) / iters
+            p.exec(xs[0].data_ptr(), ys[0].data_ptr(), cs)
+            torch.cuda.synchronize()
+            ok, worst, _, _ = metrics.gate(ys[0].cpu().numpy(), want, x_h)
+            rec[label] = {"variant": name, "us": round(t * 1e6, 3),
+                          "pct_hbm": round(100 * 16 * n * b / t / 1e9 / HBM_PEAK_GBS, 2),
+                          "worst_rel_rms": worst, "gates_pass": bool(ok)}
+            p.close()
+        out[f"b{b}"] = rec
+        del xs, ys
+    return out
 
 
 def compare_lowp(torch, np, sf, metrics, workloads, T, dev, cs, iters, warm):

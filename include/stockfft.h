@@ -84,6 +84,10 @@ enum fft_status {
  * the host and rounded once to FP32) and, for the four-step algorithm, a
  * workspace of batch * n * 8 bytes.  It belongs to the device that was
  * current when it was created.
+ * With the environment variable STOCKFFT_LOG set (to anything but "" or
+ * "0") every plan prints one line on stderr when it is created: its length,
+ * batch, direction, algorithm, kernel variant, and the shapes of its fused,
+ * matched-filter and 16-bit storage kernels.
  * Errors: FFT_INVALID_POINTER, FFT_INVALID_SIZE, FFT_INVALID_BATCH,
  * FFT_INVALID_DIRECTION, FFT_NO_DEVICE, FFT_ALLOC_FAILED, FFT_HIP_ERROR.
  */

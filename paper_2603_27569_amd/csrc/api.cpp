@@ -222,7 +222,7 @@ const BuiltinEntry kBuiltin[] = {
     {2048, 769, 1536, "n2048_e16_b1_p4_r16.16.8_pt"},
     {2048, 1537, 4096, "n2048_e32_c2_b1_p4_r16.16.8_pt"},
     {2048, 4097, INT64_MAX, "n2048_e16_b2_p4_r16.16.8_pt"},
-    {4096, 1, 64, "n4096_e16_b1_p5_r16.16.16_pt"},
+    {4096, 1, 64, "n4096_e8_b1_px_r8.8.8.8_pt_wx1"},
     {4096, 65, 384, "n4096_e8_b1_p4_r8.8.8.8_pt"},
     {4096, 385, 768, "n4096_e8_b1_p4_r8.8.8.8_pt"},
     {4096, 769, 1536, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
@@ -354,7 +354,7 @@ const BuiltinEntry kBuiltinStorage16[] = {
     {2048, 769, 1536, "n2048_e16_b1_p4_r16.16.8_pt"},
     {2048, 1537, 4096, "n2048_e16_b2_p4_r16.16.8_pt"},
     {2048, 4097, INT64_MAX, "n2048_e32_c2_b1_p4_r16.16.8_pt"},
-    {4096, 1, 64, "n4096_e8_b1_p4_r8.8.8.8"},
+    {4096, 1, 64, "n4096_e8_b1_px_r8.8.8.8_pt"},
     {4096, 65, 384, "n4096_e8_b1_p4_r8.8.8.8_pt_tall"},
     {4096, 385, 768, "n4096_e8_b1_px_r8.8.8.8_pt"},
     {4096, 769, 1536, "n4096_e32_b1_p4_r16.16.16_pt"},
@@ -721,6 +721,21 @@ static int validate_common(int64_t n, int64_t batch, int direction) {
   return FFT_SUCCESS;
 }
 
+// STOCKFFT_LOG set to anything but "" or "0": every plan prints its choices
+// (one line on stderr) when it is created.
+static void log_plan(const stockfft_plan_s* p, bool named) {
+  const char* env = std::getenv("STOCKFFT_LOG");
+  if (!env || !*env || (env[0] == '0' && !env[1])) return;
+  const auto nm = [](const SingleVariant* v) { return v ? v->name : "-"; };
+  std::fprintf(stderr,
+               "stockfft: plan n=%lld batch=%lld direction=%d algorithm=%s variant=%s "
+               "four_step=%s fused=%s filter=%s storage16=%s source=%s\n",
+               (long long)p->n, (long long)p->batch, p->direction,
+               p->algorithm == FFT_ALGO_FOUR_STEP ? "four_step" : "single_pass", nm(p->sv),
+               p->fs ? p->fs->name : "-", nm(p->sv_fused), nm(p->sv_filter), nm(p->sv_storage16),
+               named ? "named" : "tuned");
+}
+
 extern "C" int fft_plan_config(fft_plan_t* plan, int64_t n, int64_t batch, int direction,
                                int algorithm, const char* variant) {
   if (!plan) return FFT_INVALID_POINTER;
@@ -855,6 +870,7 @@ extern "C" int fft_plan_config(fft_plan_t* plan, int64_t n, int64_t batch, int d
   }
   register_handle(p);
   *plan = p;
+  log_plan(p, variant != nullptr);
   return FFT_SUCCESS;
 }
 
@@ -1125,6 +1141,9 @@ static int barriers_of(const SingleVariant& v) {
   // pass writes global memory directly, as the first pass reads it); with
   // two alternating buffers only the one after the writes.
   if (v.npass < 2) return 0;
+  // In-wave exchanges: only the middle exchange goes through the LDS, and
+  // its buffer is not reused.
+  if (v.wave_exchange) return 1;
   return v.double_buffered ? v.npass - 1 : 2 * v.chunks * (v.npass - 1) - 1;
 }
 
@@ -1146,13 +1165,13 @@ static std::string describe_single(const SingleVariant& v) {
                 "\"passes\":%d,\"radices\":%s,\"exchange_rounds\":%d,\"threads\":%d,"
                 "\"lds_bytes\":%d,\"twiddle_entries\":%d,\"barriers\":%d,"
                 "\"double_buffered\":%s,\"twiddle_schedule\":%d,\"paired_twiddles\":%s,\"paired_lanes\":%s,"
-                "\"fused_kernels\":%s,\"streamed\":%d}",
+                "\"fused_kernels\":%s,\"streamed\":%d,\"wave_exchange\":%d}",
                 v.name, v.n, v.e, v.t, v.tpb, v.padlog,
                 v.padlog > 0 ? "pad" : v.padlog < 0 ? "xor" : "none", v.npass, radices_json(v).c_str(),
                 v.chunks, v.threads, v.lds_bytes, v.tw_elems, barriers_of(v),
                 v.double_buffered ? "true" : "false", v.twiddle_schedule,
                 v.paired_twiddles ? "true" : "false", v.paired_lanes ? "true" : "false",
-                v.fused && v.filter ? "true" : "false", v.streamed);
+                v.fused && v.filter ? "true" : "false", v.streamed, v.wave_exchange);
   return buf;
 }
 

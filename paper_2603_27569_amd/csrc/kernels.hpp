@@ -181,6 +181,7 @@ hipError_t launch_single(const void* in, void* out, const void* tw, int64_t batc
 // 16-bit storage formats: one complex value in 4 bytes (real in the low
 // half).  Loads widen exactly to FP32; stores round to nearest even.
 struct IoF16 {
+  static constexpr int BYTES = 4;
   __device__ __forceinline__ static c32 load(uint32_t v) {
     const float2 f = __half22float2(*reinterpret_cast<const __half2*>(&v));
     return c32{f.x, f.y};
@@ -192,6 +193,7 @@ struct IoF16 {
 };
 
 struct IoBF16 {
+  static constexpr int BYTES = 4;
   __device__ __forceinline__ static c32 load(uint32_t v) {
     return c32{__uint_as_float(v << 16), __uint_as_float(v & 0xffff0000u)};
   }
@@ -284,6 +286,7 @@ hipError_t launch_single_io(const void* in, void* out, const void* tw, int64_t b
 // only for LDS traffic.
 
 struct IoF32 {  // complex64 storage, for the streaming form's FP32 launch
+  static constexpr int BYTES = 8;
   __device__ __forceinline__ static c32 load(u32x2 v) {
     return c32{__uint_as_float(v.x), __uint_as_float(v.y)};
   }

@@ -2,6 +2,7 @@
 #pragma once
 
 #include "kernels.hpp"
+#include "wavex.hpp"
 
 namespace stockfft {
 
@@ -25,7 +26,16 @@ SingleVariant make_variant(const char* name) {
   v.threads = S::THREADS;
   v.lds_bytes = S::TPB * S::LDS_ELEMS * (int)sizeof(c32);
   v.tw_elems = S::TW_ELEMS;
-  if constexpr (streamed<S>::value > 0) {
+  v.wave_exchange = wave_exchange<S>::value;
+  if constexpr (wave_exchange<S>::value > 0) {
+    // Plain transform only (either storage): the fused kernels run the
+    // all-LDS schedule.
+    v.launch = &launch_wx<S, IoF32>;
+    v.launch_f16 = &launch_wx<S, IoF16>;
+    v.launch_bf16 = &launch_wx<S, IoBF16>;
+    v.kernel = reinterpret_cast<const void*>(&k_stockham_wx<S, false, IoF32>);
+    return v;
+  } else if constexpr (streamed<S>::value > 0) {
     // Persistent shapes run the plain transform only (either storage).
     v.launch = &launch_stream<S, IoF32>;
     v.launch_f16 = &launch_stream<S, IoF16>;

@@ -51,6 +51,7 @@ struct SingleVariant {
   bool paired_twiddles;  // table layout: two twiddles per 16-byte entry (PairedTwiddles)
   bool paired_lanes;     // first/last pass in the paired butterfly order (PairedLanes)
   int streamed;          // 0: a workgroup per transform; k: k persistent workgroups per CU (Streamed)
+  int wave_exchange;     // 0: every exchange through the LDS; G: in-wave exchanges, G groups per lane (WaveExchange)
   int threads;
   int lds_bytes;
   int tw_elems;

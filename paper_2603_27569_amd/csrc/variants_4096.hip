@@ -9,6 +9,7 @@ using stockfft::PairedTwiddles;
 using stockfft::Shape;
 using stockfft::ShapeX;
 using stockfft::Streamed;
+using stockfft::WaveExchange;
 using stockfft::make_variant;
 
 STOCKFFT_VARIANT_GROUP(variants_4096,
@@ -59,4 +60,14 @@ STOCKFFT_VARIANT_GROUP(variants_4096,
   make_variant<Streamed<PairedTwiddles<ShapeX<1, 2, 1, 4096, 8, 1, 4, 8, 8, 8, 8>>, 1, 3>>(
       "n4096_e8_b1_p4_r8.8.8.8_pt_tall_st1d3"),
   make_variant<Streamed<PairedTwiddles<ShapeX<1, 2, 1, 4096, 8, 1, 4, 8, 8, 8, 8>>, 2, 2>>(
-      "n4096_e8_b1_p4_r8.8.8.8_pt_tall_st2d2"))
+      "n4096_e8_b1_p4_r8.8.8.8_pt_tall_st2d2"),
+  // In-wave exchanges after passes 0 and 2 (8 x 8 transposes by cross-lane
+  // moves), the LDS only between passes 1 and 2: one barrier per transform.
+  // _wx1: one group per lane (8-byte accesses in 64-byte runs); _wx2: two
+  // adjacent groups per lane (16-byte accesses in whole 128-byte lines).
+  make_variant<WaveExchange<PairedTwiddles<ShapeX<1, 2, 1, 4096, 8, 1, -1, 8, 8, 8, 8>>, 1>>(
+      "n4096_e8_b1_px_r8.8.8.8_pt_wx1"),
+  make_variant<WaveExchange<PairedTwiddles<ShapeX<1, 2, 1, 4096, 16, 1, -1, 8, 8, 8, 8>>, 2>>(
+      "n4096_e16_b1_px_r8.8.8.8_pt_wx2"),
+  make_variant<WaveExchange<ShapeX<1, 2, 1, 4096, 8, 1, -1, 8, 8, 8, 8>, 1>>(
+      "n4096_e8_b1_px_r8.8.8.8_wx1"))

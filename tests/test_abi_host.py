@@ -243,7 +243,11 @@ def test_variant_inventory():
         assert v["lds_bytes"] == v["transforms_per_workgroup"] * bufs * (chunk + pad) * 8
         assert v["lds_bytes"] <= 160 * 1024  # gfx950 LDS per workgroup
         c = v["exchange_rounds"]
-        if v["double_buffered"]:  # one barrier per exchange, whole-transform rounds
+        if v["wave_exchange"]:  # exchanges after passes 0 and 2 in registers: one LDS exchange
+            assert v["n"] == 4096 and v["radices"] == [8, 8, 8, 8] and c == 1
+            assert v["barriers"] == 1 and not v["fused_kernels"]
+            assert v["values_per_lane"] == 8 * v["wave_exchange"]
+        elif v["double_buffered"]:  # one barrier per exchange, whole-transform rounds
             assert c == 1 and v["barriers"] == v["passes"] - 1
         else:
             assert v["barriers"] == (2 * c * (v["passes"] - 1) - 1 if v["passes"] > 1 else 0)

@@ -137,3 +137,19 @@ def test_stale_tune_files_are_ignored(tmp_path):
         assert sf.fft_tune_query(2048, 5) == other
     finally:
         sf.fft_tune_clear()
+
+
+def test_plan_log_names_the_tuned_choices(monkeypatch, capfd):
+    """STOCKFFT_LOG prints each plan's choices on stderr; unset, nothing."""
+    sf.fft_tune_clear()
+    monkeypatch.setenv("STOCKFFT_LOG", "1")
+    p = sf.Plan(4096, 32, sf.FFT_FORWARD)
+    p.close()
+    err = capfd.readouterr().err
+    line = next(ln for ln in err.splitlines() if ln.startswith("stockfft: plan n=4096 batch=32"))
+    assert f"variant={sf.fft_tune_query(4096, 32)} " in line
+    assert "algorithm=single_pass" in line and "source=tuned" in line
+    assert f"storage16={sf.fft_tune_query_storage16(4096, 32)} " in line
+    monkeypatch.setenv("STOCKFFT_LOG", "0")
+    sf.Plan(4096, 32, sf.FFT_FORWARD).close()
+    assert "stockfft: plan" not in capfd.readouterr().err
