@@ -52,7 +52,7 @@ def log(*a):
 def kernel_source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_27569_amd", "csrc")
-    for f in ("stockham.hpp", "kernels.hpp", "variants_4096.hip"):
+    for f in ("stockham.hpp", "kernels.hpp", "wavex.hpp", "variants_4096.hip"):
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -203,6 +203,7 @@ def main():
 
     # -------------------------------------------------------------- roofline
     t_kernel = (t_fwd + t_bwd) / 2
+    kernel_family = "k_stockham_wx" if fwd.describe()["variant"].get("wave_exchange") else "k_stockham"
     achieved = bytes_launch / t_kernel / 1e9
     traffic = None
     try:
@@ -214,7 +215,7 @@ def main():
         pass
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": f"k_stockham<{variant}>", "algorithmic_bytes_per_launch": bytes_launch,
+                "kernel": f"{kernel_family}<{variant}>", "algorithmic_bytes_per_launch": bytes_launch,
                 "avg_launch_us": round(t_kernel * 1e6, 3)}
 
     # ----------------------------------------------------- reference kernels
@@ -480,7 +481,8 @@ def compare(args, torch, np, sf, metrics, workloads, T, dev, cs):
 
 EXCHANGE_TIERS = (("lds", "n4096_e8_b1_p4_r8.8.8.8_pt"),
                   ("in_wave_one_group_per_lane", "n4096_e8_b1_px_r8.8.8.8_pt_wx1"),
-                  ("in_wave_two_groups_per_lane", "n4096_e16_b1_px_r8.8.8.8_pt_wx2"))
+                  ("in_wave_two_groups_per_lane", "n4096_e16_b1_px_r8.8.8.8_pt_wx2"),
+                  ("in_wave_two_members_per_lane", "n4096_e16_b1_px_r8.8.8.8_pt_wm2"))
 
 
 def compare_exchange_tiers(torch, np, sf, metrics, workloads, T, dev, cs, iters, warm):

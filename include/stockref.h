@@ -102,7 +102,9 @@ int ref_lds_exchange(int64_t groups, int rounds, float *out, void *stream);
  *            with them) landed, 2 .. 2P the pass marks (after
  *            pass p's arithmetic: 2p + 2; after the exchange that follows
  *            it: 2p + 3), 2P + 1 stores issued, 2P + 2 stores completed.
- *            Unused slots are 0.
+ *            Unused slots are 0.  For the in-wave exchange shapes (names
+ *            ending in _wx1 or _wm2) the exchanges after passes 0 and 2 are
+ *            the register transposes and the one after pass 1 the LDS.
  * The readings wait for the memory operations in flight at each mark, so
  * the timed kernel runs somewhat slower than the plain one.
  */

@@ -27,6 +27,7 @@ SingleVariant make_variant(const char* name) {
   v.lds_bytes = S::TPB * S::LDS_ELEMS * (int)sizeof(c32);
   v.tw_elems = S::TW_ELEMS;
   v.wave_exchange = wave_exchange<S>::value;
+  v.wave_members = wave_members<S>::value;
   if constexpr (wave_exchange<S>::value > 0) {
     // Plain transform only (either storage): the fused kernels run the
     // all-LDS schedule.

@@ -52,6 +52,7 @@ struct SingleVariant {
   bool paired_lanes;     // first/last pass in the paired butterfly order (PairedLanes)
   int streamed;          // 0: a workgroup per transform; k: k persistent workgroups per CU (Streamed)
   int wave_exchange;     // 0: every exchange through the LDS; G: in-wave exchanges, G groups per lane (WaveExchange)
+  int wave_members;      // with in-wave exchanges: members of each group per lane (1 or 2)
   int threads;
   int lds_bytes;
   int tw_elems;

@@ -70,4 +70,8 @@ STOCKFFT_VARIANT_GROUP(variants_4096,
   make_variant<WaveExchange<PairedTwiddles<ShapeX<1, 2, 1, 4096, 16, 1, -1, 8, 8, 8, 8>>, 2>>(
       "n4096_e16_b1_px_r8.8.8.8_pt_wx2"),
   make_variant<WaveExchange<ShapeX<1, 2, 1, 4096, 8, 1, -1, 8, 8, 8, 8>, 1>>(
-      "n4096_e8_b1_px_r8.8.8.8_wx1"))
+      "n4096_e8_b1_px_r8.8.8.8_wx1"),
+  // Two members of each group per lane (_wm2): 8-byte accesses covering whole
+  // 128-byte lines, transposes by permlane swaps only.
+  make_variant<WaveExchange<PairedTwiddles<ShapeX<1, 2, 1, 4096, 16, 1, -1, 8, 8, 8, 8>>, 1, 2>>(
+      "n4096_e16_b1_px_r8.8.8.8_pt_wm2"))

@@ -22,25 +22,36 @@
 // stockham.hpp unchanged (same twiddle tables, same DFT_8), only the
 // butterfly-to-lane map differs per pass.
 //
-// The price is in the global accesses: a wave owns 8 G groups, so for one
-// leg its loads cover G 8-byte values at 8 G consecutive positions for each
-// of the 8 members (positions g + 64 m): runs of 64 G bytes instead of one
-// 512-byte run.  G = 2 (two adjacent groups per lane, 16 values per lane)
-// makes every run a whole 128-byte line and every access 16 bytes.
+// The price is in the global accesses and in the moves: with one member per
+// lane a wave owns 8 G groups, so for one leg its loads cover G 8-byte values
+// at 8 G consecutive positions for each of the 8 members (positions
+// g + 64 m): runs of 64 G bytes instead of one 512-byte run.  G = 2 (two
+// adjacent groups per lane, 16 values per lane) makes every run a whole
+// 128-byte line and every access 16 bytes; M = 2 (two members per lane) does
+// it with 8-byte accesses and replaces the DPP step by a register rename.
+// Each cross-lane step costs one VALU instruction per 32-bit value moved
+// (permlane swaps: one per two values; DPP: a move and a select per value),
+// where an LDS exchange costs two memory instructions per 64-bit value.
 #pragma once
 
 #include "stockham.hpp"
 
 namespace stockfft {
 
-template <class Base, int G_>
+// G adjacent groups per lane; M members of each group per lane (M = 1: the
+// member is lane bits 3..5; M = 2: its low two bits are lane bits 4..5 and
+// its top bit selects one of the lane's two butterflies of the group, so a
+// wave holds 16 whole groups and one leg of a wave's loads covers four
+// 128-byte lines with 8-byte accesses, and the transpose needs no DPP).
+template <class Base, int G_, int M_ = 1>
 struct WaveExchange : Base {
   static_assert(Base::N == 4096 && Base::P == 4 && Base::radix(0) == 8 && Base::radix(1) == 8 &&
                     Base::radix(2) == 8 && Base::radix(3) == 8,
                 "the in-wave exchange is derived for the radix-8 plan of 4096 points");
-  static_assert(G_ == 1 || G_ == 2, "one or two groups per lane");
-  static_assert(Base::E == 8 * G_ && Base::TPB == 1 && Base::C == 1, "shape");
+  static_assert((G_ == 1 || G_ == 2) && (M_ == 1 || M_ == 2), "one or two groups / members per lane");
+  static_assert(Base::E == 8 * G_ * M_ && Base::TPB == 1 && Base::C == 1, "shape");
   static constexpr int WX = G_;
+  static constexpr int WXM = M_;
   // The one LDS exchange uses its own swizzle over 4096 elements (wx_slot).
   static constexpr int LDS_ELEMS = 4096;
 };
@@ -49,16 +60,29 @@ template <class S, class = void>
 struct wave_exchange : std::integral_constant<int, 0> {};
 template <class S>
 struct wave_exchange<S, std::void_t<decltype(S::WX)>> : std::integral_constant<int, S::WX> {};
+template <class S, class = void>
+struct wave_members : std::integral_constant<int, 0> {};
+template <class S>
+struct wave_members<S, std::void_t<decltype(S::WXM)>> : std::integral_constant<int, S::WXM> {};
 
 // Physical LDS slot of exchange position i = 64 q + 8 b + c (c, b in [0, 8)):
 // bits 0..4 of i are xor-ed with bits 6..9, a bijection inside every block
-// of 64.  For both access patterns of the exchange (writes at 64 g + m + 8 r,
-// reads at h + 64 m + 512 r; lanes vary the group's low bits and the member)
-// any 32 consecutive lanes then hit 32 different 8-byte slots modulo 32,
-// i.e. all 64 four-byte banks once (checked on the CPU for every access).
+// of 64 that leaves bits 5 and up alone.  For both access patterns of the
+// exchange (writes at 64 g + m + 8 r, reads at h + 64 m + 512 r; lanes vary
+// the group's low bits and the member's lane bits) any 32 consecutive lanes
+// then hit 32 different 8-byte slots modulo 32, i.e. all 64 four-byte banks
+// once (checked on the CPU for every access of both layouts).
+template <int M>
 __device__ __forceinline__ int wx_slot(int i) {
   const int q = i >> 6;
-  return i ^ (q & 7) ^ (((q ^ (q >> 3)) & 1) << 3) ^ (((q >> 1) & 1) << 4);
+  if constexpr (M == 1) {
+    return i ^ (q & 7) ^ (((q ^ (q >> 3)) & 1) << 3) ^ (((q >> 1) & 1) << 4);
+  } else {
+    // Two members per lane: the lanes of one access vary the group's low four
+    // bits and two member bits; bits 0..4 are xor-ed with bits 9, 6, 7, 8 and
+    // 9 ^ 6 of i.
+    return i ^ ((q >> 3) & 1) ^ ((q & 7) << 1) ^ ((((q >> 3) ^ q) & 1) << 4);
+  }
 }
 
 // Swaps two 32-bit values between lane halves: lanes 32..63 of p with lanes
@@ -106,6 +130,38 @@ __device__ __forceinline__ void transpose8(c32 (&v)[8], bool hi3) {
   }
 }
 
+// The same transpose with M members of the group per lane: member bit k
+// pairs with leg bit k; member bits below LB = log2(8 / M) are lane bits
+// 6 - LB + k (swapped across lanes), the others select the lane's butterfly
+// (swapped between registers, which costs nothing).
+template <int M>
+__device__ __forceinline__ void transpose_members(c32 (&v)[M][8], bool hi3) {
+  if constexpr (M == 1) {
+    transpose8(v[0], hi3);
+  } else {
+    static_assert(M == 2, "members per lane");
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+#pragma unroll
+      for (int r = 0; r < 8; r += 2) {  // member bit 0: lane bit 4, leg bit 0
+        swap_lanes16(v[s][r].x, v[s][r + 1].x);
+        swap_lanes16(v[s][r].y, v[s][r + 1].y);
+      }
+#pragma unroll
+      for (int r = 0; r < 8; r += (r & 1) ? 3 : 1) {  // member bit 1: lane bit 5, leg bit 1
+        swap_lanes32(v[s][r].x, v[s][r + 2].x);
+        swap_lanes32(v[s][r].y, v[s][r + 2].y);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {  // member bit 2: the butterfly, leg bit 2
+      const c32 t = v[1][r];
+      v[1][r] = v[0][r + 4];
+      v[0][r + 4] = t;
+    }
+  }
+}
+
 // Raw storage of one value (8 bytes FP32, 4 bytes 16-bit) and of the G
 // adjacent values a lane moves with one access.
 template <class IO, int G>
@@ -141,97 +197,165 @@ struct WxAccess {
   }
 };
 
-// One 4096-point transform per workgroup of 512 / G lanes.  Lane l of wave w
-// is member m = l >> 3 of the groups G (8 w + (l & 7)) + u, u < G.
-template <class S, bool INV, class IO>
-__global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham_wx(const void* in, void* out,
-                                                             const c32* tw, int64_t rows) {
-  constexpr int G = S::WX;
-  using A = WxAccess<IO, G>;
-  constexpr int B = IO::BYTES;
-  __shared__ alignas(16) c32 lds[S::LDS_ELEMS];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int m = lane >> 3;
-  const int g0 = G * (8 * (tid >> 6) + (lane & 7));  // first group of the lane
-  const bool hi3 = (lane & 8) != 0;
-  const int64_t row = blockIdx.x;
-  (void)rows;  // one row per workgroup: the grid is the batch
+// One 4096-point transform per workgroup of 512 / (G M) lanes.  Lane l of
+// wave w holds, for u < G and s < M, member m = (l >> (6 - LB)) + 2^LB s of
+// group G (GPW w + (l mod GPW)) + u, where LB = log2(8 / M) member bits sit
+// at the top of the lane index and GPW = 64 / 2^LB groups share a wave.
+template <class S>
+struct WxLane {
+  static constexpr int G = S::WX;
+  static constexpr int M = S::WXM;
+  static constexpr int LB = M == 1 ? 3 : 2;
+  static constexpr int GPW = 64 >> LB;
+  static constexpr int MS = 1 << LB;  // member stride between a lane's butterflies
+  int m0;    // the lane's first member
+  int g0;    // the lane's first group
+  bool hi3;  // lane bit 3 (the DPP step of the one-member transpose)
+  __device__ __forceinline__ explicit WxLane(int tid)
+      : m0((tid & 63) >> (6 - LB)), g0(G * (GPW * (tid >> 6) + (tid & (GPW - 1)))),
+        hi3((tid & 8) != 0) {}
+  __device__ __forceinline__ int member(int s) const { return m0 + MS * s; }
+};
 
-  // Pass 0 legs: butterfly g + 64 m reads x[g + 64 m + 512 r].
-  c32 a[G][8];
-  {
-    const Buf src(static_cast<const char*>(in) + row * 4096 * B);
-    const int voff = B * (g0 + 64 * m);
+// The lane's values (a[u][s][r]: leg r of its butterfly (u, s)) and every
+// twiddle it applies: pass 1 (k = m, shared by the lane's groups), pass 2
+// (k = h, shared by its members), pass 3 (k = h + 64 m).
+template <class S>
+struct WxRegs {
+  c32 a[S::WX][S::WXM][8];
+  c32 w1[S::WXM][8], w2[S::WX][8], w3[S::WX][S::WXM][8];
+};
+
+// Pass 0 legs (butterfly g + 64 m reads x[g + 64 m + 512 r]) and the
+// twiddles, issued behind them.
+template <class S, class IO>
+__device__ __forceinline__ void wx_load(WxRegs<S>& R, const WxLane<S>& L, const void* in,
+                                        const c32* tw, int64_t row) {
+  constexpr int G = S::WX, M = S::WXM, B = IO::BYTES;
+  const Buf src(static_cast<const char*>(in) + row * 4096 * B);
+  const int voff = B * (L.g0 + 64 * L.m0);
+#pragma unroll
+  for (int s = 0; s < M; ++s)
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       c32 v[G];
-      A::load(v, src, voff, B * 512 * r);
+      WxAccess<IO, G>::load(v, src, voff, B * (64 * L.MS * s + 512 * r));
 #pragma unroll
-      for (int u = 0; u < G; ++u) a[u][r] = v[u];
+      for (int u = 0; u < G; ++u) R.a[u][s][r] = v[u];
     }
-  }
-  // Every twiddle, loaded behind the input: pass 1 (k = m, shared by the
-  // lane's groups), pass 2 (k = h), pass 3 (k = h + 64 m).
-  c32 w1[8], w2[G][8], w3[G][8];
-  fetch_twiddles<S, 1>(w1, 0, tw + S::tw_off(1), m);
+#pragma unroll
+  for (int s = 0; s < M; ++s) fetch_twiddles<S, 1>(R.w1[s], 0, tw + S::tw_off(1), L.member(s));
 #pragma unroll
   for (int u = 0; u < G; ++u) {
-    fetch_twiddles<S, 2>(w2[u], 0, tw + S::tw_off(2), g0 + u);
-    fetch_twiddles<S, 3>(w3[u], 0, tw + S::tw_off(3), g0 + u + 64 * m);
+    fetch_twiddles<S, 2>(R.w2[u], 0, tw + S::tw_off(2), L.g0 + u);
+#pragma unroll
+    for (int s = 0; s < M; ++s)
+      fetch_twiddles<S, 3>(R.w3[u][s], 0, tw + S::tw_off(3), L.g0 + u + 64 * L.member(s));
   }
+}
 
-  // Pass 0, in-wave exchange, pass 1.
+template <class S, bool INV>
+__device__ __forceinline__ void wx_dfts(WxRegs<S>& R) {
 #pragma unroll
-  for (int u = 0; u < G; ++u) {
-    Dft<8, INV>::run(a[u]);
-    transpose8(a[u], hi3);
+  for (int u = 0; u < S::WX; ++u)
 #pragma unroll
-    for (int r = 1; r < 8; ++r) a[u][r] = ctw<INV>(a[u][r], w1[r - 1]);
-    Dft<8, INV>::run(a[u]);
-  }
+    for (int s = 0; s < S::WXM; ++s) Dft<8, INV>::run(R.a[u][s]);
+}
+
+// The four passes.  Phase marks as run_passes sets them: 2p + 1 after pass
+// p's arithmetic, 2p + 2 after the exchange that follows it.
+template <class S, bool INV, class Pr>
+__device__ __forceinline__ void wx_passes(WxRegs<S>& R, const WxLane<S>& L, c32* lds, Pr* pr) {
+  constexpr int G = S::WX, M = S::WXM;
+  // Pass 0, in-wave exchange.
+  wx_dfts<S, INV>(R);
+  if constexpr (Pr::on) pr->mark(1);
+#pragma unroll
+  for (int u = 0; u < G; ++u) transpose_members<M>(R.a[u], L.hi3);
+  if constexpr (Pr::on) pr->mark(2);
+  // Pass 1 (Ns = 8).
+#pragma unroll
+  for (int u = 0; u < G; ++u)
+#pragma unroll
+    for (int s = 0; s < M; ++s)
+#pragma unroll
+      for (int r = 1; r < 8; ++r) R.a[u][s][r] = ctw<INV>(R.a[u][s][r], R.w1[s][r - 1]);
+  wx_dfts<S, INV>(R);
+  if constexpr (Pr::on) pr->mark(3);
   // The LDS exchange: butterfly 8 g + m writes leg r to 64 g + m + 8 r;
   // butterfly h + 64 m of pass 2 reads h + 64 m + 512 r.  Both slot maps are
   // one xor of a lane value with the leg's bits (wx_slot leaves bits 5 and
-  // up alone and is linear over the bits it mixes).
+  // up alone and xors bits 0..4 with bits 6..9 only).
 #pragma unroll
-  for (int u = 0; u < G; ++u) {
-    const int base = 64 * (g0 + u) + m;
-    const int sb = wx_slot(base);
+  for (int u = 0; u < G; ++u)
 #pragma unroll
-    for (int r = 0; r < 8; ++r) lds[sb ^ (8 * r)] = a[u][r];
-  }
+    for (int s = 0; s < M; ++s) {
+      const int sb = wx_slot<M>(64 * (L.g0 + u) + L.member(s));
+#pragma unroll
+      for (int r = 0; r < 8; ++r) lds[sb ^ (8 * r)] = R.a[u][s][r];
+    }
   __syncthreads();
 #pragma unroll
-  for (int u = 0; u < G; ++u) {
-    const int base = g0 + u + 64 * m;
-    const int s0 = wx_slot(base), s1 = wx_slot(base + 512);
+  for (int u = 0; u < G; ++u)
 #pragma unroll
-    for (int r = 0; r < 8; ++r) a[u][r] = lds[((r & 1) ? s1 - 512 : s0) + 512 * r];
-  }
-  // Pass 2, in-wave exchange, pass 3.
+    for (int s = 0; s < M; ++s) {
+      const int base = L.g0 + u + 64 * L.member(s);
+      const int s0 = wx_slot<M>(base), s1 = wx_slot<M>(base + 512);
 #pragma unroll
-  for (int u = 0; u < G; ++u) {
+      for (int r = 0; r < 8; ++r) R.a[u][s][r] = lds[((r & 1) ? s1 - 512 : s0) + 512 * r];
+    }
+  if constexpr (Pr::on) pr->mark(4);
+  // Pass 2 (Ns = 64), in-wave exchange.
 #pragma unroll
-    for (int r = 1; r < 8; ++r) a[u][r] = ctw<INV>(a[u][r], w2[u][r - 1]);
-    Dft<8, INV>::run(a[u]);
-    transpose8(a[u], hi3);
+  for (int u = 0; u < G; ++u)
 #pragma unroll
-    for (int r = 1; r < 8; ++r) a[u][r] = ctw<INV>(a[u][r], w3[u][r - 1]);
-    Dft<8, INV>::run(a[u]);
-  }
-  // Pass 3 output leg r of butterfly h + 64 m goes to h + 64 m + 512 r.
-  {
-    const Buf dst(static_cast<char*>(out) + row * 4096 * B);
-    const int voff = B * (g0 + 64 * m);
+    for (int s = 0; s < M; ++s)
+#pragma unroll
+      for (int r = 1; r < 8; ++r) R.a[u][s][r] = ctw<INV>(R.a[u][s][r], R.w2[u][r - 1]);
+  wx_dfts<S, INV>(R);
+  if constexpr (Pr::on) pr->mark(5);
+#pragma unroll
+  for (int u = 0; u < G; ++u) transpose_members<M>(R.a[u], L.hi3);
+  if constexpr (Pr::on) pr->mark(6);
+  // Pass 3 (Ns = 512).
+#pragma unroll
+  for (int u = 0; u < G; ++u)
+#pragma unroll
+    for (int s = 0; s < M; ++s)
+#pragma unroll
+      for (int r = 1; r < 8; ++r) R.a[u][s][r] = ctw<INV>(R.a[u][s][r], R.w3[u][s][r - 1]);
+  wx_dfts<S, INV>(R);
+  if constexpr (Pr::on) pr->mark(7);
+}
+
+// Pass 3 output leg r of butterfly h + 64 m goes to h + 64 m + 512 r.
+template <class S, class IO>
+__device__ __forceinline__ void wx_store(const WxRegs<S>& R, const WxLane<S>& L, void* out,
+                                         int64_t row) {
+  constexpr int G = S::WX, M = S::WXM, B = IO::BYTES;
+  const Buf dst(static_cast<char*>(out) + row * 4096 * B);
+  const int voff = B * (L.g0 + 64 * L.m0);
+#pragma unroll
+  for (int s = 0; s < M; ++s)
 #pragma unroll
     for (int r = 0; r < 8; ++r) {
       c32 v[G];
 #pragma unroll
-      for (int u = 0; u < G; ++u) v[u] = a[u][r];
-      A::store(v, dst, voff, B * 512 * r);
+      for (int u = 0; u < G; ++u) v[u] = R.a[u][s][r];
+      WxAccess<IO, G>::store(v, dst, voff, B * (64 * L.MS * s + 512 * r));
     }
-  }
+}
+
+template <class S, bool INV, class IO>
+__global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham_wx(const void* in, void* out,
+                                                             const c32* tw, int64_t rows) {
+  __shared__ alignas(16) c32 lds[S::LDS_ELEMS];
+  (void)rows;  // one row per workgroup: the grid is the batch
+  const WxLane<S> L(threadIdx.x);
+  WxRegs<S> R;
+  wx_load<S, IO>(R, L, in, tw, blockIdx.x);
+  wx_passes<S, INV, NoProbe>(R, L, lds, nullptr);
+  wx_store<S, IO>(R, L, out, blockIdx.x);
 }
 
 template <class S, class IO>

@@ -12,6 +12,7 @@
 
 #include "../../include/stockfft.h"
 #include "../csrc/kernels.hpp"
+#include "../csrc/wavex.hpp"
 
 using namespace stockfft;
 
@@ -180,6 +181,39 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham_timeline(const 
   }
 }
 
+// The same stamps around the in-wave exchange kernel's load, passes and
+// store (marks 2p + 1 after pass p, 2p + 2 after the exchange that follows).
+template <class S, bool INV>
+__global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham_wx_timeline(const c32* in, c32* out,
+                                                                           const c32* tw,
+                                                                           uint64_t* stamps) {
+  __shared__ alignas(16) c32 lds[S::LDS_ELEMS];
+  TimelineProbe pr;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) pr.rt[i] = pr.ct[i] = 0;
+  pr.read(0);
+  const int t = threadIdx.x;
+  const int64_t row = blockIdx.x;
+  const WxLane<S> L(t);
+  WxRegs<S> R;
+  wx_load<S, IoF32>(R, L, in, tw, row);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  pr.read(1);
+  wx_passes<S, INV, TimelineProbe>(R, L, lds, &pr);
+  wx_store<S, IoF32>(R, L, out, row);
+  pr.read(2 * S::P + 1);
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  pr.read(2 * S::P + 2);
+  if ((t & 63) == 0) {
+    uint64_t* dst = stamps + (row * (S::THREADS / 64) + (t >> 6)) * 32;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      dst[i] = pr.rt[i];
+      dst[16 + i] = pr.ct[i];
+    }
+  }
+}
+
 struct TimelineVariant {
   const char* name;
   int n, threads;
@@ -200,9 +234,28 @@ hipError_t launch_timeline(const void* in, void* out, const void* tw, int64_t ba
   return hipGetLastError();
 }
 
+template <class S>
+hipError_t launch_timeline_wx(const void* in, void* out, const void* tw, int64_t batch, bool inv,
+                              uint64_t* stamps, hipStream_t s) {
+  const dim3 grid((unsigned)batch), block(S::THREADS);
+  const c32* ip = static_cast<const c32*>(in);
+  c32* op = static_cast<c32*>(out);
+  const c32* twp = static_cast<const c32*>(tw);
+  if (inv)
+    k_stockham_wx_timeline<S, true><<<grid, block, 0, s>>>(ip, op, twp, stamps);
+  else
+    k_stockham_wx_timeline<S, false><<<grid, block, 0, s>>>(ip, op, twp, stamps);
+  return hipGetLastError();
+}
+
 // The shapes of the N = 4096 variants of the library with one transform
-// per workgroup (names as fft_variant_describe gives them).
+// per workgroup (names as fft_variant_describe gives them); the first is
+// the tuned shape at 256 rows.
 const TimelineVariant kTimeline[] = {
+    {"n4096_e16_b1_px_r8.8.8.8_pt_wm2", 4096, 256,
+     &launch_timeline_wx<WaveExchange<PairedTwiddles<ShapeX<1, 2, 1, 4096, 16, 1, -1, 8, 8, 8, 8>>, 1, 2>>},
+    {"n4096_e8_b1_px_r8.8.8.8_pt_wx1", 4096, 512,
+     &launch_timeline_wx<WaveExchange<PairedTwiddles<ShapeX<1, 2, 1, 4096, 8, 1, -1, 8, 8, 8, 8>>, 1>>},
     {"n4096_e8_b1_p4_r8.8.8.8_pt", 4096, 512,
      &launch_timeline<PairedTwiddles<Shape<4096, 8, 1, 4, 8, 8, 8, 8>>>},
     {"n4096_e16_b1_px_r16.16.16_db_pt_tall", 4096, 256,
