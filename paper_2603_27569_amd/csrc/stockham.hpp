@@ -140,6 +140,20 @@ struct Dft {
   }
 };
 
+// -------------------------------------------------------------- LDS poison
+// Debug builds (STOCKFFT_LDS_POISON defined) fill each exchange buffer with
+// NaNs before the first exchange and overwrite every slot with a NaN as soon
+// as it has been read.  A read that a missing barrier lets run before its
+// write then returns a NaN, and so does a slot whose next write a missing
+// barrier lets run before its last read (the reader's poison lands on the new
+// value): either way the transform's output turns NaN.
+#ifdef STOCKFFT_LDS_POISON
+constexpr bool kLdsPoison = true;
+#else
+constexpr bool kLdsPoison = false;
+#endif
+__device__ __forceinline__ c32 lds_poison() { return c32{__builtin_nanf(""), __builtin_nanf("")}; }
+
 // ------------------------------------------------------------- plan shape
 
 template <int... Rs>
@@ -513,18 +527,29 @@ __device__ __forceinline__ void exchange(c32 (&a)[S::E], c32* lds, int t) {
     }
     __syncthreads();
     if constexpr (PR) {
+      const auto at = [&](int m) {
+        return S::pidx(read_position<S, p + 1>(t, 0), read_position<S, p + 1>(0, m) - h * S::CHUNK);
+      };
 #pragma unroll
-      for (int m = h * MPC; m < (h + 1) * MPC; ++m)
-        nxt[m] = lds[S::pidx(read_position<S, p + 1>(t, 0), read_position<S, p + 1>(0, m) - h * S::CHUNK)];
+      for (int m = h * MPC; m < (h + 1) * MPC; ++m) nxt[m] = lds[at(m)];
+      if constexpr (kLdsPoison)
+#pragma unroll
+        for (int m = h * MPC; m < (h + 1) * MPC; ++m) lds[at(m)] = lds_poison();
     } else if constexpr (S::PADLOG < 0 && S::T % 128 == 0 && S::CHUNK % 128 == 0) {
       // The swizzle leaves bits 7 and up alone, so the read positions
       // t + m T stay a constant stride apart after it.
       const int base = S::pidx(t);
 #pragma unroll
       for (int m = h * MPC; m < (h + 1) * MPC; ++m) nxt[m] = lds[base + m * S::T - h * S::CHUNK];
+      if constexpr (kLdsPoison)
+#pragma unroll
+        for (int m = h * MPC; m < (h + 1) * MPC; ++m) lds[base + m * S::T - h * S::CHUNK] = lds_poison();
     } else {
 #pragma unroll
       for (int m = h * MPC; m < (h + 1) * MPC; ++m) nxt[m] = lds[S::pidx(t, m * S::T - h * S::CHUNK)];
+      if constexpr (kLdsPoison)
+#pragma unroll
+        for (int m = h * MPC; m < (h + 1) * MPC; ++m) lds[S::pidx(t, m * S::T - h * S::CHUNK)] = lds_poison();
     }
   }
 #pragma unroll
@@ -549,6 +574,13 @@ struct NoProbe {
 template <class S, int p, bool INV, class Pr>
 __device__ __forceinline__ void run_passes_from(c32 (&a)[S::E], c32 (&w)[S::TW_REGS], c32* lds,
                                                 const c32* tw, int t, Pr* pr) {
+  if constexpr (kLdsPoison && p == 0 && S::P > 1) {
+    // The transform's whole exchange buffer (both halves when double
+    // buffered) starts as NaNs.
+#pragma unroll 1
+    for (int i = t; i < S::LDS_ELEMS; i += S::T) lds[i] = lds_poison();
+    __syncthreads();
+  }
   pass_compute<S, p, INV>(a, w, tw, t);
   if constexpr (Pr::on) pr->mark(2 * p + 1);
   if constexpr (p + 1 < S::P) {

@@ -267,6 +267,11 @@ __device__ __forceinline__ void wx_dfts(WxRegs<S>& R) {
 template <class S, bool INV, class Pr>
 __device__ __forceinline__ void wx_passes(WxRegs<S>& R, const WxLane<S>& L, c32* lds, Pr* pr) {
   constexpr int G = S::WX, M = S::WXM;
+  if constexpr (kLdsPoison) {  // debug builds: the buffer starts as NaNs
+#pragma unroll 1
+    for (int i = threadIdx.x; i < S::LDS_ELEMS; i += S::THREADS) lds[i] = lds_poison();
+    __syncthreads();
+  }
   // Pass 0, in-wave exchange.
   wx_dfts<S, INV>(R);
   if constexpr (Pr::on) pr->mark(1);
@@ -303,6 +308,9 @@ __device__ __forceinline__ void wx_passes(WxRegs<S>& R, const WxLane<S>& L, c32*
       const int s0 = wx_slot<M>(base), s1 = wx_slot<M>(base + 512);
 #pragma unroll
       for (int r = 0; r < 8; ++r) R.a[u][s][r] = lds[((r & 1) ? s1 - 512 : s0) + 512 * r];
+      if constexpr (kLdsPoison)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) lds[((r & 1) ? s1 - 512 : s0) + 512 * r] = lds_poison();
     }
   if constexpr (Pr::on) pr->mark(4);
   // Pass 2 (Ns = 64), in-wave exchange.

@@ -38,6 +38,17 @@ def test_library_exports_every_declared_symbol():
     assert set(names) <= exported
 
 
+def test_lds_poison_debug_library_exports_the_same_abi():
+    """libstockfft_poison.so (the transform library built with
+    STOCKFFT_LDS_POISON, for the tests only) exports the header's entry
+    points, like the product library."""
+    path = os.path.join(os.path.dirname(_lib.LIB_PATH), "libstockfft_poison.so")
+    out = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True,
+                         text=True).stdout
+    exported = set(re.findall(r" T (fft_[a-z0-9_]+)$", out, flags=re.M))
+    assert set(_declared()) <= exported
+
+
 def test_status_strings_and_version():
     for code in range(13):
         assert sf.fft_status_string(code)
