@@ -404,9 +404,9 @@ const BuiltinEntry kBuiltinFused[] = {
     {4096, 1, 64, "n4096_e8_b1_px_r8.8.8.8_pt"},
     {4096, 65, 384, "n4096_e8_b1_px_r8.8.8.8_pt"},
     {4096, 385, 768, "n4096_e16_b1_p5_r16.16.16_pt"},
-    {4096, 769, 1536, "n4096_e16_b1_px_r16.16.16_pt"},
+    {4096, 769, 1536, "n4096_e16_b1_px_r16.16.16_db_pt_tall_st2d1"},
     {4096, 1537, 4096, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
-    {4096, 4097, INT64_MAX, "n4096_e16_b1_p5_r16.16.16_pt"},
+    {4096, 4097, INT64_MAX, "n4096_e16_b1_px_r16.16.16_db_pt_tall_st2d1"},
     {8192, 1, 64, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
     {8192, 65, 384, "n8192_e8_b1_p4_r8.8.8.8.2_pt"},
     {8192, 385, 768, "n8192_e16_b1_p4_r16.16.16.2_pt"},
@@ -1165,13 +1165,14 @@ static std::string describe_single(const SingleVariant& v) {
                 "\"passes\":%d,\"radices\":%s,\"exchange_rounds\":%d,\"threads\":%d,"
                 "\"lds_bytes\":%d,\"twiddle_entries\":%d,\"barriers\":%d,"
                 "\"double_buffered\":%s,\"twiddle_schedule\":%d,\"paired_twiddles\":%s,\"paired_lanes\":%s,"
-                "\"fused_kernels\":%s,\"streamed\":%d,\"wave_exchange\":%d,\"wave_members\":%d}",
+                "\"fused_kernels\":%s,\"fused_kernel\":%s,\"streamed\":%d,\"wave_exchange\":%d,\"wave_members\":%d}",
                 v.name, v.n, v.e, v.t, v.tpb, v.padlog,
                 v.padlog > 0 ? "pad" : v.padlog < 0 ? "xor" : "none", v.npass, radices_json(v).c_str(),
                 v.chunks, v.threads, v.lds_bytes, v.tw_elems, barriers_of(v),
                 v.double_buffered ? "true" : "false", v.twiddle_schedule,
                 v.paired_twiddles ? "true" : "false", v.paired_lanes ? "true" : "false",
-                v.fused && v.filter ? "true" : "false", v.streamed, v.wave_exchange, v.wave_members);
+                v.fused && v.filter ? "true" : "false", v.fused ? "true" : "false", v.streamed,
+                v.wave_exchange, v.wave_members);
   return buf;
 }
 

@@ -402,6 +402,72 @@ __device__ __forceinline__ float wave_group_sum(float v) {
   return v;
 }
 
+// The loss total of the fused kernels: the last workgroup to finish adds all
+// rows in a fixed order (bitwise reproducible), reading them with
+// device-scope atomic loads as they were published, so no cache write-back is
+// needed.  Every workgroup of the launch calls it once, after publishing its
+// rows; gi is its index among the groups_all workgroups that count, scratch
+// is LDS for THREADS floats, free on entry.
+template <class S>
+__device__ __forceinline__ void fused_loss_total(float* scratch, int& is_last, float* total_out,
+                                                 unsigned* counters, const float* row_loss_all,
+                                                 int64_t rows_all, unsigned groups_all, unsigned gi) {
+  const int tid = threadIdx.x;
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this lane's publication has completed
+  __syncthreads();  // ... for every lane; and the LDS is free
+  if (tid == 0) {
+    const unsigned grp = gi % kTotalGroups;
+    const unsigned in_grp = groups_all / kTotalGroups + (grp < groups_all % kTotalGroups ? 1u : 0u);
+    const unsigned ngrp = groups_all < kTotalGroups ? groups_all : kTotalGroups;
+    unsigned* c1 = counters + grp * 64;
+    unsigned* c2 = counters + kTotalGroups * 64;
+    int last = 0;
+    if (atomicAdd(c1, 1u) == in_grp - 1u) {
+      atomicExch(c1, 0u);
+      if (atomicAdd(c2, 1u) == ngrp - 1u) {
+        atomicExch(c2, 0u);
+        last = 1;
+      }
+    }
+    is_last = last;
+  }
+  __syncthreads();
+  if (is_last) {
+    // Summation order, whatever the workgroup size: 1024 lanes, lane v adds
+    // rows v, v + 1024, ... in turn, then a halving tree (lane v adds lane
+    // v + h for h = 512, 256, ..., 1).  Thread tid plays lanes tid + j THREADS.
+    static_assert(1024 % S::THREADS == 0 && S::THREADS % 64 == 0, "lane mapping");
+    static_assert(S::TPB * S::LDS_ELEMS * sizeof(c32) >= S::THREADS * sizeof(float), "tree");
+    constexpr int V = 1024 / S::THREADS;
+    float v[V];
+#pragma unroll
+    for (int j = 0; j < V; ++j) {
+      v[j] = 0.f;
+      for (int64_t i = tid + j * S::THREADS; i < rows_all; i += 1024)
+        v[j] += __hip_atomic_load(row_loss_all + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int h = V / 2; h > 0; h >>= 1)  // tree steps h * THREADS, inside a thread
+#pragma unroll
+      for (int j = 0; j < h; ++j) v[j] += v[j + h];
+    float part = v[0];
+    if constexpr (S::THREADS > 64) {  // tree steps THREADS / 2 .. 64, across waves
+      float* f = scratch;
+      f[tid] = part;
+      __syncthreads();
+#pragma unroll
+      for (int h = S::THREADS / 2; h >= 64; h >>= 1) {
+        if (tid < h) f[tid] += f[tid + h];
+        __syncthreads();
+      }
+      part = f[tid & 63];
+    }
+#pragma unroll
+    for (int h = 32; h > 0; h >>= 1) part += __shfl_xor(part, h, 64);  // steps 32 .. 1
+    if (tid == 0) total_out[0] = part;
+  }
+}
+
 // -------------------------------------------------- fused forward/adjoint
 // x -> y = F x -> (row loss sum w^2 |y|^2, g = 2 w^2 y * scale) -> F^H g.
 // Reads x once and writes the gradient once: 16 N bytes per row against the
@@ -465,65 +531,9 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_spectral_energy(
     run_passes<S, true>(a, lds, tw, t);
     buffer_store_row<S>(a, Buf(grad + row0 * S::N), slot * S::N, t, live);
   }
-  if (total_out != nullptr) {  // uniform across the launch
-    // The loss total: the last workgroup to finish adds all rows in a fixed
-    // order (bitwise reproducible), reading them with device-scope atomic
-    // loads as they were published, so no cache write-back is needed.
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this lane's publication has completed
-    __syncthreads();  // ... for every lane; and the LDS is free
-    if (tid == 0) {
-      const unsigned gi = gbase + blockIdx.x;
-      const unsigned grp = gi % kTotalGroups;
-      const unsigned in_grp = groups_all / kTotalGroups + (grp < groups_all % kTotalGroups ? 1u : 0u);
-      const unsigned ngrp = groups_all < kTotalGroups ? groups_all : kTotalGroups;
-      unsigned* c1 = counters + grp * 64;
-      unsigned* c2 = counters + kTotalGroups * 64;
-      int last = 0;
-      if (atomicAdd(c1, 1u) == in_grp - 1u) {
-        atomicExch(c1, 0u);
-        if (atomicAdd(c2, 1u) == ngrp - 1u) {
-          atomicExch(c2, 0u);
-          last = 1;
-        }
-      }
-      is_last = last;
-    }
-    __syncthreads();
-    if (is_last) {
-      // Summation order, whatever the workgroup size: 1024 lanes, lane v adds
-      // rows v, v + 1024, ... in turn, then a halving tree (lane v adds lane
-      // v + h for h = 512, 256, ..., 1).  Thread tid plays lanes tid + j THREADS.
-      static_assert(1024 % S::THREADS == 0 && S::THREADS % 64 == 0, "lane mapping");
-      static_assert(S::TPB * S::LDS_ELEMS * sizeof(c32) >= S::THREADS * sizeof(float), "tree");
-      constexpr int V = 1024 / S::THREADS;
-      float v[V];
-#pragma unroll
-      for (int j = 0; j < V; ++j) {
-        v[j] = 0.f;
-        for (int64_t i = tid + j * S::THREADS; i < rows_all; i += 1024)
-          v[j] += __hip_atomic_load(row_loss_all + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-#pragma unroll
-      for (int h = V / 2; h > 0; h >>= 1)  // tree steps h * THREADS, inside a thread
-#pragma unroll
-        for (int j = 0; j < h; ++j) v[j] += v[j + h];
-      float part = v[0];
-      if constexpr (S::THREADS > 64) {  // tree steps THREADS / 2 .. 64, across waves
-        float* f = reinterpret_cast<float*>(lds_all);
-        f[tid] = part;
-        __syncthreads();
-#pragma unroll
-        for (int h = S::THREADS / 2; h >= 64; h >>= 1) {
-          if (tid < h) f[tid] += f[tid + h];
-          __syncthreads();
-        }
-        part = f[tid & 63];
-      }
-#pragma unroll
-      for (int h = 32; h > 0; h >>= 1) part += __shfl_xor(part, h, 64);  // steps 32 .. 1
-      if (tid == 0) total_out[0] = part;
-    }
-  }
+  if (total_out != nullptr)  // uniform across the launch
+    fused_loss_total<S>(reinterpret_cast<float*>(lds_all), is_last, total_out, counters, row_loss_all,
+                        rows_all, groups_all, gbase + blockIdx.x);
 }
 
 template <class S>
@@ -541,6 +551,117 @@ hipError_t launch_spectral_energy(const void* x, const float* w, const float* sc
         static_cast<const c32*>(tw), batch - r0, total, counters, row_loss, batch,
         (unsigned)groups, (unsigned)g0);
   }
+  return hipGetLastError();
+}
+
+// Persistent form of the fused kernel (Streamed shapes): G = k x CUs
+// workgroups loop over the rows (row = blockIdx.x + i G) with the next D
+// rows' loads in flight during the current row's forward passes, weight and
+// adjoint passes, so one row's arithmetic overlaps other rows' HBM traffic
+// where a workgroup per row runs every row's loads, arithmetic and stores in
+// lockstep.  The twiddles and the squared weights of the lane's positions
+// are loaded once per workgroup.  Same outputs as k_spectral_energy.
+template <class S>
+__global__ __launch_bounds__(S::THREADS, S::WPE) void k_spectral_energy_stream(
+    const c32* x, const float* __restrict__ w, const float* __restrict__ scale, c32* grad,
+    float* row_loss, const c32* tw, int64_t rows, int64_t stride, float* total_out,
+    unsigned* counters) {
+  static_assert(round_trip_layout<S>(), "the adjoint runs on the forward's output registers");
+  constexpr int D = S::STREAM_DEPTH;
+  constexpr int NB = D + 1;
+  static_assert(D * S::E + S::E <= 63, "in-flight accesses exceed the wave's memory counter");
+  __shared__ alignas(16) c32 lds[S::LDS_ELEMS];
+  __shared__ float red[(S::THREADS + 63) / 64];
+  __shared__ int is_last;
+  const int t = threadIdx.x;
+  u32x2 buf[NB][S::E];
+  const int64_t row0 = blockIdx.x;  // the grid never exceeds rows
+#pragma unroll
+  for (int j = 0; j < D; ++j)
+    if (row0 + j * stride < rows) stream_load<S, IoF32>(buf[j], Buf(x + (row0 + j * stride) * S::N), t);
+  c32 tws[S::TW_REGS];
+  preload_twiddles<S>(tws, tw, t);
+  float w2[S::E];
+  {
+    const Buf wb(w);
+#pragma unroll
+    for (int m = 0; m < S::E; ++m) {
+      const float wq = __uint_as_float(wb.ld32(4 * t, 4 * m * S::T));
+      w2[m] = wq * wq;
+    }
+  }
+  // Wait for the twiddles and weights here (the rows loaded before them are
+  // then in too), so that the loop's waits need not count them.
+#pragma unroll
+  for (int i = 0; i < S::TW_REGS; ++i) asm volatile("" ::"v"(tws[i].x), "v"(tws[i].y));
+#pragma unroll
+  for (int m = 0; m < S::E; ++m) asm volatile("" ::"v"(w2[m]));
+  const float sc = scale ? 2.0f * scale[0] : 2.0f;
+  bool done = false;
+  for (int64_t row = row0; !done; row += NB * stride) {
+    // Unrolled NB times, so every buffer index is a constant and no loaded
+    // register is copied (a copy would wait for its load).
+#pragma unroll
+    for (int s = 0; s < NB; ++s) {
+      const int64_t r = row + s * stride;
+      if (r >= rows) {  // uniform
+        done = true;
+        break;
+      }
+      const int64_t ahead = r + D * stride;
+      if (ahead < rows) stream_load<S, IoF32>(buf[(s + D) % NB], Buf(x + ahead * S::N), t);
+      c32 a[S::E];
+#pragma unroll
+      for (int m = 0; m < S::E; ++m) a[m] = IoF32::load(buf[s][m]);
+      run_passes_preloaded<S, false>(a, tws, lds, tw, t);
+      float acc = 0.f;
+#pragma unroll
+      for (int m = 0; m < S::E; ++m) {
+        const c32 y = a[m];
+        acc += w2[m] * (y.x * y.x + y.y * y.y);
+        const float g = sc * w2[m];
+        a[m] = c32{g * y.x, g * y.y};
+      }
+      acc = wave_group_sum<S>(acc);
+      if constexpr (S::T > 64) {
+        if ((t & 63) == 0) red[t >> 6] = acc;
+      }
+      __syncthreads();  // forward passes done with LDS; wave partials visible
+      if (t == 0) {
+        float total = acc;
+        if constexpr (S::T > 64) {
+          total = 0.f;
+#pragma unroll
+          for (int i = 0; i < S::T / 64; ++i) total += red[i];
+        }
+        if (total_out != nullptr)
+          atomicExch(&row_loss[r], total);  // published where every XCD sees it
+        else
+          row_loss[r] = total;
+      }
+      if (grad != nullptr) {  // uniform across the launch
+        run_passes_preloaded<S, true>(a, tws, lds, tw, t);
+        const Buf o(grad + r * S::N);
+#pragma unroll
+        for (int m = 0; m < S::E; ++m) o.st64<kNT>(IoF32::store(a[m]), 8 * t, 8 * m * S::T);
+      }
+      __syncthreads();  // this row's exchange and partial reads are done before the next row's writes
+    }
+  }
+  if (total_out != nullptr)  // uniform across the launch
+    fused_loss_total<S>(reinterpret_cast<float*>(lds), is_last, total_out, counters, row_loss, rows,
+                        gridDim.x, blockIdx.x);
+}
+
+template <class S>
+hipError_t launch_spectral_energy_stream(const void* x, const float* w, const float* scale, void* grad,
+                                         float* row_loss, float* total, unsigned* counters,
+                                         const void* tw, int64_t batch, hipStream_t s) {
+  int64_t g = (int64_t)device_cus() * streamed<S>::value;
+  if (g > batch) g = batch;
+  k_spectral_energy_stream<S><<<dim3((unsigned)g), dim3(S::THREADS), 0, s>>>(
+      static_cast<const c32*>(x), w, scale, static_cast<c32*>(grad), row_loss,
+      static_cast<const c32*>(tw), batch, g, total, counters);
   return hipGetLastError();
 }
 

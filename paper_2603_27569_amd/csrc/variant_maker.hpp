@@ -37,10 +37,12 @@ SingleVariant make_variant(const char* name) {
     v.kernel = reinterpret_cast<const void*>(&k_stockham_wx<S, false, IoF32>);
     return v;
   } else if constexpr (streamed<S>::value > 0) {
-    // Persistent shapes run the plain transform only (either storage).
+    // Persistent shapes run the plain transform (either storage) and the
+    // fused forward -> weight -> adjoint kernel.
     v.launch = &launch_stream<S, IoF32>;
     v.launch_f16 = &launch_stream<S, IoF16>;
     v.launch_bf16 = &launch_stream<S, IoBF16>;
+    v.fused = &launch_spectral_energy_stream<S>;
     v.kernel = reinterpret_cast<const void*>(&k_stockham_stream<S, false, IoF32>);
     return v;
   } else {

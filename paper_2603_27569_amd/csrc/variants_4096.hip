@@ -61,6 +61,13 @@ STOCKFFT_VARIANT_GROUP(variants_4096,
       "n4096_e8_b1_p4_r8.8.8.8_pt_tall_st1d3"),
   make_variant<Streamed<PairedTwiddles<ShapeX<1, 2, 1, 4096, 8, 1, 4, 8, 8, 8, 8>>, 2, 2>>(
       "n4096_e8_b1_p4_r8.8.8.8_pt_tall_st2d2"),
+  // One persistent workgroup per CU, one row ahead: at 257-1024 rows each
+  // loops over two to four rows, so the fused kernel's second transform
+  // overlaps the next row's loads.
+  make_variant<Streamed<DoubleBuffered<PairedTwiddles<ShapeX<1, 2, 1, 4096, 16, 1, -1, 16, 16, 16>>>, 1, 1>>(
+      "n4096_e16_b1_px_r16.16.16_db_pt_tall_st1d1"),
+  make_variant<Streamed<PairedTwiddles<ShapeX<1, 2, 1, 4096, 8, 1, 4, 8, 8, 8, 8>>, 1, 1>>(
+      "n4096_e8_b1_p4_r8.8.8.8_pt_tall_st1d1"),
   // In-wave exchanges after passes 0 and 2 (8 x 8 transposes by cross-lane
   // moves), the LDS only between passes 1 and 2: one barrier per transform.
   // _wx1: one group per lane (8-byte accesses in 64-byte runs); _wx2: two

@@ -114,9 +114,10 @@ def _pick(times, retime):
 
 
 def fused_candidates(n):
-    """Single-pass variants of length n that have the two fused kernels."""
+    """Single-pass variants of length n that have the fused forward -> weight ->
+    adjoint kernel."""
     return [v["name"] for v in variants()
-            if v["n"] == n and v["kind"] == "single" and v["fused_kernels"]]
+            if v["n"] == n and v["kind"] == "single" and v["fused_kernel"]]
 
 
 def candidates(n):

@@ -70,7 +70,7 @@ def test_streamed_variant_many_rows_per_workgroup(v, inverse):
     xt = _gpu(x)
     sf.fft(xt, inverse=inverse, out=xt, algorithm=sf.FFT_ALGO_SINGLE_PASS, variant=v["name"])
     assert _check(_host(xt), x, inverse, ref=ref) < 2e-6
-    assert not v["fused_kernels"]
+    assert v["fused_kernel"] and not v["fused_kernels"]  # no matched filter
 
 
 @pytest.mark.parametrize("v", FOUR, ids=[v["name"] for v in FOUR])
@@ -279,7 +279,7 @@ def test_spectral_energy_fused_matches_oracle():
             assert abs(got - fd) <= 1e-4 * np.max(np.abs(ref_grad[b])), (b, i, comp)
 
 
-@pytest.mark.parametrize("n,batch", [(1024, 2000), (4096, 700), (16384, 600)])
+@pytest.mark.parametrize("n,batch", [(1024, 2000), (4096, 1200), (16384, 600)])
 def test_spectral_energy_takes_its_own_tuned_shape(n, batch):
     # The fused kernel runs two transforms per load and has a tuned table of
     # its own (here a choice that differs from the plain transform's); its
@@ -296,6 +296,40 @@ def test_spectral_energy_takes_its_own_tuned_shape(n, batch):
     rows = _host(rows).astype(np.float64)
     assert np.max(np.abs(rows - ref_rows) / ref_rows) <= 1e-5
     assert abs(float(_host(total)[0]) - ref_rows.sum()) / ref_rows.sum() <= 1e-5
+    ok, worst, ab = metrics.grad_gate(_host(grad), ref_grad)
+    assert ok, (worst, ab)
+
+
+FUSED = [v for v in SINGLE if v["fused_kernel"]]
+
+
+@pytest.mark.parametrize("v", FUSED, ids=[v["name"] for v in FUSED])
+def test_spectral_energy_every_fused_variant(v):
+    """Every shape with the fused forward -> weight -> adjoint kernel, named
+    explicitly: per-row loss, per-row gradient gate and the fixed-order loss
+    total against the oracle.  Persistent shapes get two full rounds of rows
+    and a ragged third (each workgroup loops and prefetches)."""
+    n = v["n"]
+    if v["streamed"]:
+        batch = 2 * torch.cuda.get_device_properties(0).multi_processor_count * v["streamed"] + 37
+    else:
+        batch = 3 * v["transforms_per_workgroup"] + 1
+    x, w = workloads.spectral_energy_inputs(n=n, batch=batch, seed=n + batch, wseed=n + 1)
+    xt, wt = _gpu(x), _gpu(w)
+    p = sf.Plan(n, batch, sf.FFT_FORWARD, sf.FFT_ALGO_SINGLE_PASS, v["name"])
+    assert p.describe()["fused_variant"] == v["name"]
+    rows = torch.empty(batch, device=DEV)
+    total = torch.empty(1, device=DEV)
+    grad = torch.empty_like(xt)
+    cs = torch.cuda.current_stream().cuda_stream
+    sf.fft_exec_spectral_energy(p.handle, xt.data_ptr(), wt.data_ptr(), 0, grad.data_ptr(),
+                                rows.data_ptr(), total.data_ptr(), cs)
+    torch.cuda.synchronize()
+    p.close()
+    ref_rows, ref_grad = oracle.spectral_energy(x, w)
+    got_rows = _host(rows).astype(np.float64)
+    assert np.max(np.abs(got_rows - ref_rows) / ref_rows) <= 1e-5
+    assert float(_host(total)[0]) == _fixed_order_total(_host(rows))
     ok, worst, ab = metrics.grad_gate(_host(grad), ref_grad)
     assert ok, (worst, ab)
 

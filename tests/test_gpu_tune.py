@@ -56,7 +56,7 @@ def test_fused_tuner_restricted_search():
     assert [e["n"] for e in entries] == [1024]
     e = entries[0]
     names = {v["name"] for v in sf.variants()
-             if v["kind"] == "single" and v["n"] == 1024 and v["fused_kernels"]}
+             if v["kind"] == "single" and v["n"] == 1024 and v["fused_kernel"]}
     assert set(e["candidates"]) == names
     assert e["variant"] in names and e["us"] == min(e["candidates"].values())
 
