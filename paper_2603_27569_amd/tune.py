@@ -34,6 +34,9 @@ Usage: python -m paper_2603_27569_amd.tune [--out tune_gfx950.json] [--quick]
        python -m paper_2603_27569_amd.tune --run-variants N BATCH [--iters K]
          (no search: runs every variant of length N, K launches each, so that
          an external profiler can attribute counters to each variant)
+       python -m paper_2603_27569_amd.tune --merge-counters N BATCH CSV... [--iters K] --out FILE
+         (attaches the counters of such a run under rocprofv3 --pmc, one CSV
+         per counter pass, to FILE's entries for N at BATCH, per candidate)
 """
 import argparse
 import json
@@ -376,14 +379,82 @@ def run_variants(n, batch, iters=10, log=print):
         log(f"ran {v['name']} x{iters}")
 
 
+def variant_dispatch_counters(csv_paths, n, iters):
+    """Per-variant counter medians from rocprofv3 counter-collection CSV files
+    (`--pmc ... --output-format csv`) of a `--run-variants n BATCH --iters
+    iters` run, one file per counter pass.  run_variants launches each variant
+    of length n `iters` times in variants() order (a four-step variant two
+    kernels per launch), so the library's own dispatches, taken in dispatch
+    order, split into consecutive runs that map one to one onto the variants;
+    every other dispatch (the calibration copy, fills and copies of plan
+    creation) is left out.  Returns {variant: {counter: median}}, with
+    `<counter>_per_wave` added for SQ_ counters when SQ_WAVES was collected."""
+    import csv
+    names = [(v["name"], 1 if v["kind"] == "single" else 2) for v in variants() if v["n"] == n]
+    out = {name: {} for name, _ in names}
+    for path in csv_paths:
+        disp = {}
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                if "stockfft::" not in r["Kernel_Name"]:
+                    continue
+                d = disp.setdefault(int(r["Dispatch_Id"]), {"kernel": r["Kernel_Name"], "c": {}})
+                d["c"][r["Counter_Name"]] = float(r["Counter_Value"])
+        seq = [disp[k] for k in sorted(disp)]
+        need = sum(k for _, k in names) * iters
+        if len(seq) != need:
+            raise ValueError(f"{path}: {len(seq)} library dispatches, expected {need} "
+                             f"({len(names)} variants of length {n} x {iters} launches)")
+        pos = 0
+        for name, k in names:
+            run = seq[pos:pos + k * iters]
+            pos += k * iters
+            kinds = {d["kernel"] for d in run[:k]}
+            if any(d["kernel"] != run[i % k]["kernel"] for i, d in enumerate(run)) or len(kinds) != k:
+                raise ValueError(f"{path}: the dispatches of {name} are not one repeated launch")
+            for c in run[0]["c"]:
+                out[name][c] = statistics.median(sum(d["c"][c] for d in run[i:i + k])
+                                                 for i in range(0, len(run), k))
+    for name, cs in out.items():
+        waves = cs.get("SQ_WAVES")
+        if waves:
+            for c in [c for c in cs if c.startswith("SQ_") and c != "SQ_WAVES"]:
+                cs[c + "_per_wave"] = round(cs[c] / waves, 2)
+    return out
+
+
+def merge_counters(doc, n, batch, counters):
+    """Attach per-candidate counters to the plain entries of length n whose
+    bucket holds `batch` (entry["counters"][variant])."""
+    hit = 0
+    for e in doc["entries"]:
+        if e["n"] == n and e["batch_min"] <= batch <= e["batch_max"]:
+            e["counters"] = {"batch": batch, "by_variant": counters}
+            hit += 1
+    if not hit:
+        raise ValueError(f"no tuned entry of length {n} holds batch {batch}")
+    return doc
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--out", default="tune_gfx950.json")
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--run-variants", nargs=2, type=int, metavar=("N", "BATCH"))
     ap.add_argument("--iters", type=int, default=10)
+    ap.add_argument("--merge-counters", nargs="+", metavar="N BATCH CSV",
+                    help="attach per-variant counter medians of a profiled --run-variants N BATCH "
+                         "run (rocprofv3 counter-collection CSV files) to the --out tune file")
     a = ap.parse_args(argv)
     log = lambda *x: print(*x, file=sys.stderr, flush=True)  # noqa: E731
+    if a.merge_counters:
+        n, batch, paths = int(a.merge_counters[0]), int(a.merge_counters[1]), a.merge_counters[2:]
+        with open(a.out) as f:
+            doc = json.load(f)
+        merge_counters(doc, n, batch, variant_dispatch_counters(paths, n, a.iters))
+        with open(a.out, "w") as f:
+            json.dump(doc, f, indent=1)
+        return 0
     if a.run_variants:
         run_variants(a.run_variants[0], a.run_variants[1], a.iters, log=log)
         return 0

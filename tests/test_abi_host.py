@@ -534,3 +534,47 @@ def test_reference_calls_reject_bad_arguments_before_any_device_call():
         codes["FFT_INVALID_ARGUMENT"]
     assert L.ref_timeline(b"n4096_e16_b1_px_r16.16.16_db", vp(64), vp(1 << 30), vp(64), 1, 2,
                           vp(64), None) == codes["FFT_INVALID_ARGUMENT"]
+
+
+def test_tuner_maps_profiled_dispatches_to_variants(tmp_path):
+    """tune --merge-counters: the library's dispatches of a profiled
+    --run-variants run, in dispatch order, map one to one onto the variants
+    of the length (other kernels -- the calibration copy, fills -- left out),
+    and each variant gets the median of its launches."""
+    from paper_2603_27569_amd import tune
+    n, iters = 2048, 3
+    vs = [(v["name"], 1 if v["kind"] == "single" else 2) for v in _variants() if v["n"] == n]
+    path = tmp_path / "p1_counter_collection.csv"
+    rows = ["Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value"]
+    d = 0
+
+    def emit(kernel, values):
+        nonlocal d
+        d += 1
+        for c, val in values.items():
+            rows.append(f'{d},"{kernel}",{c},{val}')
+
+    emit("at::copy_kernel", {"SQ_WAVES": 9, "SQ_INSTS_VALU": 1})
+    for i, (name, k) in enumerate(vs):
+        emit("__amd_rocclr_fillBuffer", {"SQ_WAVES": 1, "SQ_INSTS_VALU": 5})
+        for j in range(iters):
+            for part in range(k):
+                emit(f"void stockfft::k_stockham<{name}, {part}>(stockfft::c32 const*)",
+                     {"SQ_WAVES": 4, "SQ_INSTS_VALU": 100 * i + 10 * j + part})
+    path.write_text("\n".join(rows) + "\n")
+    got = tune.variant_dispatch_counters([str(path)], n, iters)
+    assert set(got) == {name for name, _ in vs}
+    for i, (name, k) in enumerate(vs):
+        # launches j = 0, 1, 2 sum their k kernels: median at j = 1
+        want = k * (100 * i + 10) + sum(range(k))
+        assert got[name]["SQ_INSTS_VALU"] == want
+        assert got[name]["SQ_WAVES"] == 4 * k
+        assert got[name]["SQ_INSTS_VALU_per_wave"] == round(want / (4 * k), 2)
+    doc = {"entries": [{"n": n, "batch_min": 65, "batch_max": 384}, {"n": n, "batch_min": 385,
+                                                                       "batch_max": 768}]}
+    tune.merge_counters(doc, n, 256, got)
+    assert doc["entries"][0]["counters"]["by_variant"] == got and "counters" not in doc["entries"][1]
+    # a run that does not match the variant list is refused
+    path.write_text("\n".join(rows[:-3]) + "\n")
+    with pytest.raises(ValueError):
+        tune.variant_dispatch_counters([str(path)], n, iters)
