@@ -29,9 +29,10 @@ SingleVariant make_variant(const char* name) {
   v.wave_exchange = wave_exchange<S>::value;
   v.wave_members = wave_members<S>::value;
   if constexpr (wave_exchange<S>::value > 0) {
-    // Plain transform only (either storage): the fused kernels run the
-    // all-LDS schedule.
+    // The plain transform (either storage) and both fused kernels.
     v.launch = &launch_wx<S, IoF32>;
+    v.fused = &launch_spectral_energy_wx<S>;
+    v.filter = &launch_matched_filter_wx<S>;
     v.launch_f16 = &launch_wx<S, IoF16>;
     v.launch_bf16 = &launch_wx<S, IoBF16>;
     v.kernel = reinterpret_cast<const void*>(&k_stockham_wx<S, false, IoF32>);

@@ -34,7 +34,7 @@
 // where an LDS exchange costs two memory instructions per 64-bit value.
 #pragma once
 
-#include "stockham.hpp"
+#include "kernels.hpp"
 
 namespace stockfft {
 
@@ -364,6 +364,130 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_stockham_wx(const void* 
   wx_load<S, IO>(R, L, in, tw, blockIdx.x);
   wx_passes<S, INV, NoProbe>(R, L, lds, nullptr);
   wx_store<S, IO>(R, L, out, blockIdx.x);
+}
+
+// The fused forward -> weight -> adjoint kernel (k_spectral_energy's outputs)
+// on the in-wave layout.  The forward's output register map (lane (h, m),
+// leg r at h + 64 m + 512 r) is the input register map of the adjoint, so
+// the adjoint runs on the registers in place; the weight of each value is
+// read at its output position.
+template <class S>
+__global__ __launch_bounds__(S::THREADS, S::WPE) void k_spectral_energy_wx(
+    const c32* x, const float* __restrict__ w, const float* __restrict__ scale, c32* grad,
+    float* row_loss, const c32* tw, float* total_out, unsigned* counters, float* row_loss_all,
+    int64_t rows_all, unsigned groups_all, unsigned gbase) {
+  constexpr int G = S::WX, M = S::WXM;
+  __shared__ alignas(16) c32 lds[S::LDS_ELEMS];
+  __shared__ float red[S::THREADS / 64];
+  __shared__ int is_last;
+  const int tid = threadIdx.x;
+  const int64_t row = blockIdx.x;  // one row per workgroup
+  const WxLane<S> L(tid);
+  WxRegs<S> R;
+  wx_load<S, IoF32>(R, L, x, tw, row);
+  wx_passes<S, false, NoProbe>(R, L, lds, nullptr);
+  const float sc = scale ? 2.0f * scale[0] : 2.0f;
+  float acc = 0.f;
+  {
+    const Buf wb(w);
+    const int voff = 4 * (L.g0 + 64 * L.m0);
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+#pragma unroll
+      for (int s = 0; s < M; ++s)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const float wq = __uint_as_float(wb.ld32(voff, 4 * (u + 64 * L.MS * s + 512 * r)));
+          const float w2 = wq * wq;
+          const c32 y = R.a[u][s][r];
+          acc += w2 * (y.x * y.x + y.y * y.y);
+          const float g = sc * w2;
+          R.a[u][s][r] = c32{g * y.x, g * y.y};
+        }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+  if ((tid & 63) == 0) red[tid >> 6] = acc;
+  __syncthreads();  // forward passes done with the LDS; wave partials visible
+  if (tid == 0) {
+    float total = 0.f;
+#pragma unroll
+    for (int i = 0; i < S::THREADS / 64; ++i) total += red[i];
+    if (total_out != nullptr)
+      atomicExch(&row_loss[row], total);  // published where every XCD sees it
+    else
+      row_loss[row] = total;
+  }
+  if (grad != nullptr) {  // uniform across the launch
+    wx_passes<S, true, NoProbe>(R, L, lds, nullptr);
+    wx_store<S, IoF32>(R, L, grad, row);
+  }
+  if (total_out != nullptr)  // uniform across the launch
+    fused_loss_total<S>(reinterpret_cast<float*>(lds), is_last, total_out, counters, row_loss_all,
+                        rows_all, groups_all, gbase + blockIdx.x);
+}
+
+template <class S>
+hipError_t launch_spectral_energy_wx(const void* x, const float* w, const float* scale, void* grad,
+                                     float* row_loss, float* total, unsigned* counters,
+                                     const void* tw, int64_t batch, hipStream_t s) {
+  const int64_t cap = max_groups_per_launch();
+  for (int64_t r0 = 0; r0 < batch; r0 += cap) {
+    const int64_t g = batch - r0 < cap ? batch - r0 : cap;
+    k_spectral_energy_wx<S><<<dim3((unsigned)g), dim3(S::THREADS), 0, s>>>(
+        static_cast<const c32*>(x) + r0 * 4096, w, scale,
+        grad ? static_cast<c32*>(grad) + r0 * 4096 : nullptr, row_loss + r0,
+        static_cast<const c32*>(tw), total, counters, row_loss, batch, (unsigned)batch,
+        (unsigned)r0);
+  }
+  return hipGetLastError();
+}
+
+// The fused matched filter (k_matched_filter's output, (1/N) F^H(conj(h) .*
+// F x)) on the in-wave layout: the filter spectrum is read at each value's
+// output position and the inverse runs on the registers in place.
+template <class S>
+__global__ __launch_bounds__(S::THREADS, S::WPE) void k_matched_filter_wx(const c32* x,
+                                                                   const c32* __restrict__ h,
+                                                                   c32* out, const c32* tw) {
+  constexpr int G = S::WX, M = S::WXM;
+  __shared__ alignas(16) c32 lds[S::LDS_ELEMS];
+  const int64_t row = blockIdx.x;  // one row per workgroup
+  const WxLane<S> L(threadIdx.x);
+  WxRegs<S> R;
+  wx_load<S, IoF32>(R, L, x, tw, row);
+  wx_passes<S, false, NoProbe>(R, L, lds, nullptr);
+  constexpr float inv_n = 1.0f / 4096.0f;  // a power of two: exact
+  {
+    const Buf hb(h);
+    const int voff = 8 * (L.g0 + 64 * L.m0);
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+#pragma unroll
+      for (int s = 0; s < M; ++s)
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          const u32x2 hw = hb.ld64(voff, 8 * (u + 64 * L.MS * s + 512 * r));
+          const c32 y = cmulc(R.a[u][s][r], c32{__uint_as_float(hw.x), __uint_as_float(hw.y)});
+          R.a[u][s][r] = c32{y.x * inv_n, y.y * inv_n};
+        }
+  }
+  __syncthreads();  // the forward's LDS reads are done before the inverse's writes
+  wx_passes<S, true, NoProbe>(R, L, lds, nullptr);
+  wx_store<S, IoF32>(R, L, out, row);
+}
+
+template <class S>
+hipError_t launch_matched_filter_wx(const void* x, const void* h, void* out, const void* tw,
+                                    int64_t batch, hipStream_t s) {
+  const int64_t cap = max_groups_per_launch();
+  for (int64_t r0 = 0; r0 < batch; r0 += cap) {
+    const int64_t g = batch - r0 < cap ? batch - r0 : cap;
+    k_matched_filter_wx<S><<<dim3((unsigned)g), dim3(S::THREADS), 0, s>>>(
+        static_cast<const c32*>(x) + r0 * 4096, static_cast<const c32*>(h),
+        static_cast<c32*>(out) + r0 * 4096, static_cast<const c32*>(tw));
+  }
+  return hipGetLastError();
 }
 
 template <class S, class IO>

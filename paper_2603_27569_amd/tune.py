@@ -116,6 +116,12 @@ def _pick(times, retime):
     return min(times, key=times.get)
 
 
+def filter_candidates(n):
+    """Single-pass variants of length n that have the fused matched filter."""
+    return [v["name"] for v in variants()
+            if v["n"] == n and v["kind"] == "single" and v["fused_kernels"]]
+
+
 def fused_candidates(n):
     """Single-pass variants of length n that have the fused forward -> weight ->
     adjoint kernel."""
@@ -183,7 +189,7 @@ def tune_filter(torch, dev, stream, sizes=SIZES, buckets=BUCKETS, iters=30, log=
             k = len(xs)
             times = {}
             cs = stream.cuda_stream
-            names = fused_candidates(n)
+            names = filter_candidates(n)
 
             def timed(name, factor=1):
                 p = Plan(n, b, FFT_FORWARD, FFT_ALGO_SINGLE_PASS, name)

@@ -256,7 +256,7 @@ def test_variant_inventory():
         c = v["exchange_rounds"]
         if v["wave_exchange"]:  # exchanges after passes 0 and 2 in registers: one LDS exchange
             assert v["n"] == 4096 and v["radices"] == [8, 8, 8, 8] and c == 1
-            assert v["barriers"] == 1 and not v["fused_kernels"]
+            assert v["barriers"] == 1 and v["fused_kernels"]
             assert v["wave_members"] in (1, 2)
             assert v["values_per_lane"] == 8 * v["wave_exchange"] * v["wave_members"]
         elif v["double_buffered"]:  # one barrier per exchange, whole-transform rounds
