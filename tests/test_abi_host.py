@@ -578,3 +578,14 @@ def test_tuner_maps_profiled_dispatches_to_variants(tmp_path):
     path.write_text("\n".join(rows[:-3]) + "\n")
     with pytest.raises(ValueError):
         tune.variant_dispatch_counters([str(path)], n, iters)
+
+
+def test_bench_names_compiled_variants():
+    """The shapes bench.py names in its exchange-tier comparison are compiled
+    variants of N = 4096 with the layouts the comparison's labels state."""
+    import bench
+    by = {v["name"]: v for v in _variants()}
+    for label, name in bench.EXCHANGE_TIERS:
+        v = by[name]
+        assert v["n"] == 4096 and v["radices"] == [8, 8, 8, 8], name
+        assert bool(v["wave_exchange"]) == label.startswith("in_wave"), name

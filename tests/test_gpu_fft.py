@@ -279,7 +279,7 @@ def test_spectral_energy_fused_matches_oracle():
             assert abs(got - fd) <= 1e-4 * np.max(np.abs(ref_grad[b])), (b, i, comp)
 
 
-@pytest.mark.parametrize("n,batch", [(1024, 2000), (4096, 1200), (16384, 600)])
+@pytest.mark.parametrize("n,batch", [(1024, 2000), (4096, 256), (4096, 512), (4096, 1200), (16384, 600)])
 def test_spectral_energy_takes_its_own_tuned_shape(n, batch):
     # The fused kernel runs two transforms per load and has a tuned table of
     # its own (here a choice that differs from the plain transform's); its
