@@ -50,6 +50,24 @@ def test_single_pass_variant_parity(v, inverse):
     assert worst < 2e-6  # a healthy FP32 Stockham sits near 1e-7
 
 
+WAVEX = [v for v in SINGLE if v["wave_exchange"]]
+
+
+@pytest.mark.parametrize("v", WAVEX, ids=[v["name"] for v in WAVEX])
+def test_in_wave_exchange_in_place_round_trip(v):
+    """The in-wave shapes in place (out == in): every lane has consumed its row
+    before the workgroup's one barrier and stores after it.  Forward, then
+    backward, both in place, and the result against the oracle at each step."""
+    n, batch = v["n"], 37
+    x = workloads.plain_normal(n, batch, seed=900 + v["values_per_lane"])
+    xt = _gpu(x)
+    sf.fft(xt, out=xt, algorithm=sf.FFT_ALGO_SINGLE_PASS, variant=v["name"])
+    y = _host(xt)
+    _check(y, x)
+    sf.fft(xt, inverse=True, out=xt, algorithm=sf.FFT_ALGO_SINGLE_PASS, variant=v["name"])
+    _check(_host(xt), y, inverse=True)
+
+
 STREAMED = [v for v in SINGLE if v["streamed"]]
 
 
