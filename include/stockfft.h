@@ -355,7 +355,15 @@ int fft_set_launch_limit(int64_t max_groups);
  * fft_variant_count: number of compiled kernel variants.
  * fft_variant_describe: JSON text for variant `index` into buf (cap bytes,
  *   NUL-terminated); returns FFT_INVALID_ARGUMENT for a bad index or a
- *   buffer that is too small.
+ *   buffer that is too small.  A single-pass variant states its shape
+ *   (values_per_lane, lanes_per_transform, transforms_per_workgroup,
+ *   radices, lds_layout, exchange_rounds, barriers, twiddle_schedule, ...),
+ *   whether it has the fused forward -> weight -> adjoint kernel
+ *   ("fused_kernel") and also the matched filter ("fused_kernels"), its
+ *   persistent workgroups per CU ("streamed", 0 for a workgroup per row)
+ *   and, for the in-wave exchange shapes at N = 4096, the groups and
+ *   members of a group per lane ("wave_exchange", "wave_members"; 0 for
+ *   shapes that exchange through the LDS only).
  * fft_variant_twiddles: the FP32 twiddle table of variant `index` as built
  *   for the device (interleaved re, im; forward direction), written into
  *   out[0 .. 2*count); *count receives the number of complex entries.
