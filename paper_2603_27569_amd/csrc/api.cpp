@@ -403,7 +403,7 @@ const BuiltinEntry kBuiltinFused[] = {
     {2048, 4097, INT64_MAX, "n2048_e16_b2_p4_r16.16.8_pt"},
     {4096, 1, 64, "n4096_e8_b1_px_r8.8.8.8_pt_wx1"},
     {4096, 65, 384, "n4096_e8_b1_px_r8.8.8.8_pt_wx1"},
-    {4096, 385, 768, "n4096_e16_b1_p5_r16.16.16_pt"},
+    {4096, 385, 768, "n4096_e8_b1_px_r8.8.8.8_pt_wx1"},
     {4096, 769, 1536, "n4096_e16_b1_px_r16.16.16_db_pt_tall_st2d1"},
     {4096, 1537, 4096, "n4096_e32_c2_b1_p4_r16.16.16_pt"},
     {4096, 4097, INT64_MAX, "n4096_e16_b1_px_r16.16.16_db_pt_tall_st2d1"},

@@ -402,70 +402,80 @@ __device__ __forceinline__ float wave_group_sum(float v) {
   return v;
 }
 
-// The loss total of the fused kernels: the last workgroup to finish adds all
-// rows in a fixed order (bitwise reproducible), reading them with
+// The loss total of the fused kernels: the last workgroup to count itself
+// adds all rows in a fixed order (bitwise reproducible), reading them with
 // device-scope atomic loads as they were published, so no cache write-back is
-// needed.  Every workgroup of the launch calls it once, after publishing its
-// rows; gi is its index among the groups_all workgroups that count, scratch
-// is LDS for THREADS floats, free on entry.
+// needed.  fused_loss_count: thread 0 of a workgroup whose row losses have
+// been published (and have completed) counts it; gi is its index among the
+// groups_all workgroups that count; returns whether it came last.
+__device__ __forceinline__ int fused_loss_count(unsigned* counters, unsigned groups_all, unsigned gi) {
+  const unsigned grp = gi % kTotalGroups;
+  const unsigned in_grp = groups_all / kTotalGroups + (grp < groups_all % kTotalGroups ? 1u : 0u);
+  const unsigned ngrp = groups_all < kTotalGroups ? groups_all : kTotalGroups;
+  unsigned* c1 = counters + grp * 64;
+  unsigned* c2 = counters + kTotalGroups * 64;
+  int last = 0;
+  if (atomicAdd(c1, 1u) == in_grp - 1u) {
+    atomicExch(c1, 0u);
+    if (atomicAdd(c2, 1u) == ngrp - 1u) {
+      atomicExch(c2, 0u);
+      last = 1;
+    }
+  }
+  return last;
+}
+
+// The sum itself, by every thread of the last workgroup; scratch is LDS for
+// THREADS floats, free on entry.
+template <class S>
+__device__ __forceinline__ void fused_loss_sum(float* scratch, float* total_out,
+                                               const float* row_loss_all, int64_t rows_all) {
+  const int tid = threadIdx.x;
+  // Summation order, whatever the workgroup size: 1024 lanes, lane v adds
+  // rows v, v + 1024, ... in turn, then a halving tree (lane v adds lane
+  // v + h for h = 512, 256, ..., 1).  Thread tid plays lanes tid + j THREADS.
+  static_assert(1024 % S::THREADS == 0 && S::THREADS % 64 == 0, "lane mapping");
+  static_assert(S::TPB * S::LDS_ELEMS * sizeof(c32) >= S::THREADS * sizeof(float), "tree");
+  constexpr int V = 1024 / S::THREADS;
+  float v[V];
+#pragma unroll
+  for (int j = 0; j < V; ++j) {
+    v[j] = 0.f;
+    for (int64_t i = tid + j * S::THREADS; i < rows_all; i += 1024)
+      v[j] += __hip_atomic_load(row_loss_all + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+#pragma unroll
+  for (int h = V / 2; h > 0; h >>= 1)  // tree steps h * THREADS, inside a thread
+#pragma unroll
+    for (int j = 0; j < h; ++j) v[j] += v[j + h];
+  float part = v[0];
+  if constexpr (S::THREADS > 64) {  // tree steps THREADS / 2 .. 64, across waves
+    float* f = scratch;
+    f[tid] = part;
+    __syncthreads();
+#pragma unroll
+    for (int h = S::THREADS / 2; h >= 64; h >>= 1) {
+      if (tid < h) f[tid] += f[tid + h];
+      __syncthreads();
+    }
+    part = f[tid & 63];
+  }
+#pragma unroll
+  for (int h = 32; h > 0; h >>= 1) part += __shfl_xor(part, h, 64);  // steps 32 .. 1
+  if (tid == 0) total_out[0] = part;
+}
+
+// Both steps after the workgroup's last store: every workgroup of the launch
+// calls it once, after publishing its rows.
 template <class S>
 __device__ __forceinline__ void fused_loss_total(float* scratch, int& is_last, float* total_out,
                                                  unsigned* counters, const float* row_loss_all,
                                                  int64_t rows_all, unsigned groups_all, unsigned gi) {
-  const int tid = threadIdx.x;
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");  // this lane's publication has completed
   __syncthreads();  // ... for every lane; and the LDS is free
-  if (tid == 0) {
-    const unsigned grp = gi % kTotalGroups;
-    const unsigned in_grp = groups_all / kTotalGroups + (grp < groups_all % kTotalGroups ? 1u : 0u);
-    const unsigned ngrp = groups_all < kTotalGroups ? groups_all : kTotalGroups;
-    unsigned* c1 = counters + grp * 64;
-    unsigned* c2 = counters + kTotalGroups * 64;
-    int last = 0;
-    if (atomicAdd(c1, 1u) == in_grp - 1u) {
-      atomicExch(c1, 0u);
-      if (atomicAdd(c2, 1u) == ngrp - 1u) {
-        atomicExch(c2, 0u);
-        last = 1;
-      }
-    }
-    is_last = last;
-  }
+  if (threadIdx.x == 0) is_last = fused_loss_count(counters, groups_all, gi);
   __syncthreads();
-  if (is_last) {
-    // Summation order, whatever the workgroup size: 1024 lanes, lane v adds
-    // rows v, v + 1024, ... in turn, then a halving tree (lane v adds lane
-    // v + h for h = 512, 256, ..., 1).  Thread tid plays lanes tid + j THREADS.
-    static_assert(1024 % S::THREADS == 0 && S::THREADS % 64 == 0, "lane mapping");
-    static_assert(S::TPB * S::LDS_ELEMS * sizeof(c32) >= S::THREADS * sizeof(float), "tree");
-    constexpr int V = 1024 / S::THREADS;
-    float v[V];
-#pragma unroll
-    for (int j = 0; j < V; ++j) {
-      v[j] = 0.f;
-      for (int64_t i = tid + j * S::THREADS; i < rows_all; i += 1024)
-        v[j] += __hip_atomic_load(row_loss_all + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-#pragma unroll
-    for (int h = V / 2; h > 0; h >>= 1)  // tree steps h * THREADS, inside a thread
-#pragma unroll
-      for (int j = 0; j < h; ++j) v[j] += v[j + h];
-    float part = v[0];
-    if constexpr (S::THREADS > 64) {  // tree steps THREADS / 2 .. 64, across waves
-      float* f = scratch;
-      f[tid] = part;
-      __syncthreads();
-#pragma unroll
-      for (int h = S::THREADS / 2; h >= 64; h >>= 1) {
-        if (tid < h) f[tid] += f[tid + h];
-        __syncthreads();
-      }
-      part = f[tid & 63];
-    }
-#pragma unroll
-    for (int h = 32; h > 0; h >>= 1) part += __shfl_xor(part, h, 64);  // steps 32 .. 1
-    if (tid == 0) total_out[0] = part;
-  }
+  if (is_last) fused_loss_sum<S>(scratch, total_out, row_loss_all, rows_all);
 }
 
 // -------------------------------------------------- fused forward/adjoint

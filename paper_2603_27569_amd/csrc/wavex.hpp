@@ -413,18 +413,26 @@ __global__ __launch_bounds__(S::THREADS, S::WPE) void k_spectral_energy_wx(
     float total = 0.f;
 #pragma unroll
     for (int i = 0; i < S::THREADS / 64; ++i) total += red[i];
-    if (total_out != nullptr)
-      atomicExch(&row_loss[row], total);  // published where every XCD sees it
-    else
+    if (total_out != nullptr) {
+      // Published where every XCD sees it, then the workgroup counts itself
+      // at once, so the counters' round trips overlap the adjoint instead of
+      // waiting behind the gradient stores; this wave has nothing else in
+      // flight here.
+      atomicExch(&row_loss[row], total);
+      asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+      is_last = fused_loss_count(counters, groups_all, gbase + blockIdx.x);
+    } else {
       row_loss[row] = total;
+    }
   }
   if (grad != nullptr) {  // uniform across the launch
     wx_passes<S, true, NoProbe>(R, L, lds, nullptr);
     wx_store<S, IoF32>(R, L, grad, row);
   }
-  if (total_out != nullptr)  // uniform across the launch
-    fused_loss_total<S>(reinterpret_cast<float*>(lds), is_last, total_out, counters, row_loss_all,
-                        rows_all, groups_all, gbase + blockIdx.x);
+  if (total_out != nullptr) {  // uniform across the launch
+    __syncthreads();  // is_last visible; the LDS free for the sum's tree
+    if (is_last) fused_loss_sum<S>(reinterpret_cast<float*>(lds), total_out, row_loss_all, rows_all);
+  }
 }
 
 template <class S>
