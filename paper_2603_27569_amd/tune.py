@@ -34,6 +34,8 @@ Usage: python -m paper_2603_27569_amd.tune [--out tune_gfx950.json] [--quick]
        python -m paper_2603_27569_amd.tune --run-variants N BATCH [--iters K]
          (no search: runs every variant of length N, K launches each, so that
          an external profiler can attribute counters to each variant)
+       python -m paper_2603_27569_amd.tune --run-fused-variants N BATCH [--iters K]
+         (the same for the fused forward -> weight -> adjoint kernel)
        python -m paper_2603_27569_amd.tune --merge-counters N BATCH CSV... [--iters K] --out FILE
          (attaches the counters of such a run under rocprofv3 --pmc, one CSV
          per counter pass, to FILE's entries for N at BATCH, per candidate)
@@ -385,6 +387,28 @@ def run_variants(n, batch, iters=10, log=print):
         log(f"ran {v['name']} x{iters}")
 
 
+def run_fused_variants(n, batch, iters=10, log=print):
+    """The same for the fused forward -> weight -> adjoint kernel (with its
+    loss total): every variant of length n that has it, `iters` calls each."""
+    import torch
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream()
+    x = torch.randn(batch, n, dtype=torch.complex64, device=dev)
+    w = torch.rand(n, device=dev)
+    g = torch.empty_like(x)
+    rows = torch.empty(batch, device=dev)
+    total = torch.empty(1, device=dev)
+    torch.cuda.synchronize()
+    for name in fused_candidates(n):
+        p = Plan(n, batch, FFT_FORWARD, FFT_ALGO_SINGLE_PASS, name)
+        for _ in range(iters):
+            fft_exec_spectral_energy(p.handle, x.data_ptr(), w.data_ptr(), 0, g.data_ptr(),
+                                     rows.data_ptr(), total.data_ptr(), stream.cuda_stream)
+        torch.cuda.synchronize()
+        p.close()
+        log(f"ran fused {name} x{iters}")
+
+
 def variant_dispatch_counters(csv_paths, n, iters):
     """Per-variant counter medians from rocprofv3 counter-collection CSV files
     (`--pmc ... --output-format csv`) of a `--run-variants n BATCH --iters
@@ -447,6 +471,7 @@ def main(argv=None):
     ap.add_argument("--out", default="tune_gfx950.json")
     ap.add_argument("--quick", action="store_true")
     ap.add_argument("--run-variants", nargs=2, type=int, metavar=("N", "BATCH"))
+    ap.add_argument("--run-fused-variants", nargs=2, type=int, metavar=("N", "BATCH"))
     ap.add_argument("--iters", type=int, default=10)
     ap.add_argument("--merge-counters", nargs="+", metavar="N BATCH CSV",
                     help="attach per-variant counter medians of a profiled --run-variants N BATCH "
@@ -463,6 +488,9 @@ def main(argv=None):
         return 0
     if a.run_variants:
         run_variants(a.run_variants[0], a.run_variants[1], a.iters, log=log)
+        return 0
+    if a.run_fused_variants:
+        run_fused_variants(a.run_fused_variants[0], a.run_fused_variants[1], a.iters, log=log)
         return 0
     run(a.out, a.quick, log=log)
     return 0
